@@ -1,0 +1,203 @@
+/*
+ * bem.h - C ABI of the MI355X (gfx950) differential-BEM hot path for fitting
+ * diffusion curves to noisy Monte Carlo samples.
+ *
+ * The method: colours u(x) in the unit-square image domain solve Laplace's
+ * equation away from handle curves, with prescribed jumps of the colour (wd)
+ * and of its normal derivative (wc) across each handle and zero Neumann data
+ * on the outer boundary (paper Sec. 2.1, Eq. laplace / Eq. neumann; Sec. 3.1.1,
+ * Eq. bie / Eq. handleterm).  The outer boundary is discretised into constant
+ * elements and solved once by a Galerkin system (Eq. bie_galerkin) whose
+ * one-dimensional null space is removed by dropping the smallest singular
+ * value (Sec. 3.1.3); derivatives with respect to handle parameters solve the
+ * same system with differentiated right-hand sides (Eq. diffbie, Sec. 3.2);
+ * a Levenberg-Marquardt step uses Monte Carlo estimates of J^T J and J^T r
+ * (Eq. optimstep, Eq. losshessian, Eq. lossjacobian, Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ *  - Handles: H cubic Bezier curves, each cut at t = k/S into S straight
+ *    segments (K = H*S).  theta is [H,20] float64 row-major, per handle
+ *      [P0x P0y P1x P1y P2x P2y P3x P3y | wd0 RGB | wd1 RGB | wc0 RGB | wc1 RGB]
+ *    where wd/wc at end 0 (t=0) and end 1 (t=1) are interpolated linearly in t.
+ *    P = 20*H parameters; every Jacobian/gradient uses this column order.
+ *  - Orientation: a segment a->b has right normal n = (tau_y, -tau_x); wd is
+ *    the colour on the left minus the colour on the right, wc the jump of the
+ *    derivative along n.  The outer boundary is counter-clockwise, so n is
+ *    outward there.
+ *  - The handle kernels are regularised r^2 -> r^2 + eps^2 (Sec. 3.1.3); the
+ *    outer-boundary kernels are exact.
+ *  - Samples x are [N,2] float64 strictly inside the open unit square.
+ *  - All array pointers are DEVICE pointers owned by the caller unless marked
+ *    (host).  The library owns only the context and its internal workspaces,
+ *    which it grows with hipMalloc on first use of a size and frees in
+ *    bem_destroy.
+ *  - Calls enqueue on `stream` and return without a host synchronisation,
+ *    except where stated (lm_step; growth of a workspace).
+ *  - Every call returns a bem_status; nothing throws across the ABI.  On an
+ *    error, outputs are unspecified and bem_last_error() describes it.
+ *  - A context is not thread-safe; use one context per stream.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_ctx bem_ctx;
+
+typedef enum {
+    BEM_OK = 0,
+    BEM_EINVAL = -1,     /* bad argument (null pointer, size out of range, bad enum)       */
+    BEM_ENOMEM = -2,     /* device allocation failed                                      */
+    BEM_ESTATE = -3,     /* call order: the boundary system is not built/factored yet     */
+    BEM_ENOTPD = -4,     /* Cholesky of the damped normal matrix met a non-positive pivot */
+    BEM_EHIP = -5,       /* a HIP runtime call or kernel launch failed                    */
+    BEM_ENUMERIC = -6    /* non-finite value where a finite one is required               */
+} bem_status;
+
+/* Arithmetic of the sample x segment sweeps.
+ * FP64 : every pair in float64; u and cotangents are float64.
+ * MIXED: pairs in float32 except near-singular pairs (both segment end points
+ *        within 2*near_factor*L of the sample, which contains every sample
+ *        closer than near_factor*L to the segment), which are evaluated in
+ *        float64 from the float64 inputs; u and cotangents are float32; every
+ *        reduction over samples is finished in float64.  The boundary system,
+ *        its solves and the LM solve are float64 in both modes. */
+typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
+
+/* Arithmetic of the Gram contraction that forms J^T J and J^T r.
+ * FP64         : float64 tiles, float64 accumulation (VALU).
+ * FP32_MFMA    : float32 J tiles, float32 MFMA, float32 accumulation within
+ *                a sample tile, float64 across tiles.
+ * BF16X3_MFMA  : J split as hi + lo bfloat16, hi*hi + hi*lo + lo*hi on bf16
+ *                MFMA with float32 accumulation within a tile, float64 across. */
+typedef enum { BEM_GRAM_FP64 = 0, BEM_GRAM_FP32_MFMA = 1, BEM_GRAM_BF16X3_MFMA = 2 } bem_gram;
+
+typedef struct {
+    int32_t elems_per_side;   /* outer elements per side of the unit square (256: length 1/256, Sec. 3.1.3) */
+    int32_t segs_per_handle;  /* S >= 1 */
+    double eps;               /* handle-kernel regularisation (1e-2 in the paper's experiments); >= 0 */
+    double near_factor;       /* MIXED near-pair threshold in segment lengths (1.0); > 0 */
+    int32_t tile_rows;        /* sample rows per J tile in bem_jtj (0: automatic) */
+    int32_t device;           /* HIP device ordinal the context lives on */
+} bem_opts;
+
+/* Host-side state of the LM iteration (Sec. 4.3).  lambda is the damping
+ * factor; the mean colour cbar is either the running mean of every target
+ * seen (mean_rule 0: the paper's rule, outside LM) or the least-squares
+ * constant mean(T - u_bem) of the current step (mean_rule 1). */
+typedef struct {
+    double lambda;            /* in/out: damping (clamped to [1e-12, 1e12])         */
+    double cbar[3];           /* out: mean colour used in this step                 */
+    double cbar_sum[3];       /* in/out: running sum of targets (mean_rule 0)       */
+    int64_t cbar_count;       /* in/out: number of target rows summed               */
+    int32_t mean_rule;        /* in: 0 running mean of targets, 1 least squares     */
+    int32_t accepted;         /* out: 1 if the step lowered the loss                */
+    double loss_before;       /* out: (1/2N) sum |u - T|^2 at theta                 */
+    double loss_after;        /* out: same at the trial parameters                  */
+    int32_t chol_retries;     /* out: extra damping rounds after a failed Cholesky  */
+} bem_lm_state;
+
+/* Build the outer boundary (unit square, counter-clockwise, elems_per_side
+ * equal elements per side, M = 4*elems_per_side) and assemble the float64
+ * Galerkin matrix A of Eq. bie_galerkin: A_ii = |G_i|/2, A_ij = 3x3-point
+ * Gauss integral of dG/dn_y over G_i x G_j, the coincident term zero
+ * (Sec. 3.1.3).  *out receives a new context (host).  opts is host memory,
+ * copied.  Errors: EINVAL (null pointer, elems_per_side < 2 or > 4096,
+ * S < 1 or > 1024, eps < 0 or not finite, near_factor <= 0), ENOMEM, EHIP. */
+int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out);
+
+/* One-time float64 factorisation (Sec. 3.1.3, factor once and reuse, Sec. 4.2):
+ * the smallest singular triplet (sigma_n, u_n, v_n) of A by inverse iteration
+ * with a pivoted LU of A, the deflated matrix B = A + (s - sigma_n) u_n v_n^T
+ * (s = |A|_F / sqrt(M)), and the explicit truncated pseudo-inverse
+ * A+ = B^{-1} - v_n u_n^T / s, which equals the SVD solve that drops the
+ * smallest singular value.  Synchronises the stream.
+ * Errors: ESTATE (not built), ENUMERIC (zero pivot), ENOMEM, EHIP. */
+int bem_factor(bem_ctx* ctx, hipStream_t stream);
+
+/* Forward evaluation u(x) = cbar + sum_j beta_j(x) U_j + f(x) (Eq. bie with
+ * alpha = 1 plus the mean colour, Sec. 3.1.3), where f is the handle term of
+ * Eq. handleterm, U = A+ F the solved outer-boundary values with
+ * F_i = int_{G_i} f by 3-point Gauss, and beta_j(x) = -int_{G_j} dG/dn_y.
+ * theta [H,20] f64, x [N,2] f64, cbar[3] (host), u [N,3] row-major, float64
+ * for FP64 and float32 for MIXED.  H = 0 or N = 0 are allowed.
+ * Errors: ESTATE (not factored), EINVAL, ENOMEM, EHIP. */
+int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+             const double* cbar, void* u, bem_prec prec, hipStream_t stream);
+
+/* Vector-Jacobian product: grad[p] = sum_x sum_c gbar_c(x) du_c(x)/dtheta_p,
+ * the reverse-mode form of the differential BIE (Eq. diffbie): segment
+ * adjoints over all samples, psi = sum_x gbar(x) beta(x), mu = A+^T psi, and
+ * the segment adjoints at the boundary Gauss points with cotangent mu.
+ * gbar [N,3] row-major (float64 for FP64, float32 for MIXED), grad [H,20]
+ * float64, overwritten.  The mean colour does not depend on theta.
+ * Errors: as bem_eval. */
+int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+            const void* gbar, double* grad, bem_prec prec, hipStream_t stream);
+
+/* Monte Carlo normal equations with uniform samples (p = 1 on the unit
+ * square; Eq. losshessian, Eq. lossjacobian):
+ *   JtJ = (1/N) sum_x sum_c J_c(x)^T J_c(x)   [P,P] float64 (full, symmetric)
+ *   Jtr = (1/N) sum_x sum_c J_c(x)^T r_c(x)   [P]   float64
+ * with J_c(x) = du_c(x)/dtheta.  resid [N,3] (float64 for FP64, float32 for
+ * MIXED).  The Gram contraction runs in `gram` arithmetic.
+ * Errors: as bem_eval. */
+int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+            const void* resid, double* JtJ, double* Jtr, bem_gram gram, bem_prec prec,
+            hipStream_t stream);
+
+/* One Levenberg-Marquardt step (Eq. optimstep, Sec. 4.3) on the samples x
+ * with targets T [N,3] float64:
+ *   cbar update (state->mean_rule), u = u(theta), r = u - T, loss L0 = (1/2N) sum r^2,
+ *   g = (1/N) sum J^T r by the adjoint (bem_vjp), H = (1/N) sum J^T J (bem_jtj),
+ *   delta = (lambda diag(H) + H)^{-1} g by float64 Cholesky,
+ *   theta' = theta - delta, L1 = loss at theta' on the same samples with cbar fixed;
+ *   accept iff L1 < L0: theta <- theta', lambda /= 10; else lambda *= 10.
+ * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
+ * most 10 times) before ENOTPD.  theta [H,20] (device) is updated in place;
+ * state (host) is read and written.  Synchronises the stream.
+ * Errors: as bem_eval, ENOTPD, ENUMERIC (non-finite loss or step). */
+int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N,
+            const double* target, bem_lm_state* state, bem_gram gram, bem_prec prec,
+            hipStream_t stream);
+
+/* Explicit float64 Jacobian J [N,3,P] (row = sample*3 + channel), the
+ * quantity the paper differentiates in Sec. 3.2.  For tests and small N.
+ * Errors: as bem_eval. */
+int bem_jacobian(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+                 double* J, hipStream_t stream);
+
+/* Intermediate quantities of the forward path, float64, for inspection:
+ * F [M,3] = int_{G_i} f (right-hand side of Eq. bie_galerkin) and
+ * U [M,3] = A+ F.  Either pointer may be NULL.  Errors: as bem_eval. */
+int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U,
+                       hipStream_t stream);
+
+/* Copy the assembled matrix A [M,M] (after bem_build) or the truncated
+ * pseudo-inverse A+ [M,M] (after bem_factor), row-major float64, into a
+ * caller buffer; which = 0 for A, 1 for A+.  Errors: ESTATE, EINVAL, EHIP. */
+int bem_get_matrix(bem_ctx* ctx, int32_t which, double* out, hipStream_t stream);
+
+/* Number of outer elements M (host); 0 for a null context. */
+int32_t bem_num_elements(const bem_ctx* ctx);
+
+/* Smallest singular value sigma_n and the deflation shift s found by bem_factor (host). */
+int bem_factor_info(const bem_ctx* ctx, double* sigma_n, double* shift);
+
+/* Release the context and every workspace it owns.  Null is ignored. */
+void bem_destroy(bem_ctx* ctx);
+
+/* Description of the last non-OK status of this context (NULL: of the last
+ * failed bem_build on this thread).  Valid until the next call on the context. */
+const char* bem_last_error(const bem_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEM_H */

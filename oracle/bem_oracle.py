@@ -16,7 +16,10 @@ the HIP library and takes every step in the paper's order, in float64:
                                             Eq. lossjacobian, Sec. 4.3)
 
 Segment integrals are the antiderivatives of the two kernels evaluated at the
-segment ends (exactly the integral the paper approximates by quadrature).
+segment ends (exactly the integral the paper approximates by quadrature); the
+differences of logarithms and arctangents at the two ends are formed with the
+identities log a - log b = log1p((a-b)/b) and atan(p) - atan(q) =
+atan2(p-q, 1+pq), which keep relative accuracy for short segments.
 Derivatives with respect to segment end points use forward-mode dual numbers
 through those same expressions.
 
@@ -117,31 +120,43 @@ def _segment_moments(x, ax, ay, bx, by, eps: float):
     u1 = L - t0
     q2 = h * h + eps * eps
     q = du.sqrt(q2)
-    r0 = u0 * u0 + q2
+    r0 = u0 * u0 + q2                                  # |z - x|^2 + eps^2 at the two ends
     r1 = u1 * u1 + q2
     qv = du.value(q)
     r0v = du.value(r0)
     r1v = du.value(r1)
-    lam0 = du.log(du.where(r0v > 0, r0, 1.0))          # r^2 log r^2 -> 0 and u log r^2 -> 0 at r = 0
-    lam1 = du.log(du.where(r1v > 0, r1, 1.0))
+    # lam0 = log r0;  ell = log r1 - log r0 = log1p((r1 - r0)/r0), r1 - r0 = L (u0 + u1).
+    # Limits at an end point (eps = 0, x = a or x = b): u log u^2 -> 0, r log r -> 0.
+    lam0 = du.log(du.where(r0v > 0, r0, 1.0))
+    ell = du.where(r0v > 0,
+                   du.where(r1v > 0, du.log1p(L * (u0 + u1) / du.where(r0v > 0, r0, 1.0)), -lam0),
+                   du.log(du.where(r1v > 0, r1, 1.0)))
+    # Delta = atan(u1/q) - atan(u0/q) = atan2(q L, q^2 + u0 u1)  (q > 0)
     qs = du.where(qv > 0, q, 1.0)
-    at0 = du.arctan2(u0, qs)                           # atan(u/q)
-    at1 = du.arctan2(u1, qs)
+    Delta = du.arctan2(q * L, q2 + u0 * u1)
 
     # double layer: int h/(u^2+q^2) du = (h/q) atan(u/q);  int u h/(u^2+q^2) du = (h/2) log(u^2+q^2)
-    K0d = du.where(qv > 0, h / qs * (at1 - at0), 0.0) / TWO_PI   # principal value 0 on the line when eps = 0
-    K1d = h * (lam1 - lam0) / FOUR_PI
+    K0d = du.where(qv > 0, h / qs * Delta, 0.0) / TWO_PI       # principal value 0 on the line when eps = 0
+    K1d = h * ell / FOUR_PI
     # single layer: int log(u^2+q^2) du = u log(u^2+q^2) - 2u + 2q atan(u/q)
-    #               int u log(u^2+q^2) du = ((u^2+q^2) log(u^2+q^2) - (u^2+q^2)) / 2
-    F0 = lambda u, lam, at: u * lam - 2.0 * u + 2.0 * q * at           # noqa: E731
-    F1 = lambda r, lam: 0.5 * (r * lam - r)                             # noqa: E731
-    K0s = -(F0(u1, lam1, at1) - F0(u0, lam0, at0)) / FOUR_PI
-    K1s = -(F1(r1, lam1) - F1(r0, lam0)) / FOUR_PI
+    #   between u0 and u1:  u1 ell + L lam0 - 2L + 2 q Delta
+    # int u log(u^2+q^2) du = ((u^2+q^2) log(u^2+q^2) - (u^2+q^2)) / 2
+    #   between u0 and u1:  (r1 ell + (r1 - r0)(lam0 - 1)) / 2
+    u1ell = du.where(r1v > 0, u1 * ell, 0.0)
+    r1ell = du.where(r1v > 0, r1 * ell, 0.0)
+    K0s = -(u1ell + L * lam0 - 2.0 * L + 2.0 * q * Delta) / FOUR_PI
+    K1s = -0.5 * (r1ell + L * (u0 + u1) * (lam0 - 1.0)) / FOUR_PI
 
     # s = u + t0:  int k s/L ds = (K1 + t0 K0)/L
     Md_b = (K1d + t0 * K0d) / L
     Ms_b = (K1s + t0 * K0s) / L
     return K0d - Md_b, Md_b, K0s - Ms_b, Ms_b
+
+
+# A segment shorter than this (in units of the domain width) is degenerate:
+# its integral is below ~1e-11 for the regularised kernels and its end-point
+# derivative has no limit as the length goes to 0, so it contributes nothing.
+DEGENERATE_LENGTH = 1e-12
 
 
 def _chunks(n: int, k: int):
@@ -154,7 +169,7 @@ def handle_term(x: np.ndarray, theta: np.ndarray, S: int, eps: float) -> np.ndar
     """f(x) of Eq. handleterm summed over all handle segments, [n, 3]."""
     seg = segment_table(theta, S)
     a, b = seg["a"], seg["b"]
-    keep = np.hypot(*(b - a).T) > 0                     # zero-length segments carry no integral
+    keep = np.hypot(*(b - a).T) > DEGENERATE_LENGTH     # degenerate segments carry no integral
     a, b = a[keep], b[keep]
     w = [seg[k][keep] for k in ("wd_a", "wd_b", "wc_a", "wc_b")]
     out = np.zeros((len(x), 3))
@@ -290,7 +305,7 @@ def handle_term_jacobian(x: np.ndarray, theta: np.ndarray, S: int, eps: float) -
     a, b = seg["a"], seg["b"]
     K = H * S
     ln = np.hypot(*(b - a).T)
-    live = ln > 0
+    live = ln > DEGENERATE_LENGTH
     B = bernstein3(vertex_params(S))                     # [S+1, 4]
     tk = vertex_params(S)
     w = [seg[k] for k in ("wd_a", "wd_b", "wc_a", "wc_b")]

@@ -100,6 +100,11 @@ def log(x):
     return Dual._combine(np.log(xv), [(xd, 1.0 / xv)])
 
 
+def log1p(x):
+    xv, xd = Dual._parts(x)
+    return Dual._combine(np.log1p(xv), [(xd, 1.0 / (1.0 + xv))])
+
+
 def arctan2(y, x):
     yv, yd = Dual._parts(y)
     xv, xd = Dual._parts(x)

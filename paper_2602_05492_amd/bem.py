@@ -1,0 +1,252 @@
+"""Thin Python binding of libbem.so (include/bem.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module checks tensor
+placement, dtypes and shapes, passes raw device pointers and the current HIP
+stream, and raises BemError on a non-zero status.  PyTorch provides device
+memory and streams.  If the library is not built, every call fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbem.so")
+HEADER = os.path.join(HERE, "..", "include", "bem.h")
+
+PREC = {"fp64": 0, "mixed": 1}
+GRAM = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2}
+STATUS = {0: "BEM_OK", -1: "BEM_EINVAL", -2: "BEM_ENOMEM", -3: "BEM_ESTATE", -4: "BEM_ENOTPD",
+          -5: "BEM_EHIP", -6: "BEM_ENUMERIC"}
+
+
+class BemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("elems_per_side", ctypes.c_int32), ("segs_per_handle", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("near_factor", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class LMState(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("cbar", ctypes.c_double * 3), ("cbar_sum", ctypes.c_double * 3),
+                ("cbar_count", ctypes.c_int64), ("mean_rule", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("loss_before", ctypes.c_double), ("loss_after", ctypes.c_double), ("chol_retries", ctypes.c_int32)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+
+_SIGS = {
+    "bem_build": (ctypes.c_int, [ctypes.POINTER(Opts), P, ctypes.POINTER(P)]),
+    "bem_factor": (ctypes.c_int, [P, P]),
+    "bem_eval": (ctypes.c_int, [P, P, I32, P, I64, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int, P]),
+    "bem_vjp": (ctypes.c_int, [P, P, I32, P, I64, P, P, ctypes.c_int, P]),
+    "bem_jtj": (ctypes.c_int, [P, P, I32, P, I64, P, P, P, ctypes.c_int, ctypes.c_int, P]),
+    "lm_step": (ctypes.c_int, [P, P, I32, P, I64, P, ctypes.POINTER(LMState), ctypes.c_int, ctypes.c_int, P]),
+    "bem_jacobian": (ctypes.c_int, [P, P, I32, P, I64, P, P]),
+    "bem_boundary_solve": (ctypes.c_int, [P, P, I32, P, P, P]),
+    "bem_get_matrix": (ctypes.c_int, [P, I32, P, P]),
+    "bem_num_elements": (I32, [P]),
+    "bem_factor_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "bem_destroy": (None, [P]),
+    "bem_last_error": (ctypes.c_char_p, [P]),
+}
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/bem.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|int32_t|const char\*)\s+\**\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2602_05492_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check_dev(name, t, dtype, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass
+class Options:
+    segs_per_handle: int = 32
+    eps: float = 1e-2
+    elems_per_side: int = 256
+    near_factor: float = 1.0
+    tile_rows: int = 0
+    device: int = 0
+
+
+class Context:
+    """A built and factored outer-boundary system plus the library's workspaces."""
+
+    def __init__(self, opts: Options | None = None, **kw):
+        self.opts = opts or Options(**kw)
+        L = lib()
+        o = Opts(self.opts.elems_per_side, self.opts.segs_per_handle, self.opts.eps, self.opts.near_factor,
+                 self.opts.tile_rows, self.opts.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.opts.device):
+            st = _stream()
+            rc = L.bem_build(ctypes.byref(o), st, ctypes.byref(h))
+            if rc != 0:
+                raise BemError(rc, L.bem_last_error(None).decode())
+            self._h = h
+            self._check(L.bem_factor(self._h, st))
+        self.M = L.bem_num_elements(self._h)
+        self.device = torch.device("cuda", self.opts.device)
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise BemError(rc, lib().bem_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _theta_x(self, theta, x):
+        _check_dev("theta", theta, torch.float64)
+        if theta.dim() != 2 or theta.shape[1] != 20:
+            raise ValueError("theta must be [H, 20]")
+        if x is not None:
+            _check_dev("x", x, torch.float64)
+            if x.dim() != 2 or x.shape[1] != 2:
+                raise ValueError("x must be [N, 2]")
+        return theta.shape[0], (x.shape[0] if x is not None else 0)
+
+    # -- entry points ----------------------------------------------------------
+    def factor_info(self):
+        s = ctypes.c_double()
+        sh = ctypes.c_double()
+        self._check(lib().bem_factor_info(self._h, ctypes.byref(s), ctypes.byref(sh)))
+        return s.value, sh.value
+
+    def matrix(self, which: int = 0) -> torch.Tensor:
+        out = torch.empty((self.M, self.M), dtype=torch.float64, device=self.device)
+        self._check(lib().bem_get_matrix(self._h, which, _ptr(out), _stream()))
+        return out
+
+    def boundary_solve(self, theta):
+        H, _ = self._theta_x(theta, None)
+        F = torch.empty((self.M, 3), dtype=torch.float64, device=self.device)
+        U = torch.empty_like(F)
+        self._check(lib().bem_boundary_solve(self._h, _ptr(theta), H, _ptr(F), _ptr(U), _stream()))
+        return F, U
+
+    def eval(self, theta, x, cbar=(0.0, 0.0, 0.0), prec: str = "fp64", out=None) -> torch.Tensor:
+        H, N = self._theta_x(theta, x)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        if out is None:
+            out = torch.empty((N, 3), dtype=dt, device=self.device)
+        else:
+            _check_dev("out", out, dt, (N, 3))
+        cb = (ctypes.c_double * 3)(*[float(c) for c in cbar])
+        self._check(lib().bem_eval(self._h, _ptr(theta), H, _ptr(x), N, cb, _ptr(out), PREC[prec], _stream()))
+        return out
+
+    def vjp(self, theta, x, gbar, prec: str = "fp64", out=None) -> torch.Tensor:
+        H, N = self._theta_x(theta, x)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        _check_dev("gbar", gbar, dt, (N, 3))
+        if out is None:
+            out = torch.empty((H, 20), dtype=torch.float64, device=self.device)
+        self._check(lib().bem_vjp(self._h, _ptr(theta), H, _ptr(x), N, _ptr(gbar), _ptr(out), PREC[prec], _stream()))
+        return out
+
+    def jtj(self, theta, x, resid, gram: str = "fp64", prec: str = "fp64"):
+        H, N = self._theta_x(theta, x)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        _check_dev("resid", resid, dt, (N, 3))
+        P_ = 20 * H
+        JtJ = torch.empty((P_, P_), dtype=torch.float64, device=self.device)
+        Jtr = torch.empty((P_,), dtype=torch.float64, device=self.device)
+        self._check(lib().bem_jtj(self._h, _ptr(theta), H, _ptr(x), N, _ptr(resid), _ptr(JtJ), _ptr(Jtr),
+                                  GRAM[gram], PREC[prec], _stream()))
+        return JtJ, Jtr
+
+    def jacobian(self, theta, x) -> torch.Tensor:
+        H, N = self._theta_x(theta, x)
+        J = torch.empty((N, 3, 20 * H), dtype=torch.float64, device=self.device)
+        self._check(lib().bem_jacobian(self._h, _ptr(theta), H, _ptr(x), N, _ptr(J), _stream()))
+        return J
+
+    def lm_step(self, theta, x, target, state: LMState, gram: str = "fp64", prec: str = "fp64") -> LMState:
+        H, N = self._theta_x(theta, x)
+        _check_dev("target", target, torch.float64, (N, 3))
+        self._check(lib().lm_step(self._h, _ptr(theta), H, _ptr(x), N, _ptr(target), ctypes.byref(state),
+                                  GRAM[gram], PREC[prec], _stream()))
+        return state
+
+
+def new_lm_state(lam: float = 1e-3, mean_rule: int = 0) -> LMState:
+    s = LMState()
+    s.lam = lam
+    s.mean_rule = mean_rule
+    return s
+
+
+class BemEval(torch.autograd.Function):
+    """u = bem_eval(theta, x); backward = bem_vjp (gradient with respect to theta only)."""
+
+    @staticmethod
+    def forward(fctx, theta, x, ctx: Context, cbar, prec: str):
+        fctx.save_for_backward(theta, x)
+        fctx.bem = ctx
+        fctx.prec = prec
+        return ctx.eval(theta.detach(), x, cbar, prec)
+
+    @staticmethod
+    def backward(fctx, gu):
+        theta, x = fctx.saved_tensors
+        dt = torch.float64 if fctx.prec == "fp64" else torch.float32
+        g = fctx.bem.vjp(theta.detach(), x, gu.to(dt).contiguous(), fctx.prec)
+        return g, None, None, None, None
+
+
+def bem_eval(theta, x, ctx: Context, cbar=(0.0, 0.0, 0.0), prec: str = "fp64"):
+    return BemEval.apply(theta, x, ctx, tuple(cbar), prec)

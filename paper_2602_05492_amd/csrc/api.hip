@@ -1,0 +1,212 @@
+// api.hip - the C ABI of include/bem.h: argument checks, call order,
+// workspaces and the orchestration of the kernels of each entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace bem {
+
+static thread_local std::string g_build_error;
+
+int set_error(bem_ctx* ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_build_error = buf;
+    return code;
+}
+
+int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream)
+{
+    if (bytes <= b.bytes && b.ptr) return BEM_OK;
+    if (b.ptr) {
+        // kernels already queued may still read the old buffer
+        if (hipStreamSynchronize(stream) != hipSuccess) return set_error(ctx, BEM_EHIP, "stream sync before regrow");
+        hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes < 256 ? 256 : bytes;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        b.ptr = nullptr;
+        hipGetLastError();
+        return set_error(ctx, BEM_ENOMEM, "hipMalloc of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    return BEM_OK;
+}
+
+int check_launch(bem_ctx* ctx, const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(ctx, BEM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return BEM_OK;
+}
+
+static void release(DevBuf& b)
+{
+    if (b.ptr) hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+int check_common(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N)
+{
+    if (!ctx) return BEM_EINVAL;
+    ctx->err.clear();
+    if (ctx->state < 2) return set_error(ctx, BEM_ESTATE, "the boundary system is not factored (call bem_factor)");
+    if (H < 0 || H > (1 << 20)) return set_error(ctx, BEM_EINVAL, "H = %d out of range", (int)H);
+    if ((int64_t)H * ctx->opts.segs_per_handle > (1 << 24)) return set_error(ctx, BEM_EINVAL, "too many segments");
+    if (N < 0 || N > ((int64_t)1 << 31)) return set_error(ctx, BEM_EINVAL, "N = %lld out of range", (long long)N);
+    if (H > 0 && !theta) return set_error(ctx, BEM_EINVAL, "theta is null");
+    if (N > 0 && !x) return set_error(ctx, BEM_EINVAL, "x is null");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, BEM_EHIP, "hipSetDevice(%d)", ctx->device);
+    return BEM_OK;
+}
+
+// expand -> F -> U -> element table.  Leaves F in ctx->F and U in ctx->U.
+int prepare_forward(bem_ctx* ctx, const double* theta, int32_t H, hipStream_t s)
+{
+    int rc;
+    const int K = H * ctx->opts.segs_per_handle;
+    if ((rc = ensure(ctx, ctx->F, (size_t)ctx->M * 3 * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->U, (size_t)ctx->M * 3 * sizeof(double), s))) return rc;
+    if ((rc = launch_expand(ctx, theta, H, s))) return rc;
+    if ((rc = launch_boundary_rhs(ctx, K, (double*)ctx->F.ptr, s))) return rc;
+    if ((rc = launch_boundary_solve(ctx, (const double*)ctx->F.ptr, (double*)ctx->U.ptr, false, s))) return rc;
+    return launch_pack_elements(ctx, (const double*)ctx->U.ptr, s);
+}
+
+}  // namespace bem
+
+using namespace bem;
+
+extern "C" {
+
+int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
+{
+    g_build_error.clear();
+    if (!opts || !out) return set_error(nullptr, BEM_EINVAL, "null opts or out");
+    *out = nullptr;
+    const bem_opts& o = *opts;
+    if (o.elems_per_side < 2 || o.elems_per_side > 1024)
+        return set_error(nullptr, BEM_EINVAL, "elems_per_side = %d not in [2, 1024]", o.elems_per_side);
+    if (o.segs_per_handle < 1 || o.segs_per_handle > 1024)
+        return set_error(nullptr, BEM_EINVAL, "segs_per_handle = %d not in [1, 1024]", o.segs_per_handle);
+    if (!(o.eps >= 0.0) || !std::isfinite(o.eps)) return set_error(nullptr, BEM_EINVAL, "eps must be finite and >= 0");
+    if (!(o.near_factor > 0.0) || !std::isfinite(o.near_factor))
+        return set_error(nullptr, BEM_EINVAL, "near_factor must be finite and > 0");
+    if (o.tile_rows < 0) return set_error(nullptr, BEM_EINVAL, "tile_rows must be >= 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        hipGetLastError();
+        return set_error(nullptr, BEM_EHIP, "no HIP device");
+    }
+    if (o.device < 0 || o.device >= ndev) return set_error(nullptr, BEM_EINVAL, "device %d not present", o.device);
+    if (hipSetDevice(o.device) != hipSuccess) return set_error(nullptr, BEM_EHIP, "hipSetDevice");
+    bem_ctx* ctx = new (std::nothrow) bem_ctx();
+    if (!ctx) return set_error(nullptr, BEM_ENOMEM, "context allocation");
+    ctx->opts = o;
+    ctx->device = o.device;
+    ctx->per_side = o.elems_per_side;
+    ctx->M = 4 * o.elems_per_side;
+    int rc = ensure(ctx, ctx->A, (size_t)ctx->M * ctx->M * sizeof(double), stream);
+    if (!rc) rc = launch_assemble(ctx, stream);
+    if (rc) {
+        g_build_error = ctx->err;
+        bem_destroy(ctx);
+        return rc;
+    }
+    ctx->state = 1;
+    *out = ctx;
+    return BEM_OK;
+}
+
+int bem_factor(bem_ctx* ctx, hipStream_t stream)
+{
+    if (!ctx) return BEM_EINVAL;
+    ctx->err.clear();
+    if (ctx->state < 1) return set_error(ctx, BEM_ESTATE, "not built");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, BEM_EHIP, "hipSetDevice");
+    const int rc = launch_factor(ctx, stream);
+    if (rc) return rc;
+    ctx->state = 2;
+    return BEM_OK;
+}
+
+int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N, const double* cbar, void* u,
+             bem_prec prec, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (!cbar) return set_error(ctx, BEM_EINVAL, "cbar is null");
+    if (N > 0 && !u) return set_error(ctx, BEM_EINVAL, "u is null");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
+    if ((rc = prepare_forward(ctx, theta, H, stream))) return rc;
+    const int K = H * ctx->opts.segs_per_handle;
+    if (prec == BEM_PREC_FP64) return launch_sweep_f64(ctx, x, N, K, cbar, (double*)u, stream);
+    return launch_sweep_mixed(ctx, x, N, K, cbar, (float*)u, stream);
+}
+
+int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, nullptr, 0);
+    if (rc) return rc;
+    if ((rc = prepare_forward(ctx, theta, H, stream))) return rc;
+    const size_t bytes = (size_t)ctx->M * 3 * sizeof(double);
+    if (F && hipMemcpyAsync(F, ctx->F.ptr, bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "copy F");
+    if (U && hipMemcpyAsync(U, ctx->U.ptr, bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "copy U");
+    return BEM_OK;
+}
+
+int bem_get_matrix(bem_ctx* ctx, int32_t which, double* out, hipStream_t stream)
+{
+    if (!ctx) return BEM_EINVAL;
+    ctx->err.clear();
+    if (!out) return set_error(ctx, BEM_EINVAL, "out is null");
+    if (which != 0 && which != 1) return set_error(ctx, BEM_EINVAL, "which must be 0 or 1");
+    if (ctx->state < 1 + which) return set_error(ctx, BEM_ESTATE, "matrix not available yet");
+    const DevBuf& b = which ? ctx->Apinv : ctx->A;
+    if (hipMemcpyAsync(out, b.ptr, (size_t)ctx->M * ctx->M * sizeof(double), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "copy matrix");
+    return BEM_OK;
+}
+
+int32_t bem_num_elements(const bem_ctx* ctx) { return ctx ? ctx->M : 0; }
+
+int bem_factor_info(const bem_ctx* ctx, double* sigma_n, double* shift)
+{
+    if (!ctx || ctx->state < 2) return BEM_ESTATE;
+    if (sigma_n) *sigma_n = ctx->sigma_n;
+    if (shift) *shift = ctx->shift;
+    return BEM_OK;
+}
+
+void bem_destroy(bem_ctx* ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
+                      &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
+                      &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5};
+    for (DevBuf* b : bufs) release(*b);
+    delete ctx;
+}
+
+const char* bem_last_error(const bem_ctx* ctx)
+{
+    if (!ctx) return g_build_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// common.hpp - context, workspaces and launch helpers shared by the library's
+// translation units.  Not part of the public ABI (see include/bem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/bem.h"
+#include "seg_math.hpp"
+
+namespace bem {
+
+// ---- device math policies ---------------------------------------------------
+struct DevF64 {
+    __device__ static double log(double x) { return ::log(x); }
+    __device__ static double log1p(double x) { return ::log1p(x); }
+    __device__ static double sqrt(double x) { return ::sqrt(x); }
+    __device__ static double atan2(double y, double x) { return ::atan2(y, x); }
+};
+
+// Segments no longer than this (domain-width units) are degenerate: their
+// integral is below ~1e-11 for the regularised kernels and the derivative
+// with respect to their end points has no limit as the length goes to 0, so
+// they contribute nothing (an expansion of a zero-length handle carries
+// rounding-level lengths of ~1e-16).
+constexpr double kDegenerateLength = 1e-12;
+
+// ---- layouts ----------------------------------------------------------------
+// Segment record: SegGeom (9 values) + wd_a, wd_b, wc_a, wc_b RGB (12) = 21, padded.
+constexpr int kSegStride = 24;
+// Element record: ax, ay, vx, vy, U0, U1, U2, pad.
+constexpr int kElemStride = 8;
+
+template <class T>
+__device__ inline SegGeom<T> load_geom(const T* __restrict__ s)
+{
+    SegGeom<T> g;
+    g.ax = s[0]; g.ay = s[1]; g.bx = s[2]; g.by = s[3];
+    g.vx = s[4]; g.vy = s[5]; g.L2 = s[6]; g.kd = s[7]; g.ks = s[8];
+    return g;
+}
+// density offsets inside a segment record
+constexpr int kWdA = 9, kWdB = 12, kWcA = 15, kWcB = 18;
+
+// ---- device buffers -----------------------------------------------------------
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace bem
+
+struct bem_ctx {
+    bem_opts opts{};
+    int M = 0;               // outer elements
+    int per_side = 0;
+    int state = 0;           // 0 empty, 1 built, 2 factored
+    int device = 0;
+    double sigma_n = 0.0, shift = 0.0;
+    std::string err;
+    // one-time boundary system
+    bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
+    // per-call workspaces
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5;
+};
+
+namespace bem {
+
+int set_error(bem_ctx* ctx, int code, const char* fmt, ...);
+int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream);
+int check_launch(bem_ctx* ctx, const char* what);
+
+inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
+
+// ---- kernels' host launchers (defined in the .hip files) ----------------------
+// factor.hip
+int launch_assemble(bem_ctx* ctx, hipStream_t s);
+int launch_factor(bem_ctx* ctx, hipStream_t s);
+// forward.hip
+int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
+int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s);
+int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpose, hipStream_t s);
+int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
+int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
+int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s);
+
+}  // namespace bem
+
+namespace bem {
+// float32 policy of the mixed sweeps: hardware log2 and square root;
+// log1p(z) = log(w) z / (w - 1) with w = 1 + z rounded (Goldberg 1991, the
+// rounding error of w cancels between the two factors), exact z when w == 1.
+struct DevF32 {
+    __device__ static float log(float x) { return __logf(x); }
+    __device__ static float log1p(float z)
+    {
+        const float w = 1.0f + z;
+        const float d = w - 1.0f;
+        return d == 0.0f ? z : __logf(w) * (z / d);
+    }
+    __device__ static float sqrt(float x) { return __builtin_sqrtf(x); }
+    __device__ static float atan2(float y, float x) { return atan2f(y, x); }
+};
+}  // namespace bem

@@ -1,0 +1,231 @@
+// seg_math.hpp - per-pair closed forms of the handle term and its adjoint.
+//
+// A straight handle segment a->b, seen from a sample x, contributes to the
+// handle term of Eq. handleterm (regularised kernels, r^2 -> r^2 + eps^2,
+// Sec. 3.1.3)
+//     Md_a wd(a) + Md_b wd(b) + Ms_a wc(a) + Ms_b wc(b)
+// where M?_a / M?_b are the integrals of the double-layer (d) or single-layer
+// (s) kernel against the two linear hat functions of the segment.  Written in
+// d = a - x, e = b - x, v = b - a (L2 = |v|^2):
+//     C  = d x v          (= h L, signed)       D0 = d.v     D1 = e.v = D0 + L2
+//     P  = d.e            R0 = |d|^2 + eps^2    R1 = |e|^2 + eps^2
+//     l0 = log R0         ell = log(R1/R0) = log1p((2 D0 + L2)/R0)
+//     Q  = sqrt(C^2 + eps^2 L2)   (= q L)       Dl = atan2(Q, P + eps^2) in [0, pi]
+//     Md_b = C/(4 pi L2) (ell - 2 D0 Dl/Q)      Md_a = C/(4 pi L2) (2 D1 Dl/Q - ell)
+//     S0 = L2 l0 + D1 ell - 2 L2 + 2 Q Dl       S1 = (2 D0 + L2)(l0 - 1) + R1 ell
+//     Ms_b = (2 D0 S0 - L2 S1) / (8 pi L2^1.5)  Ms_a = (L2 S1 - 2 D1 S0) / (8 pi L2^1.5)
+// ell is formed from R1 - R0 = 2 D0 + L2 rather than as a difference of two
+// logarithms: far from a short segment ell ~ L/|d| is tiny, and the difference
+// of two rounded logs would carry an absolute error that the factor C/L2 ~ |d|/L
+// then amplifies (float32 error growing like |d|/L).
+// (the four moments of the two kernels over the segment; Q^2 + (P+eps^2)^2 =
+// R0 R1 is used by the adjoint).  With eps = 0 and C = 0 the double layer
+// takes its principal value 0; R = 0 (eps = 0, x on an end point) gives the
+// limits u log u^2 -> 0.
+//
+// The adjoint returns, for cotangents (wa, wb, sa, sb) of the four moments,
+// the gradient of  wa Md_a + wb Md_b + sa Ms_a + sb Ms_b  with respect to the
+// end points a and b (the parametric differentiation of Sec. 3.2: the
+// integration variable runs over a fixed interval, so only the integrand
+// depends on the end points).  It needs eps > 0 or a sample off the segment
+// line.
+//
+// Everything is a template over the arithmetic type T and a math policy M
+// supplying log, log1p, sqrt and atan2 for T, so the same code runs on gfx950 and in
+// host-side unit tests.
+#pragma once
+
+#ifndef BEM_HD
+#define BEM_HD __host__ __device__
+#endif
+
+namespace bem {
+
+template <class T>
+struct Moments {
+    T da, db, sa, sb;
+};
+
+template <class T>
+struct Grad4 {
+    T ax, ay, bx, by;
+};
+
+// Per-segment constants that do not depend on the sample.
+template <class T>
+struct SegGeom {
+    T ax, ay, bx, by;   // end points
+    T vx, vy;           // b - a
+    T L2;               // |b - a|^2
+    T kd;               // 1 / (4 pi L2)
+    T ks;               // 1 / (8 pi L2^1.5)
+};
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
+
+// l0 = log R0 and ell = log(R1/R0) = log1p(dR/R0), with the limits of the
+// end-point cases R0 = 0 or R1 = 0 (eps = 0 and x on an end point) when Guard.
+template <class T, class M, bool Guard>
+BEM_HD inline void log_pair(T R0, T R1, T dR, T& l0, T& ell)
+{
+    if (!Guard) {
+        l0 = M::log(R0);
+        ell = M::log1p(dR / R0);
+        return;
+    }
+    l0 = R0 > T(0) ? M::log(R0) : T(0);
+    if (R0 > T(0) && R1 > T(0)) ell = M::log1p(dR / R0);
+    else if (R0 > T(0)) ell = -l0;
+    else ell = R1 > T(0) ? M::log(R1) : T(0);
+}
+
+// Forward moments of one pair.  X, Y: sample; eps2 = eps^2.  Guard = false
+// drops the end-point and on-line limits (valid when both R0, R1 > 0 and
+// Q > 0, e.g. a pair with the sample away from the segment).
+template <class T, class M, bool Guard = true>
+BEM_HD inline Moments<T> seg_moments(const SegGeom<T>& g, T X, T Y, T eps2)
+{
+    const T dx = g.ax - X, dy = g.ay - Y;
+    const T ex = g.bx - X, ey = g.by - Y;
+    const T C = dx * g.vy - dy * g.vx;
+    const T D0 = dx * g.vx + dy * g.vy;
+    const T D1 = D0 + g.L2;
+    const T P = dx * ex + dy * ey;
+    const T R0 = dx * dx + dy * dy + eps2;
+    const T R1 = ex * ex + ey * ey + eps2;
+    const T dR = T(2) * D0 + g.L2;                     // R1 - R0
+    T l0, ell;
+    log_pair<T, M, Guard>(R0, R1, dR, l0, ell);
+    const T Q2 = C * C + eps2 * g.L2;
+    const T Q = M::sqrt(Q2);
+    const T Dl = M::atan2(Q, P + eps2);
+    const T gq = (!Guard || Q2 > T(0)) ? Dl / Q : T(0);
+    const T kd = C * g.kd;
+    Moments<T> m;
+    m.db = kd * (ell - T(2) * D0 * gq);
+    m.da = kd * (T(2) * D1 * gq - ell);
+    const T S0 = g.L2 * l0 + D1 * ell - T(2) * g.L2 + T(2) * Q * Dl;
+    const T S1 = dR * (l0 - T(1)) + R1 * ell;
+    m.sb = g.ks * (T(2) * D0 * S0 - g.L2 * S1);
+    m.sa = g.ks * (g.L2 * S1 - T(2) * D1 * S0);
+    return m;
+}
+
+// Reverse mode: gradient of wa Md_a + wb Md_b + sa Ms_a + sb Ms_b w.r.t. (a, b).
+// Also returns the moments themselves in *mom (the cotangents of the
+// densities) when mom != nullptr.  Intermediates as in seg_moments; the
+// partials of ell = log R1 - log R0 are 1/R1 and -1/R0.
+template <class T, class M, bool Guard = true>
+BEM_HD inline Grad4<T> seg_adjoint(const SegGeom<T>& g, T X, T Y, T eps2,
+                                   T wa, T wb, T sa, T sb, Moments<T>* mom)
+{
+    const T dx = g.ax - X, dy = g.ay - Y;
+    const T ex = g.bx - X, ey = g.by - Y;
+    const T C = dx * g.vy - dy * g.vx;
+    const T D0 = dx * g.vx + dy * g.vy;
+    const T D1 = D0 + g.L2;
+    const T P = dx * ex + dy * ey;
+    const T R0 = dx * dx + dy * dy + eps2;
+    const T R1 = ex * ex + ey * ey + eps2;
+    const T dR = T(2) * D0 + g.L2;
+    T l0, ell;
+    log_pair<T, M, Guard>(R0, R1, dR, l0, ell);
+    const T Q2 = C * C + eps2 * g.L2;
+    const bool qok = !Guard || Q2 > T(0);
+    const T Q = M::sqrt(Q2);
+    const T Pe = P + eps2;
+    const T Dl = M::atan2(Q, Pe);
+    const T iQ = qok ? T(1) / Q : T(0);
+    const T gq = Dl * iQ;
+    const T kd = C * g.kd;
+    const T S0 = g.L2 * l0 + D1 * ell - T(2) * g.L2 + T(2) * Q * Dl;
+    const T S1 = dR * (l0 - T(1)) + R1 * ell;
+    if (mom) {
+        mom->db = kd * (ell - T(2) * D0 * gq);
+        mom->da = kd * (T(2) * D1 * gq - ell);
+        mom->sb = g.ks * (T(2) * D0 * S0 - g.L2 * S1);
+        mom->sa = g.ks * (g.L2 * S1 - T(2) * D1 * S0);
+    }
+    const T iL2 = T(1) / g.L2;
+    // double layer: F_d = (C kd0) Ad,  kd0 = 1/(4 pi L2)
+    const T Ad = (wb - wa) * ell + T(2) * gq * (wa * D1 - wb * D0);
+    // single layer: F_s = ks As,  ks = 1/(8 pi L2^1.5)
+    const T As = T(2) * S0 * (sb * D0 - sa * D1) + g.L2 * S1 * (sa - sb);
+
+    T bC = Ad * g.kd;
+    T bL2 = -kd * Ad * iL2 + g.ks * S1 * (sa - sb) - T(1.5) * g.ks * As * iL2;
+    T bell = kd * (wb - wa);
+    const T bg = T(2) * kd * (wa * D1 - wb * D0);
+    T bD1 = T(2) * kd * gq * wa - T(2) * g.ks * S0 * sa;
+    T bD0 = -T(2) * kd * gq * wb + T(2) * g.ks * S0 * sb;
+    const T bS0 = T(2) * g.ks * (sb * D0 - sa * D1);
+    const T bS1 = g.ks * g.L2 * (sa - sb);
+    // S0 = L2 l0 + D1 ell - 2 L2 + 2 Q Dl
+    bL2 += bS0 * (l0 - T(2));
+    T bl0 = bS0 * g.L2;
+    bD1 += bS0 * ell;
+    bell += bS0 * D1;
+    T bQ = T(2) * bS0 * Dl;
+    T bDl = T(2) * bS0 * Q;
+    // S1 = dR (l0 - 1) + R1 ell,  dR = 2 D0 + L2
+    const T bdR = bS1 * (l0 - T(1));
+    bl0 += bS1 * dR;
+    T bR1 = bS1 * ell;
+    bell += bS1 * R1;
+    bD0 += T(2) * bdR;
+    bL2 += bdR;
+    // gq = Dl / Q
+    bDl += bg * iQ;
+    bQ -= bg * gq * iQ;
+    // l0 = log R0, ell = log R1 - log R0
+    const bool r0ok = !Guard || R0 > T(0), r1ok = !Guard || R1 > T(0);
+    const T iR0 = r0ok ? T(1) / R0 : T(0);
+    const T iR1 = r1ok ? T(1) / R1 : T(0);
+    T bR0 = (bl0 - bell) * iR0;
+    bR1 += bell * iR1;
+    // Dl = atan2(Q, Pe):  dDl/dQ = Pe/(R0 R1), dDl/dP = -Q/(R0 R1)
+    const T iRR = iR0 * iR1;
+    bQ += bDl * Pe * iRR;
+    const T bP = -bDl * Q * iRR;
+    // Q = sqrt(C^2 + eps2 L2)
+    const T bQ2 = qok ? T(0.5) * bQ * iQ : T(0);
+    bC += T(2) * C * bQ2;
+    bL2 += eps2 * bQ2;
+    // back to the vectors d = a - x, e = b - x (C = d x e, D0 = d.e - d.d, D1 = e.e - e.d,
+    // P = d.e, R0 = d.d + eps2, R1 = e.e + eps2, L2 = |e - d|^2)
+    const T ce = bD0 - bD1 + bP;            // coefficient of e in grad_d and of d in grad_e
+    const T cd = T(2) * (bR0 - bD0);        // coefficient of d in grad_d
+    const T cf = T(2) * (bR1 + bD1);        // coefficient of e in grad_e
+    Grad4<T> r;
+    r.ax = bC * ey + ce * ex + cd * dx - T(2) * bL2 * g.vx;
+    r.ay = -bC * ex + ce * ey + cd * dy - T(2) * bL2 * g.vy;
+    r.bx = -bC * dy + ce * dx + cf * ex + T(2) * bL2 * g.vx;
+    r.by = bC * dx + ce * dy + cf * ey + T(2) * bL2 * g.vy;
+    return r;
+}
+
+// Double layer of a constant unit density over an outer element with the
+// exact kernel: beta(x) = -int dG/dn_y dy = (signed angle subtended at x)/2pi.
+template <class T, class M>
+BEM_HD inline T element_beta(T ax, T ay, T vx, T vy, T X, T Y)
+{
+    const T dx = ax - X, dy = ay - Y;
+    const T ex = dx + vx, ey = dy + vy;
+    const T C = dx * vy - dy * vx;
+    const T P = dx * ex + dy * ey;
+    return M::atan2(C, P) * T(kInv2Pi);
+}
+
+// Cubic Bernstein weights at t.
+template <class T>
+BEM_HD inline void bernstein3(T t, T w[4])
+{
+    const T s = T(1) - t;
+    w[0] = s * s * s;
+    w[1] = T(3) * s * s * t;
+    w[2] = T(3) * s * t * t;
+    w[3] = t * t * t;
+}
+
+}  // namespace bem
