@@ -155,6 +155,17 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
     return launch_sweep_mixed(ctx, x, N, K, cbar, (float*)u, stream);
 }
 
+int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N, const void* gbar, double* grad,
+            bem_prec prec, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (N > 0 && !gbar) return set_error(ctx, BEM_EINVAL, "gbar is null");
+    if (H > 0 && !grad) return set_error(ctx, BEM_EINVAL, "grad is null");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
+    return run_vjp(ctx, theta, H, x, N, gbar, prec == BEM_PREC_MIXED, grad, stream);
+}
+
 int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U, hipStream_t stream)
 {
     int rc = check_common(ctx, theta, H, nullptr, 0);

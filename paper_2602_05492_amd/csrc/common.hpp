@@ -86,6 +86,9 @@ int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpo
 int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
 int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s);
+// vjp.hip
+int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
+            double* grad, hipStream_t s);
 
 }  // namespace bem
 

@@ -3,6 +3,7 @@
 // triplet by inverse iteration, deflation and the explicit truncated
 // pseudo-inverse A+ = B^{-1} - v_n u_n^T / s, B = A + (s - sigma_n) u_n v_n^T.
 #include "common.hpp"
+#include "sweep_common.hpp"
 
 namespace bem {
 
@@ -11,17 +12,6 @@ namespace {
 constexpr double kGaussNode = 0.77459666924148337703585307995647992;   // sqrt(3/5)
 constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
 
-// Element i of the counter-clockwise unit square with m elements per side.
-__device__ inline void square_element(int i, int m, double& ax, double& ay, double& bx, double& by)
-{
-    const int side = i / m, k = i % m;
-    const double t0 = (double)k / (double)m, t1 = (double)(k + 1) / (double)m;
-    const double cx[5] = {0.0, 1.0, 1.0, 0.0, 0.0};
-    const double cy[5] = {0.0, 0.0, 1.0, 1.0, 0.0};
-    const double dx = cx[side + 1] - cx[side], dy = cy[side + 1] - cy[side];
-    ax = cx[side] + t0 * dx; ay = cy[side] + t0 * dy;
-    bx = cx[side] + t1 * dx; by = cy[side] + t1 * dy;
-}
 
 // A_ij = delta_ij |G_i|/2 + sum_{q,q'} w_q w_q' dG/dn_y(x_iq, y_jq'), the coincident term zero.
 __global__ void k_assemble(double* __restrict__ A, int M, int m)

@@ -5,6 +5,7 @@
 //   pack       outer element table with the solved values U
 //   sweep      u(x) = cbar + sum_j beta_j(x) U_j + f(x) for every sample
 #include "common.hpp"
+#include "sweep_common.hpp"
 
 namespace bem {
 
@@ -66,16 +67,6 @@ __device__ inline double block_reduce(double v, double* red)
     return r;
 }
 
-__device__ inline void square_element(int i, int m, double& ax, double& ay, double& bx, double& by)
-{
-    const int side = i / m, k = i % m;
-    const double t0 = (double)k / (double)m, t1 = (double)(k + 1) / (double)m;
-    const double cx[5] = {0.0, 1.0, 1.0, 0.0, 0.0};
-    const double cy[5] = {0.0, 0.0, 1.0, 1.0, 0.0};
-    const double dx = cx[side + 1] - cx[side], dy = cy[side + 1] - cy[side];
-    ax = cx[side] + t0 * dx; ay = cy[side] + t0 * dy;
-    bx = cx[side] + t1 * dx; by = cy[side] + t1 * dy;
-}
 
 // F[i, c] = sum_q w_q |G_i|/2 f_c(x_iq): one block per element, threads over segments.
 __global__ void k_boundary_rhs(const double* __restrict__ seg, int K, int m, double eps2, double* __restrict__ F)

@@ -112,85 +112,99 @@ BEM_HD inline Moments<T> seg_moments(const SegGeom<T>& g, T X, T Y, T eps2)
     return m;
 }
 
-// Reverse mode: gradient of wa Md_a + wb Md_b + sa Ms_a + sb Ms_b w.r.t. (a, b).
-// Also returns the moments themselves in *mom (the cotangents of the
-// densities) when mom != nullptr.  Intermediates as in seg_moments; the
-// partials of ell = log R1 - log R0 are 1/R1 and -1/R0.
+// Forward state of one pair kept for the reverse pass.
+template <class T>
+struct PairState {
+    T dx, dy, ex, ey;          // d = a - x, e = b - x
+    T C, D0, D1, dR, R0, R1;
+    T l0, ell, Q, Pe, Dl, iQ, gq, kdC, S0, S1, iR0, iR1;
+};
+
 template <class T, class M, bool Guard = true>
-BEM_HD inline Grad4<T> seg_adjoint(const SegGeom<T>& g, T X, T Y, T eps2,
-                                   T wa, T wb, T sa, T sb, Moments<T>* mom)
+BEM_HD inline PairState<T> pair_forward(const SegGeom<T>& g, T X, T Y, T eps2)
 {
-    const T dx = g.ax - X, dy = g.ay - Y;
-    const T ex = g.bx - X, ey = g.by - Y;
-    const T C = dx * g.vy - dy * g.vx;
-    const T D0 = dx * g.vx + dy * g.vy;
-    const T D1 = D0 + g.L2;
-    const T P = dx * ex + dy * ey;
-    const T R0 = dx * dx + dy * dy + eps2;
-    const T R1 = ex * ex + ey * ey + eps2;
-    const T dR = T(2) * D0 + g.L2;
-    T l0, ell;
-    log_pair<T, M, Guard>(R0, R1, dR, l0, ell);
-    const T Q2 = C * C + eps2 * g.L2;
-    const bool qok = !Guard || Q2 > T(0);
-    const T Q = M::sqrt(Q2);
-    const T Pe = P + eps2;
-    const T Dl = M::atan2(Q, Pe);
-    const T iQ = qok ? T(1) / Q : T(0);
-    const T gq = Dl * iQ;
-    const T kd = C * g.kd;
-    const T S0 = g.L2 * l0 + D1 * ell - T(2) * g.L2 + T(2) * Q * Dl;
-    const T S1 = dR * (l0 - T(1)) + R1 * ell;
-    if (mom) {
-        mom->db = kd * (ell - T(2) * D0 * gq);
-        mom->da = kd * (T(2) * D1 * gq - ell);
-        mom->sb = g.ks * (T(2) * D0 * S0 - g.L2 * S1);
-        mom->sa = g.ks * (g.L2 * S1 - T(2) * D1 * S0);
-    }
+    PairState<T> p;
+    p.dx = g.ax - X; p.dy = g.ay - Y;
+    p.ex = g.bx - X; p.ey = g.by - Y;
+    p.C = p.dx * g.vy - p.dy * g.vx;
+    p.D0 = p.dx * g.vx + p.dy * g.vy;
+    p.D1 = p.D0 + g.L2;
+    const T P = p.dx * p.ex + p.dy * p.ey;
+    p.R0 = p.dx * p.dx + p.dy * p.dy + eps2;
+    p.R1 = p.ex * p.ex + p.ey * p.ey + eps2;
+    p.dR = T(2) * p.D0 + g.L2;
+    log_pair<T, M, Guard>(p.R0, p.R1, p.dR, p.l0, p.ell);
+    const T Q2 = p.C * p.C + eps2 * g.L2;
+    p.Q = M::sqrt(Q2);
+    p.Pe = P + eps2;
+    p.Dl = M::atan2(p.Q, p.Pe);
+    p.iQ = (!Guard || Q2 > T(0)) ? T(1) / p.Q : T(0);
+    p.gq = p.Dl * p.iQ;
+    p.kdC = p.C * g.kd;
+    p.S0 = g.L2 * p.l0 + p.D1 * p.ell - T(2) * g.L2 + T(2) * p.Q * p.Dl;
+    p.S1 = p.dR * (p.l0 - T(1)) + p.R1 * p.ell;
+    p.iR0 = (!Guard || p.R0 > T(0)) ? T(1) / p.R0 : T(0);
+    p.iR1 = (!Guard || p.R1 > T(0)) ? T(1) / p.R1 : T(0);
+    return p;
+}
+
+template <class T>
+BEM_HD inline Moments<T> pair_moments(const SegGeom<T>& g, const PairState<T>& p)
+{
+    Moments<T> m;
+    m.db = p.kdC * (p.ell - T(2) * p.D0 * p.gq);
+    m.da = p.kdC * (T(2) * p.D1 * p.gq - p.ell);
+    m.sb = g.ks * (T(2) * p.D0 * p.S0 - g.L2 * p.S1);
+    m.sa = g.ks * (g.L2 * p.S1 - T(2) * p.D1 * p.S0);
+    return m;
+}
+
+// Reverse pass: gradient of wa Md_a + wb Md_b + sa Ms_a + sb Ms_b w.r.t. (a, b),
+// the partials of ell = log R1 - log R0 being 1/R1 and -1/R0.
+template <class T>
+BEM_HD inline Grad4<T> pair_backward(const SegGeom<T>& g, const PairState<T>& p, T eps2, T wa, T wb, T sa, T sb)
+{
     const T iL2 = T(1) / g.L2;
     // double layer: F_d = (C kd0) Ad,  kd0 = 1/(4 pi L2)
-    const T Ad = (wb - wa) * ell + T(2) * gq * (wa * D1 - wb * D0);
+    const T Ad = (wb - wa) * p.ell + T(2) * p.gq * (wa * p.D1 - wb * p.D0);
     // single layer: F_s = ks As,  ks = 1/(8 pi L2^1.5)
-    const T As = T(2) * S0 * (sb * D0 - sa * D1) + g.L2 * S1 * (sa - sb);
+    const T As = T(2) * p.S0 * (sb * p.D0 - sa * p.D1) + g.L2 * p.S1 * (sa - sb);
 
     T bC = Ad * g.kd;
-    T bL2 = -kd * Ad * iL2 + g.ks * S1 * (sa - sb) - T(1.5) * g.ks * As * iL2;
-    T bell = kd * (wb - wa);
-    const T bg = T(2) * kd * (wa * D1 - wb * D0);
-    T bD1 = T(2) * kd * gq * wa - T(2) * g.ks * S0 * sa;
-    T bD0 = -T(2) * kd * gq * wb + T(2) * g.ks * S0 * sb;
-    const T bS0 = T(2) * g.ks * (sb * D0 - sa * D1);
+    T bL2 = -p.kdC * Ad * iL2 + g.ks * p.S1 * (sa - sb) - T(1.5) * g.ks * As * iL2;
+    T bell = p.kdC * (wb - wa);
+    const T bg = T(2) * p.kdC * (wa * p.D1 - wb * p.D0);
+    T bD1 = T(2) * p.kdC * p.gq * wa - T(2) * g.ks * p.S0 * sa;
+    T bD0 = -T(2) * p.kdC * p.gq * wb + T(2) * g.ks * p.S0 * sb;
+    const T bS0 = T(2) * g.ks * (sb * p.D0 - sa * p.D1);
     const T bS1 = g.ks * g.L2 * (sa - sb);
     // S0 = L2 l0 + D1 ell - 2 L2 + 2 Q Dl
-    bL2 += bS0 * (l0 - T(2));
+    bL2 += bS0 * (p.l0 - T(2));
     T bl0 = bS0 * g.L2;
-    bD1 += bS0 * ell;
-    bell += bS0 * D1;
-    T bQ = T(2) * bS0 * Dl;
-    T bDl = T(2) * bS0 * Q;
+    bD1 += bS0 * p.ell;
+    bell += bS0 * p.D1;
+    T bQ = T(2) * bS0 * p.Dl;
+    T bDl = T(2) * bS0 * p.Q;
     // S1 = dR (l0 - 1) + R1 ell,  dR = 2 D0 + L2
-    const T bdR = bS1 * (l0 - T(1));
-    bl0 += bS1 * dR;
-    T bR1 = bS1 * ell;
-    bell += bS1 * R1;
+    const T bdR = bS1 * (p.l0 - T(1));
+    bl0 += bS1 * p.dR;
+    T bR1 = bS1 * p.ell;
+    bell += bS1 * p.R1;
     bD0 += T(2) * bdR;
     bL2 += bdR;
     // gq = Dl / Q
-    bDl += bg * iQ;
-    bQ -= bg * gq * iQ;
+    bDl += bg * p.iQ;
+    bQ -= bg * p.gq * p.iQ;
     // l0 = log R0, ell = log R1 - log R0
-    const bool r0ok = !Guard || R0 > T(0), r1ok = !Guard || R1 > T(0);
-    const T iR0 = r0ok ? T(1) / R0 : T(0);
-    const T iR1 = r1ok ? T(1) / R1 : T(0);
-    T bR0 = (bl0 - bell) * iR0;
-    bR1 += bell * iR1;
+    const T bR0 = (bl0 - bell) * p.iR0;
+    bR1 += bell * p.iR1;
     // Dl = atan2(Q, Pe):  dDl/dQ = Pe/(R0 R1), dDl/dP = -Q/(R0 R1)
-    const T iRR = iR0 * iR1;
-    bQ += bDl * Pe * iRR;
-    const T bP = -bDl * Q * iRR;
+    const T iRR = p.iR0 * p.iR1;
+    bQ += bDl * p.Pe * iRR;
+    const T bP = -bDl * p.Q * iRR;
     // Q = sqrt(C^2 + eps2 L2)
-    const T bQ2 = qok ? T(0.5) * bQ * iQ : T(0);
-    bC += T(2) * C * bQ2;
+    const T bQ2 = T(0.5) * bQ * p.iQ;
+    bC += T(2) * p.C * bQ2;
     bL2 += eps2 * bQ2;
     // back to the vectors d = a - x, e = b - x (C = d x e, D0 = d.e - d.d, D1 = e.e - e.d,
     // P = d.e, R0 = d.d + eps2, R1 = e.e + eps2, L2 = |e - d|^2)
@@ -198,11 +212,22 @@ BEM_HD inline Grad4<T> seg_adjoint(const SegGeom<T>& g, T X, T Y, T eps2,
     const T cd = T(2) * (bR0 - bD0);        // coefficient of d in grad_d
     const T cf = T(2) * (bR1 + bD1);        // coefficient of e in grad_e
     Grad4<T> r;
-    r.ax = bC * ey + ce * ex + cd * dx - T(2) * bL2 * g.vx;
-    r.ay = -bC * ex + ce * ey + cd * dy - T(2) * bL2 * g.vy;
-    r.bx = -bC * dy + ce * dx + cf * ex + T(2) * bL2 * g.vx;
-    r.by = bC * dx + ce * dy + cf * ey + T(2) * bL2 * g.vy;
+    r.ax = bC * p.ey + ce * p.ex + cd * p.dx - T(2) * bL2 * g.vx;
+    r.ay = -bC * p.ex + ce * p.ey + cd * p.dy - T(2) * bL2 * g.vy;
+    r.bx = -bC * p.dy + ce * p.dx + cf * p.ex + T(2) * bL2 * g.vx;
+    r.by = bC * p.dx + ce * p.dy + cf * p.ey + T(2) * bL2 * g.vy;
     return r;
+}
+
+// Gradient of wa Md_a + wb Md_b + sa Ms_a + sb Ms_b w.r.t. (a, b), and the
+// moments themselves in *mom when mom != nullptr.
+template <class T, class M, bool Guard = true>
+BEM_HD inline Grad4<T> seg_adjoint(const SegGeom<T>& g, T X, T Y, T eps2,
+                                   T wa, T wb, T sa, T sb, Moments<T>* mom)
+{
+    const PairState<T> p = pair_forward<T, M, Guard>(g, X, Y, eps2);
+    if (mom) *mom = pair_moments(g, p);
+    return pair_backward(g, p, eps2, wa, wb, sa, sb);
 }
 
 // Double layer of a constant unit density over an outer element with the

@@ -1,0 +1,320 @@
+// vjp.hip - reverse mode of the forward path (Eq. diffbie, Sec. 3.2), as a
+// vector-Jacobian product with cotangents gbar(x) of u(x):
+//
+//   segments  per handle segment, sums over samples of the pair adjoint:
+//             d/da, d/db of sum_c gbar_c f_c   and  sum gbar_c M_m  (16 sums)
+//   psi       psi_j = sum_x gbar(x) beta_j(x) for every outer element
+//   mu        mu = A+^T psi  (the transposed boundary solve)
+//   boundary  the same segment adjoint at the 3M boundary Gauss points with
+//             cotangent mu_i w_q |G_i|/2 (F_i = sum_q w_q |G_i|/2 f(x_iq))
+//   chain     segment end points -> Bezier control points (Bernstein weights),
+//             end densities -> handle-end jumps (1 - t, t)
+//
+// Sweep mapping: the 64 lanes of a wavefront own 64 consecutive segments (or
+// outer elements) and keep their sums in registers; the wavefront walks a
+// chunk of samples whose positions and cotangents are wave-uniform (scalar
+// loads).  Four wavefronts of a block split the chunk and are summed through
+// LDS; chunks are summed by a separate fixed-order pass, so results do not
+// depend on scheduling.
+#include "common.hpp"
+#include "sweep_common.hpp"
+
+namespace bem {
+
+namespace {
+
+constexpr int kV = kSegVjpVals;   // 16 sums per segment
+constexpr double kGaussNode = 0.77459666924148337703585307995647992;
+constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
+
+template <class GT>
+__device__ inline void load_cot(const GT* __restrict__ gbar, int64_t s, double& g0, double& g1, double& g2)
+{
+    g0 = (double)gbar[3 * s]; g1 = (double)gbar[3 * s + 1]; g2 = (double)gbar[3 * s + 2];
+}
+
+template <class T>
+__device__ inline void add_pair(T* acc, const Grad4<T>& gr, const Moments<T>& m, T g0, T g1, T g2)
+{
+    acc[0] += gr.ax; acc[1] += gr.ay; acc[2] += gr.bx; acc[3] += gr.by;
+    acc[4] += m.da * g0; acc[5] += m.da * g1; acc[6] += m.da * g2;
+    acc[7] += m.db * g0; acc[8] += m.db * g1; acc[9] += m.db * g2;
+    acc[10] += m.sa * g0; acc[11] += m.sa * g1; acc[12] += m.sa * g2;
+    acc[13] += m.sb * g0; acc[14] += m.sb * g1; acc[15] += m.sb * g2;
+}
+
+template <bool Mixed, class GT>
+__global__ void __launch_bounds__(256) k_vjp_segments(const double* __restrict__ x, const GT* __restrict__ gbar,
+                                                      int64_t N, int64_t chunk, const double* __restrict__ seg64,
+                                                      const float* __restrict__ seg32, int K, double eps2, float eps2f,
+                                                      float near2, double* __restrict__ partial)
+{
+    __shared__ double red[3][64][kV + 1];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k = blockIdx.x * 64 + lane;
+    const int64_t n0 = (int64_t)blockIdx.y * chunk;
+    const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
+    double acc[kV];
+    for (int v = 0; v < kV; ++v) acc[v] = 0.0;
+    if (k < K) {
+        const double* s64 = seg64 + (size_t)k * kSegStride;
+        const SegGeom<double> g = load_geom(s64);
+        if (g.L2 > 0.0) {
+            double w[12];
+            for (int c = 0; c < 12; ++c) w[c] = s64[kWdA + c];
+            if (!Mixed) {
+                for (int64_t s = n0 + wave; s < n1; s += 4) {
+                    const double X = x[2 * s], Y = x[2 * s + 1];
+                    double g0, g1, g2;
+                    load_cot(gbar, s, g0, g1, g2);
+                    const double wa = g0 * w[0] + g1 * w[1] + g2 * w[2];
+                    const double wb = g0 * w[3] + g1 * w[4] + g2 * w[5];
+                    const double sa = g0 * w[6] + g1 * w[7] + g2 * w[8];
+                    const double sb = g0 * w[9] + g1 * w[10] + g2 * w[11];
+                    const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+                    add_pair(acc, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
+                }
+            } else {
+                const float* s32 = seg32 + (size_t)k * kSegStride;
+                const SegGeom<float> gf = load_geom(s32);
+                float wf[12];
+                for (int c = 0; c < 12; ++c) wf[c] = s32[kWdA + c];
+                const float lim = near2 * gf.L2;
+                for (int64_t s0 = n0 + wave; s0 < n1; s0 += 4 * 64) {
+                    // float sums over at most 64 samples, then folded into the float64 sums
+                    float af[kV];
+                    for (int v = 0; v < kV; ++v) af[v] = 0.0f;
+                    const int64_t s1 = s0 + 4 * 64 < n1 ? s0 + 4 * 64 : n1;
+                    for (int64_t s = s0; s < s1; s += 4) {
+                        const double X = x[2 * s], Y = x[2 * s + 1];
+                        double g0, g1, g2;
+                        load_cot(gbar, s, g0, g1, g2);
+                        const float Xf = (float)X, Yf = (float)Y;
+                        const float dx = gf.ax - Xf, dy = gf.ay - Yf, ex = gf.bx - Xf, ey = gf.by - Yf;
+                        if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim)) {
+                            const double wa = g0 * w[0] + g1 * w[1] + g2 * w[2];
+                            const double wb = g0 * w[3] + g1 * w[4] + g2 * w[5];
+                            const double sa = g0 * w[6] + g1 * w[7] + g2 * w[8];
+                            const double sb = g0 * w[9] + g1 * w[10] + g2 * w[11];
+                            const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+                            add_pair(acc, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
+                        } else {
+                            const float f0 = (float)g0, f1 = (float)g1, f2 = (float)g2;
+                            const float wa = f0 * wf[0] + f1 * wf[1] + f2 * wf[2];
+                            const float wb = f0 * wf[3] + f1 * wf[4] + f2 * wf[5];
+                            const float sa = f0 * wf[6] + f1 * wf[7] + f2 * wf[8];
+                            const float sb = f0 * wf[9] + f1 * wf[10] + f2 * wf[11];
+                            const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                            add_pair(af, pair_backward(gf, st, eps2f, wa, wb, sa, sb), pair_moments(gf, st), f0, f1, f2);
+                        }
+                    }
+                    for (int v = 0; v < kV; ++v) acc[v] += (double)af[v];
+                }
+            }
+        }
+    }
+    if (wave > 0)
+        for (int v = 0; v < kV; ++v) red[wave - 1][lane][v] = acc[v];
+    __syncthreads();
+    if (wave == 0 && k < K) {
+        double* o = partial + ((size_t)blockIdx.y * K + k) * kV;
+        for (int v = 0; v < kV; ++v) o[v] = ((acc[v] + red[0][lane][v]) + red[1][lane][v]) + red[2][lane][v];
+    }
+}
+
+// psi_j = sum_x gbar(x) beta_j(x): lanes own outer elements.
+template <bool Mixed, class GT>
+__global__ void __launch_bounds__(256) k_vjp_elements(const double* __restrict__ x, const GT* __restrict__ gbar,
+                                                      int64_t N, int64_t chunk, const double* __restrict__ el64,
+                                                      const float* __restrict__ el32, int M, float near2,
+                                                      double* __restrict__ partial)
+{
+    __shared__ double red[3][64][3];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = blockIdx.x * 64 + lane;
+    const int64_t n0 = (int64_t)blockIdx.y * chunk;
+    const int64_t n1 = n0 + chunk < N ? n0 + chunk : N;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (j < M) {
+        const double* e = el64 + (size_t)j * kElemStride;
+        const double ax = e[0], ay = e[1], vx = e[2], vy = e[3];
+        if (!Mixed) {
+            for (int64_t s = n0 + wave; s < n1; s += 4) {
+                double g0, g1, g2;
+                load_cot(gbar, s, g0, g1, g2);
+                const double b = element_beta<double, DevF64>(ax, ay, vx, vy, x[2 * s], x[2 * s + 1]);
+                a0 += b * g0; a1 += b * g1; a2 += b * g2;
+            }
+        } else {
+            const float* ef = el32 + (size_t)j * kElemStride;
+            const float fax = ef[0], fay = ef[1], fvx = ef[2], fvy = ef[3];
+            const float lim = near2 * (fvx * fvx + fvy * fvy);
+            for (int64_t s0 = n0 + wave; s0 < n1; s0 += 4 * 64) {
+                float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+                const int64_t s1 = s0 + 4 * 64 < n1 ? s0 + 4 * 64 : n1;
+                for (int64_t s = s0; s < s1; s += 4) {
+                    const double X = x[2 * s], Y = x[2 * s + 1];
+                    double g0, g1, g2;
+                    load_cot(gbar, s, g0, g1, g2);
+                    const float Xf = (float)X, Yf = (float)Y;
+                    const float dx = fax - Xf, dy = fay - Yf, ex = dx + fvx, ey = dy + fvy;
+                    if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim)) {
+                        const double b = element_beta<double, DevF64>(ax, ay, vx, vy, X, Y);
+                        a0 += b * g0; a1 += b * g1; a2 += b * g2;
+                    } else {
+                        const float b = element_beta<float, DevF32>(fax, fay, fvx, fvy, Xf, Yf);
+                        b0 += b * (float)g0; b1 += b * (float)g1; b2 += b * (float)g2;
+                    }
+                }
+                a0 += (double)b0; a1 += (double)b1; a2 += (double)b2;
+            }
+        }
+    }
+    if (wave > 0) { red[wave - 1][lane][0] = a0; red[wave - 1][lane][1] = a1; red[wave - 1][lane][2] = a2; }
+    __syncthreads();
+    if (wave == 0 && j < M) {
+        double* o = partial + ((size_t)blockIdx.y * M + j) * 3;
+        o[0] = ((a0 + red[0][lane][0]) + red[1][lane][0]) + red[2][lane][0];
+        o[1] = ((a1 + red[0][lane][1]) + red[1][lane][1]) + red[2][lane][1];
+        o[2] = ((a2 + red[0][lane][2]) + red[1][lane][2]) + red[2][lane][2];
+    }
+}
+
+// out[i] = sum_p partial[p * len + i], fixed order.
+__global__ void k_reduce_parts(const double* __restrict__ partial, int nparts, int64_t len, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * len + i];
+    out[i] = s;
+}
+
+// Gauss points of the outer elements and their cotangents mu_i w_q |G_i|/2.
+__global__ void k_gauss_cotangent(const double* __restrict__ mu, int M, int m, double* __restrict__ gx,
+                                  double* __restrict__ gc)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * M) return;
+    const int i = t / 3, q = t % 3;
+    double ax, ay, bx, by;
+    square_element(i, m, ax, ay, bx, by);
+    const double hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay);
+    const double node = q == 0 ? -kGaussNode : (q == 1 ? 0.0 : kGaussNode);
+    const double w = (q == 1 ? kGaussW1 : kGaussW0) * sqrt(hx * hx + hy * hy);
+    gx[2 * t] = 0.5 * (ax + bx) + node * hx;
+    gx[2 * t + 1] = 0.5 * (ay + by) + node * hy;
+    for (int c = 0; c < 3; ++c) gc[3 * t + c] = mu[3 * i + c] * w;
+}
+
+// Segment sums -> theta gradient: one thread per handle.
+__global__ void k_chain_theta(const double* __restrict__ sg, int H, int S, double* __restrict__ grad)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= H) return;
+    double out[20];
+    for (int p = 0; p < 20; ++p) out[p] = 0.0;
+    for (int j = 0; j < S; ++j) {
+        const double* v = sg + ((size_t)h * S + j) * kV;
+        const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
+        double Ba[4], Bb[4];
+        bernstein3(ta, Ba);
+        bernstein3(tb, Bb);
+        for (int c = 0; c < 4; ++c) {
+            out[2 * c] += Ba[c] * v[0] + Bb[c] * v[2];
+            out[2 * c + 1] += Ba[c] * v[1] + Bb[c] * v[3];
+        }
+        for (int c = 0; c < 3; ++c) {
+            out[8 + c] += (1.0 - ta) * v[4 + c] + (1.0 - tb) * v[7 + c];     // wd at end 0
+            out[11 + c] += ta * v[4 + c] + tb * v[7 + c];                    // wd at end 1
+            out[14 + c] += (1.0 - ta) * v[10 + c] + (1.0 - tb) * v[13 + c];  // wc at end 0
+            out[17 + c] += ta * v[10 + c] + tb * v[13 + c];                  // wc at end 1
+        }
+    }
+    for (int p = 0; p < 20; ++p) grad[(size_t)h * 20 + p] = out[p];
+}
+
+int chunks_for(int64_t N, int groups, int64_t& chunk)
+{
+    int64_t nch = (4096 + groups - 1) / groups;
+    const int64_t cap = (N + 255) / 256;
+    if (nch > cap) nch = cap;
+    if (nch < 1) nch = 1;
+    chunk = (N + nch - 1) / nch;
+    if (chunk < 1) chunk = 1;
+    nch = (N + chunk - 1) / chunk;
+    if (nch < 1) nch = 1;
+    return (int)nch;
+}
+
+}  // namespace
+
+int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
+            double* grad, hipStream_t s)
+{
+    int rc;
+    const int S = ctx->opts.segs_per_handle;
+    const int K = H * S;
+    const int M = ctx->M;
+    const double eps2 = ctx->opts.eps * ctx->opts.eps;
+    const double nf = 2.0 * ctx->opts.near_factor;
+    const float near2 = (float)(nf * nf);
+    if (H == 0) return BEM_OK;
+    if ((rc = launch_expand(ctx, theta, H, s))) return rc;
+    if ((rc = ensure(ctx, ctx->U, (size_t)M * 3 * sizeof(double), s))) return rc;
+    if ((rc = launch_pack_elements(ctx, (const double*)ctx->U.ptr, s))) return rc;   // element geometry only
+    const int kgroups = (K + 63) / 64, mgroups = (M + 63) / 64;
+    int64_t chunk_s = 1, chunk_g = 1, chunk_e = 1;
+    const int ns = N > 0 ? chunks_for(N, kgroups, chunk_s) : 0;
+    const int ng = chunks_for(3 * (int64_t)M, kgroups, chunk_g);
+    const int ne = N > 0 ? chunks_for(N, mgroups, chunk_e) : 0;
+    const size_t seg_part = (size_t)(ns + ng) * K * kV;
+    // workspaces: tmp1 segment partials, tmp2 element partials + psi + mu, tmp3 Gauss points, red segment sums
+    if ((rc = ensure(ctx, ctx->tmp1, seg_part * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp2, ((size_t)(ne > 0 ? ne : 1) * M * 3 + 2 * (size_t)M * 3) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp3, (size_t)3 * M * 5 * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->red, (size_t)K * kV * sizeof(double), s))) return rc;
+    double* part = (double*)ctx->tmp1.ptr;
+    double* epart = (double*)ctx->tmp2.ptr;
+    double* psi = epart + (size_t)(ne > 0 ? ne : 1) * M * 3;
+    double* mu = psi + (size_t)M * 3;
+    double* gx = (double*)ctx->tmp3.ptr;
+    double* gc = gx + (size_t)3 * M * 2;
+    const double* seg64 = (const double*)ctx->seg64.ptr;
+    const float* seg32 = (const float*)ctx->seg32.ptr;
+    if (N > 0) {
+        if (!mixed)
+            hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ns), dim3(256), 0, s, x,
+                               (const double*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+        else
+            hipLaunchKernelGGL((k_vjp_segments<true, float>), dim3(kgroups, ns), dim3(256), 0, s, x,
+                               (const float*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+        if (!mixed)
+            hipLaunchKernelGGL((k_vjp_elements<false, double>), dim3(mgroups, ne), dim3(256), 0, s, x,
+                               (const double*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, M, near2, epart);
+        else
+            hipLaunchKernelGGL((k_vjp_elements<true, float>), dim3(mgroups, ne), dim3(256), 0, s, x,
+                               (const float*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, M, near2, epart);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)M * 3, 256)), dim3(256), 0, s, epart, ne,
+                           (int64_t)M * 3, psi);
+        if ((rc = check_launch(ctx, "vjp sweeps"))) return rc;
+        if ((rc = launch_boundary_solve(ctx, psi, mu, true, s))) return rc;
+        hipLaunchKernelGGL(k_gauss_cotangent, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, mu, M, ctx->per_side, gx, gc);
+        hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ng), dim3(256), 0, s, gx, gc,
+                           (int64_t)3 * M, chunk_g, seg64, seg32, K, eps2, (float)eps2, near2,
+                           part + (size_t)ns * K * kV);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, ns + ng,
+                           (int64_t)K * kV, (double*)ctx->red.ptr);
+    } else {
+        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, 0,
+                           (int64_t)K * kV, (double*)ctx->red.ptr);
+    }
+    hipLaunchKernelGGL(k_chain_theta, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->red.ptr, H, S, grad);
+    return check_launch(ctx, "vjp");
+}
+
+}  // namespace bem
