@@ -71,6 +71,15 @@ int check_common(bem_ctx* ctx, const double* theta, int32_t H, const double* x, 
     return BEM_OK;
 }
 
+// expand + element geometry tables (the element values are not used by callers of this one).
+int prepare_forward_tables(bem_ctx* ctx, const double* theta, int32_t H, hipStream_t s)
+{
+    int rc;
+    if ((rc = ensure(ctx, ctx->U, (size_t)ctx->M * 3 * sizeof(double), s))) return rc;
+    if ((rc = launch_expand(ctx, theta, H, s))) return rc;
+    return launch_pack_elements(ctx, (const double*)ctx->U.ptr, s);
+}
+
 // expand -> F -> U -> element table.  Leaves F in ctx->F and U in ctx->U.
 int prepare_forward(bem_ctx* ctx, const double* theta, int32_t H, hipStream_t s)
 {
@@ -166,6 +175,46 @@ int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
     return run_vjp(ctx, theta, H, x, N, gbar, prec == BEM_PREC_MIXED, grad, stream);
 }
 
+int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N, const void* resid, double* JtJ,
+            double* Jtr, bem_gram gram, bem_prec prec, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (N > 0 && !resid) return set_error(ctx, BEM_EINVAL, "resid is null");
+    if (H > 0 && (!JtJ || !Jtr)) return set_error(ctx, BEM_EINVAL, "JtJ / Jtr is null");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
+    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA)
+        return set_error(ctx, BEM_EINVAL, "bad gram mode %d", (int)gram);
+    return run_jtj(ctx, theta, H, x, N, resid, prec == BEM_PREC_MIXED, (int)gram, JtJ, Jtr, stream);
+}
+
+int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N, const double* target,
+            bem_lm_state* state, bem_gram gram, bem_prec prec, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (!state) return set_error(ctx, BEM_EINVAL, "state is null");
+    if (N > 0 && !target) return set_error(ctx, BEM_EINVAL, "target is null");
+    if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
+    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA)
+        return set_error(ctx, BEM_EINVAL, "bad gram mode %d", (int)gram);
+    if (state->mean_rule != 0 && state->mean_rule != 1) return set_error(ctx, BEM_EINVAL, "bad mean_rule");
+    if (!(state->lambda > 0.0) || !std::isfinite(state->lambda)) return set_error(ctx, BEM_EINVAL, "lambda must be > 0");
+    state->lambda = std::fmin(std::fmax(state->lambda, 1e-12), 1e12);
+    rc = run_lm_step(ctx, theta, H, x, N, target, state, (int)gram, prec == BEM_PREC_MIXED, stream);
+    if (rc && ctx->err.empty()) set_error(ctx, rc, "lm_step failed");
+    return rc;
+}
+
+int bem_jacobian(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N, double* J, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (N > 0 && H > 0 && !J) return set_error(ctx, BEM_EINVAL, "J is null");
+    if (N > (1 << 20)) return set_error(ctx, BEM_EINVAL, "bem_jacobian is meant for small N (<= 2^20)");
+    return run_jacobian(ctx, theta, H, x, N, J, stream);
+}
+
 int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U, hipStream_t stream)
 {
     int rc = check_common(ctx, theta, H, nullptr, 0);
@@ -209,7 +258,7 @@ void bem_destroy(bem_ctx* ctx)
     hipDeviceSynchronize();
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
-                      &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5};
+                      &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw};
     for (DevBuf* b : bufs) release(*b);
     delete ctx;
 }

@@ -1,0 +1,188 @@
+// chol.hip - float64 Cholesky of the damped approximate Hessian
+// lambda D + J^T J (Eq. optimstep: positive definite, solved by Cholesky,
+// Sec. 4.3) and the two triangular solves for the LM step.
+// Blocked right-looking factorisation with 64-column panels: diagonal block
+// in LDS, panel rows by per-row forward substitution, trailing update by the
+// float64 GEMM.  A non-positive or non-finite pivot raises a device flag.
+#include "common.hpp"
+#include "sweep_common.hpp"
+
+namespace bem {
+
+namespace {
+
+constexpr int NB = 64;
+
+// dmax[0] = max_i H_ii (one block)
+__global__ void k_diag_max(const double* __restrict__ H, int64_t P, double* __restrict__ dmax)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < P; i += blockDim.x) m = fmax(m, H[i * P + i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dmax[0] = red[0];
+}
+
+// A = H + lam * diag(max(H_ii, 1e-12 * max_j H_jj))
+__global__ void k_damp(const double* __restrict__ H, int64_t P, double lam, const double* __restrict__ dmax,
+                       double* __restrict__ A)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= P) return;
+    double v = H[i * P + j];
+    if (i == j) v += lam * fmax(v, 1e-12 * dmax[0]);
+    A[i * P + j] = v;
+}
+
+// Factor the diagonal block kb in place (lower triangle).
+__global__ void k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag)
+{
+    __shared__ double L[NB][NB + 1];
+    const int64_t o = (int64_t)kb * NB;
+    const int nb = (int)(P - o < NB ? P - o : NB);
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        L[i][j] = A[(o + i) * P + o + j];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = L[j][j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                flag[0] = 1;
+                L[j][j] = 1.0;
+            } else {
+                L[j][j] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        const double djj = L[j][j];
+        for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) L[i][j] /= djj;
+        __syncthreads();
+        const int rem = nb - j - 1;
+        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+            const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) A[(o + i) * P + o + j] = L[i][j];
+    }
+}
+
+// Panel rows below diagonal block kb: row <- row L_kk^{-T} (one thread per row, 64 columns).
+__global__ void __launch_bounds__(64) k_trsm_panel(double* __restrict__ A, int64_t P, int kb)
+{
+    __shared__ double L[NB][NB + 1];
+    const int64_t o = (int64_t)kb * NB;
+    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, j = e % NB;
+        L[i][j] = j <= i ? A[(o + i) * P + o + j] : 0.0;
+    }
+    __syncthreads();
+    const int64_t r = o + NB + (int64_t)blockIdx.x * NB + threadIdx.x;
+    if (r >= P) return;
+    double a[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[j] = A[r * P + o + j];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double s = a[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) s -= a[l] * L[j][l];
+        a[j] = s / L[j][j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) A[r * P + o + j] = a[j];
+}
+
+// Triangular solve of diagonal block kb on b (in place): L y = b (trans 0) or L^T y = b (trans 1).
+__global__ void k_trsv_diag(const double* __restrict__ A, int64_t P, int kb, double* __restrict__ b, int trans)
+{
+    __shared__ double x[NB];
+    const int64_t o = (int64_t)kb * NB;
+    const int nb = (int)(P - o < NB ? P - o : NB);
+    const int t = threadIdx.x;
+    if (t < nb) x[t] = b[o + t];
+    __syncthreads();
+    if (!trans) {
+        for (int j = 0; j < nb; ++j) {
+            if (t == 0) x[j] /= A[(o + j) * P + o + j];
+            __syncthreads();
+            if (t > j && t < nb) x[t] -= A[(o + t) * P + o + j] * x[j];
+            __syncthreads();
+        }
+    } else {
+        for (int j = nb - 1; j >= 0; --j) {
+            if (t == 0) x[j] /= A[(o + j) * P + o + j];
+            __syncthreads();
+            if (t < j) x[t] -= A[(o + j) * P + o + t] * x[j];
+            __syncthreads();
+        }
+    }
+    if (t < nb) b[o + t] = x[t];
+}
+
+}  // namespace
+
+// Damp, factor and check: returns BEM_ENOTPD when a pivot fails (host sync).
+int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,
+                hipStream_t s)
+{
+    int rc;
+    hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(256), 0, s, H, P, dscal);
+    hipLaunchKernelGGL(k_damp, dim3(blocks_for(P, 256), P), dim3(256), 0, s, H, P, lam, dscal, A);
+    if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
+    const int nblk = (int)((P + NB - 1) / NB);
+    for (int kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb, dflag);
+        const int64_t rem = P - (int64_t)(kb + 1) * NB;
+        if (rem > 0) {
+            hipLaunchKernelGGL(k_trsm_panel, dim3(blocks_for(rem, NB)), dim3(NB), 0, s, A, P, kb);
+            double* panel = A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB;
+            double* trail = A + (int64_t)(kb + 1) * NB * P + (int64_t)(kb + 1) * NB;
+            if ((rc = gemm_f64(ctx, (int)rem, (int)rem, NB, -1.0, panel, P, false, panel, P, true, 1.0, trail, P, s,
+                               nullptr, 0)))
+                return rc;
+        }
+    }
+    if ((rc = check_launch(ctx, "cholesky"))) return rc;
+    int hflag = 0;
+    if (hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "cholesky flag readback");
+    return hflag ? BEM_ENOTPD : BEM_OK;
+}
+
+// b <- (L L^T)^{-1} b with the factor in A.
+int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* b, hipStream_t s)
+{
+    int rc;
+    const int nblk = (int)((P + NB - 1) / NB);
+    for (int kb = 0; kb < nblk; ++kb) {
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, b, 0);
+        const int64_t rem = P - (int64_t)(kb + 1) * NB;
+        if (rem > 0 &&
+            (rc = gemm_f64(ctx, (int)rem, 1, NB, -1.0, A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB, P, false,
+                           b + (int64_t)kb * NB, 1, false, 1.0, b + (int64_t)(kb + 1) * NB, 1, s, nullptr, 0)))
+            return rc;
+    }
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, b, 1);
+        const int64_t o = (int64_t)kb * NB;
+        const int nb = (int)(P - o < NB ? P - o : NB);
+        if (o > 0 && (rc = gemm_f64(ctx, (int)o, 1, nb, -1.0, A + o * P, P, true, b + o, 1, false, 1.0, b, 1, s, nullptr, 0)))
+            return rc;
+    }
+    return check_launch(ctx, "cholesky solve");
+}
+
+}  // namespace bem

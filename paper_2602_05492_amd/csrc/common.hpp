@@ -64,7 +64,7 @@ struct bem_ctx {
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw;
 };
 
 namespace bem {
@@ -89,6 +89,29 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
 // vjp.hip
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
             double* grad, hipStream_t s);
+// api.hip: expand + element tables (no boundary solve)
+int prepare_forward_tables(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
+// gemm.hip
+int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta, const double* B,
+             int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles);
+// jtj.hip
+int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s);
+int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
+            int gram, double* JtJ, double* Jtr, hipStream_t s);
+int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, double* J, hipStream_t s);
+// gram_mfma.hip
+int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
+                     const int* tiles128, int ntiles, double* G, hipStream_t s);
+int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
+              const double* r, double* R, hipStream_t s);
+// chol.hip
+int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,
+                hipStream_t s);
+int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* b, hipStream_t s);
+// lm.hip
+int fill_i32(bem_ctx* ctx, int* p, int64_t n, int v, hipStream_t s);
+int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,
+                int gram, bool mixed, hipStream_t s);
 
 }  // namespace bem
 

@@ -1,0 +1,499 @@
+// jtj.hip - Monte Carlo normal equations (Eq. losshessian, Eq. lossjacobian)
+// with the Jacobian of the differential BIE (Eq. diffbie, Sec. 3.2):
+//
+//   J_c(x) = df_c/dtheta(x) + sum_i beta_i(x) Z_c[i, :],   Z = A+ dF/dtheta.
+//
+// Per sample x and channel c the augmented row a_c(x) = [g_c(x) | e(x) | beta(x)]
+// holds the 8H geometry derivatives of f_c (control points), the 4H
+// channel-independent colour coefficients and the M outer-element weights, so
+// that J_c(x) = a_c(x) S_c with S_c = [E_c ; Z_c'] (E_c a column selection).
+// Sample tiles of feature rows Xt = [g_1 | g_2 | g_3 | e | beta] (feature-major,
+// W = 28H + M rows) are formed by the feature kernels and contracted into the
+// Gram G = sum_x Xt Xt^T (only the blocks the three channels need), and into
+// R = sum_x Xt r.  Afterwards, per channel,
+//   J^T J += E_c^T A_c E_c + sym(E_c^T B_c Z_c') + Z_c'^T D Z_c'
+// with A_c, B_c, D the channel's blocks of G, and J^T r likewise.
+#include <vector>
+
+#include "common.hpp"
+#include "sweep_common.hpp"
+
+namespace bem {
+
+namespace {
+
+constexpr double kGaussNode = 0.77459666924148337703585307995647992;
+constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
+
+// ---- output element types of the feature kernels ------------------------------
+__device__ inline uint16_t bf16_bits(float v)
+{
+    // round to nearest even (inputs are finite)
+    const uint32_t u = __float_as_uint(v);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+template <class OutT> struct Store;
+template <> struct Store<double> {
+    __device__ static void put(double* hi, uint16_t*, size_t i, double v) { hi[i] = v; }
+};
+template <> struct Store<float> {
+    __device__ static void put(float* hi, uint16_t*, size_t i, double v) { hi[i] = (float)v; }
+};
+// hi + lo bfloat16 split of the float value
+template <> struct Store<uint16_t> {
+    __device__ static void put(uint16_t* hi, uint16_t* lo, size_t i, double v)
+    {
+        const float f = (float)v;
+        const uint16_t h = bf16_bits(f);
+        hi[i] = h;
+        lo[i] = bf16_bits(f - bf16_value(h));
+    }
+};
+
+// Handle features of one point and one handle (thread per (point, handle)):
+//   rows c*8H + 8h + 2j + d : d f_c / d P_{h,j,d}      (c = 0..2, j = 0..3, d = x, y)
+//   rows 24H + 4h + m       : coefficient of wd0, wd1, wc0, wc1 of handle h (any channel)
+// The vertex gradient of the polyline is chained to control points with the
+// Bernstein weights of the vertex parameter t_k = k/S.
+template <bool Mixed, class OutT>
+__global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, int64_t npts,
+                                                  const double* __restrict__ seg64, const float* __restrict__ seg32,
+                                                  int H, int S, double eps2, float eps2f, float near2,
+                                                  OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
+{
+    using A = typename std::conditional<Mixed, float, double>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = blockIdx.y;
+    if (t >= npts) return;
+    const double X = x[2 * t], Y = x[2 * t + 1];
+    const float Xf = (float)X, Yf = (float)Y;
+    A geo[3][8];
+    A col[4];
+    A pv[3][2];   // gradient carried to the next vertex (from the previous segment's b end)
+    for (int c = 0; c < 3; ++c) {
+        for (int q = 0; q < 8; ++q) geo[c][q] = A(0);
+        pv[c][0] = pv[c][1] = A(0);
+    }
+    for (int q = 0; q < 4; ++q) col[q] = A(0);
+    for (int j = 0; j <= S; ++j) {
+        // contributions to vertex j: a end of segment j (if j < S) + b end of segment j-1 (carried)
+        A va[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
+        A vb[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
+        if (j < S) {
+            const int k = h * S + j;
+            const double* s64 = seg64 + (size_t)k * kSegStride;
+            const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
+            Moments<A> m{A(0), A(0), A(0), A(0)};
+            bool done = false;
+            if (s64[6] == 0.0) done = true;                  // degenerate segment: nothing
+            if (!done && Mixed) {
+                const float* s32 = seg32 + (size_t)k * kSegStride;
+                const SegGeom<float> gf = load_geom(s32);
+                const float dx = gf.ax - Xf, dy = gf.ay - Yf, ex = gf.bx - Xf, ey = gf.by - Yf;
+                const float lim = near2 * gf.L2;
+                if (!((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim))) {
+                    const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                    const Moments<float> mf = pair_moments(gf, st);
+                    m = Moments<A>{(A)mf.da, (A)mf.db, (A)mf.sa, (A)mf.sb};
+                    for (int c = 0; c < 3; ++c) {
+                        const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
+                                                              s32[kWcA + c], s32[kWcB + c]);
+                        va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
+                    }
+                    done = true;
+                }
+            }
+            if (!done) {
+                const SegGeom<double> g = load_geom(s64);
+                const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+                const Moments<double> md = pair_moments(g, st);
+                m = Moments<A>{(A)md.da, (A)md.db, (A)md.sa, (A)md.sb};
+                for (int c = 0; c < 3; ++c) {
+                    const Grad4<double> gr = pair_backward(g, st, eps2, s64[kWdA + c], s64[kWdB + c], s64[kWcA + c],
+                                                           s64[kWcB + c]);
+                    va[c][0] = (A)gr.ax; va[c][1] = (A)gr.ay; vb[c][0] = (A)gr.bx; vb[c][1] = (A)gr.by;
+                }
+            }
+            col[0] += m.da * (A)(1.0 - ta) + m.db * (A)(1.0 - tb);
+            col[1] += m.da * (A)ta + m.db * (A)tb;
+            col[2] += m.sa * (A)(1.0 - ta) + m.sb * (A)(1.0 - tb);
+            col[3] += m.sa * (A)ta + m.sb * (A)tb;
+        }
+        double B[4];
+        bernstein3((double)j / (double)S, B);
+        for (int c = 0; c < 3; ++c) {
+            const A gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
+            for (int q = 0; q < 4; ++q) {
+                geo[c][2 * q] += (A)B[q] * gx;
+                geo[c][2 * q + 1] += (A)B[q] * gy;
+            }
+            pv[c][0] = vb[c][0];
+            pv[c][1] = vb[c][1];
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int q = 0; q < 8; ++q)
+            Store<OutT>::put(Xt, Xlo, (size_t)((size_t)c * 8 * H + 8 * h + q) * ld + t, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (size_t)((size_t)24 * H + 4 * h + q) * ld + t, (double)col[q]);
+}
+
+// beta rows: Xt[row0 + j][t] = beta_j(x_t); thread per (point, element).
+template <bool Mixed, class OutT>
+__global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x, int64_t npts,
+                                                   const double* __restrict__ el64, const float* __restrict__ el32,
+                                                   float near2, OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo,
+                                                   int64_t ld, int64_t row0)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (t >= npts) return;
+    const double X = x[2 * t], Y = x[2 * t + 1];
+    const double* e = el64 + (size_t)j * kElemStride;
+    double b;
+    if (Mixed) {
+        const float* f = el32 + (size_t)j * kElemStride;
+        const float Xf = (float)X, Yf = (float)Y;
+        const float dx = f[0] - Xf, dy = f[1] - Yf, ex = dx + f[2], ey = dy + f[3];
+        const float lim = near2 * (f[2] * f[2] + f[3] * f[3]);
+        if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim))
+            b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+        else
+            b = (double)element_beta<float, DevF32>(f[0], f[1], f[2], f[3], Xf, Yf);
+    } else {
+        b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+    }
+    Store<OutT>::put(Xt, Xlo, (size_t)(row0 + j) * ld + t, b);
+}
+
+__global__ void k_gauss_points(int M, int m, double* __restrict__ gx)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * M) return;
+    const int i = t / 3, q = t % 3;
+    double ax, ay, bx, by;
+    square_element(i, m, ax, ay, bx, by);
+    const double node = q == 0 ? -kGaussNode : (q == 1 ? 0.0 : kGaussNode);
+    gx[2 * t] = 0.5 * (ax + bx) + node * 0.5 * (bx - ax);
+    gx[2 * t + 1] = 0.5 * (ay + by) + node * 0.5 * (by - ay);
+}
+
+// dF[i][f] = sum_q w_q |G_i|/2 Xg[f][3i + q]
+__global__ void k_boundary_features(const double* __restrict__ Xg, int nf, int M, int m, double* __restrict__ dF)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (f >= nf) return;
+    double ax, ay, bx, by;
+    square_element(i, m, ax, ay, bx, by);
+    const double half = 0.5 * sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+    const double* r = Xg + (size_t)f * 3 * M + 3 * i;
+    dF[(size_t)i * nf + f] = half * (kGaussW0 * r[0] + kGaussW1 * r[1] + kGaussW0 * r[2]);
+}
+
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <class T>
+__global__ void k_to_f64(const T* __restrict__ in, int64_t n, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
+// Channel-c augmented Gram in compact order [g_c (8H) | e (4H) | beta (M)],
+// symmetric fill from the upper triangle of G.
+__global__ void k_gather_gram(const double* __restrict__ G, int64_t W, int H, int c, int Wc, double* __restrict__ Gc)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    if (b >= Wc) return;
+    const int64_t ia = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)16 * H + a;
+    const int64_t ib = b < 8 * H ? (int64_t)c * 8 * H + b : (int64_t)16 * H + b;
+    // the upper triangle holds every needed entry (diagonal tiles are computed whole); reading
+    // it on both sides makes the gathered block exactly symmetric
+    Gc[(size_t)a * Wc + b] = ia <= ib ? G[(size_t)ia * W + ib] : G[(size_t)ib * W + ia];
+}
+
+// Zc[i][a] = Z[i][col(a)], col(a) = a < 8H ? c*8H + a : 24H + (a - 8H)
+__global__ void k_gather_z(const double* __restrict__ Z, int H, int M, int c, double* __restrict__ Zc)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int n = 12 * H;
+    if (a >= n) return;
+    const int64_t src = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)24 * H + (a - 8 * H);
+    Zc[(size_t)i * n + a] = Z[(size_t)i * 28 * H + src];
+}
+
+__device__ inline int64_t param_col(int a, int H, int c)
+{
+    if (a < 8 * H) return (int64_t)20 * (a / 8) + (a % 8);
+    const int b = a - 8 * H;
+    return (int64_t)20 * (b / 4) + 8 + 3 * (b % 4) + c;
+}
+
+// JtJ[col(a)][col(b)] += s * (Gc[a][b] + T1[a][b] + T1[b][a] + T2[a][b]), T2 symmetrised so
+// that J^T J is exactly symmetric
+__global__ void k_scatter_h(const double* __restrict__ Gc, int Wc, const double* __restrict__ T1,
+                            const double* __restrict__ T2, int H, int c, double s, double* __restrict__ JtJ, int64_t P)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int a = blockIdx.y;
+    const int n = 12 * H;
+    if (b >= n) return;
+    const double v = Gc[(size_t)a * Wc + b] + T1[(size_t)a * n + b] + T1[(size_t)b * n + a] +
+                     0.5 * (T2[(size_t)a * n + b] + T2[(size_t)b * n + a]);
+    JtJ[param_col(a, H, c) * P + param_col(b, H, c)] += s * v;
+}
+
+// Jtr[col(a)] += s * (R[idx(a)][c] + sum_i Zc[i][a] R[28H + i][c])
+__global__ void k_scatter_g(const double* __restrict__ R, const double* __restrict__ Zc, int H, int M, int c, double s,
+                            double* __restrict__ Jtr)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = 12 * H;
+    if (a >= n) return;
+    const int64_t idx = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)16 * H + a;
+    double v = R[(size_t)idx * 3 + c];
+    for (int i = 0; i < M; ++i) v += Zc[(size_t)i * n + a] * R[((size_t)28 * H + i) * 3 + c];
+    Jtr[param_col(a, H, c)] += s * v;
+}
+
+// J[n][c][p] assembly for the explicit Jacobian: features + beta . Z
+__global__ void k_assemble_jacobian(const double* __restrict__ Xt, int64_t ld, const double* __restrict__ BZ, int H,
+                                    int64_t npts, double* __restrict__ J)
+{
+    const int64_t t = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = 20 * H;
+    if (p >= P || t >= npts) return;
+    const int h = p / 20, q = p % 20;
+    for (int c = 0; c < 3; ++c) {
+        double v;
+        if (q < 8) {
+            const int64_t f = (int64_t)c * 8 * H + 8 * h + q;
+            v = Xt[(size_t)f * ld + t] + BZ[(size_t)t * 28 * H + f];
+        } else {
+            const int m = (q - 8) / 3, cc = (q - 8) % 3;
+            const int64_t f = (int64_t)24 * H + 4 * h + m;
+            v = cc == c ? Xt[(size_t)f * ld + t] + BZ[(size_t)t * 28 * H + f] : 0.0;
+        }
+        J[((size_t)t * 3 + c) * P + p] = v;
+    }
+}
+
+}  // namespace
+
+int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return BEM_OK;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return check_launch(ctx, "fill");
+}
+
+// Feature rows of npts points into Xt (ld = row stride); rows 0..28H-1 handle
+// features, rows 28H.. beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
+template <class OutT>
+static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
+                           uint16_t* Xlo, int64_t ld, hipStream_t s)
+{
+    if (npts == 0) return BEM_OK;
+    const int S = ctx->opts.segs_per_handle;
+    const double eps2 = ctx->opts.eps * ctx->opts.eps;
+    const double nf = 2.0 * ctx->opts.near_factor;
+    const float near2 = (float)(nf * nf);
+    const dim3 grid(blocks_for(npts, 256), H);
+    if (H > 0) {
+        if (mixed)
+            hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+        else
+            hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+    }
+    if (with_beta) {
+        const dim3 gb(blocks_for(npts, 256), ctx->M);
+        if (mixed)
+            hipLaunchKernelGGL((k_beta_rows<true, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+        else
+            hipLaunchKernelGGL((k_beta_rows<false, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+    }
+    return check_launch(ctx, "features");
+}
+
+// Z = A+ dF/dtheta in compact feature columns [M][28H] -> ctx->tmp4 (also leaves Gauss features in tmp3)
+int boundary_derivatives(bem_ctx* ctx, int H, hipStream_t s, double** Zout)
+{
+    int rc;
+    const int M = ctx->M;
+    const int nf = 28 * H;
+    const size_t gxs = (size_t)3 * M * 2;
+    if ((rc = ensure(ctx, ctx->tmp3, (gxs + (size_t)nf * 3 * M) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp4, (size_t)2 * M * nf * sizeof(double), s))) return rc;
+    double* gx = (double*)ctx->tmp3.ptr;
+    double* Xg = gx + gxs;
+    double* dF = (double*)ctx->tmp4.ptr;
+    double* Z = dF + (size_t)M * nf;
+    hipLaunchKernelGGL(k_gauss_points, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, M, ctx->per_side, gx);
+    if ((rc = launch_features<double>(ctx, gx, 3 * (int64_t)M, H, false, false, Xg, nullptr, 3 * (int64_t)M, s))) return rc;
+    hipLaunchKernelGGL(k_boundary_features, dim3(blocks_for(nf, 256), M), dim3(256), 0, s, Xg, nf, M, ctx->per_side, dF);
+    if ((rc = check_launch(ctx, "boundary features"))) return rc;
+    if ((rc = gemm_f64(ctx, M, nf, M, 1.0, (const double*)ctx->Apinv.ptr, M, false, dF, nf, false, 0.0, Z, nf, s,
+                       nullptr, 0)))
+        return rc;
+    *Zout = Z;
+    return BEM_OK;
+}
+
+static std::vector<int> gram_tiles(int H, int W, int ts)
+{
+    // upper-triangle ts x ts tiles, skipping pairs of tiles that lie inside two
+    // different channels' geometry blocks (those products never enter J^T J)
+    const int nt = (W + ts - 1) / ts;
+    auto region = [&](int t) {
+        const int64_t lo = (int64_t)t * ts, hi = lo + ts - 1;
+        if (lo >= 24LL * H) return -1;                           // colour coefficients / beta: shared
+        if (hi >= 24LL * H) return -2;                           // straddles geometry and shared rows
+        const int64_t c0 = lo / (8LL * H), c1 = hi / (8LL * H);
+        return c0 == c1 ? (int)c0 : -2;
+    };
+    std::vector<int> t;
+    for (int i = 0; i < nt; ++i)
+        for (int j = i; j < nt; ++j) {
+            const int ri = region(i), rj = region(j);
+            if (ri >= 0 && rj >= 0 && ri != rj) continue;
+            t.push_back(i);
+            t.push_back(j);
+        }
+    return t;
+}
+
+int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
+            int gram, double* JtJ, double* Jtr, hipStream_t s)
+{
+    int rc;
+    const int M = ctx->M;
+    const int64_t P = 20 * (int64_t)H;
+    const int64_t W = 28 * (int64_t)H + M;
+    const int Wc = 12 * H + M;
+    const int n12 = 12 * H;
+    if (H == 0) return BEM_OK;
+    if ((rc = prepare_forward_tables(ctx, theta, H, s))) return rc;
+    double* Z = nullptr;
+    if ((rc = boundary_derivatives(ctx, H, s, &Z))) return rc;
+    // sample tiles
+    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : 16384;
+    const size_t elem = gram == BEM_GRAM_FP64 ? 8 : 4;
+    while (T > 1024 && (size_t)W * T * elem > ((size_t)3 << 30)) T /= 2;
+    if (T > N) T = N > 0 ? N : 1;
+    T = (T + 63) / 64 * 64;
+    // tmp0: feature tile; tmp1: G [W][W] + R [W][3]; tmp2: residual in f64
+    if ((rc = ensure(ctx, ctx->tmp0, (size_t)W * T * elem, s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp1, ((size_t)W * W + (size_t)W * 3) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp2, (size_t)(N > 0 ? N : 1) * 3 * sizeof(double), s))) return rc;
+    double* G = (double*)ctx->tmp1.ptr;
+    double* R = G + (size_t)W * W;
+    double* r64 = (double*)ctx->tmp2.ptr;
+    if ((rc = fill_f64(ctx, G, W * W + W * 3, 0.0, s))) return rc;
+    if (N > 0) {
+        if (mixed)
+            hipLaunchKernelGGL(k_to_f64<float>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const float*)resid, 3 * N, r64);
+        else
+            hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)resid, 3 * N, r64);
+    }
+    const int ts = gram == BEM_GRAM_FP64 ? 64 : 128;
+    const std::vector<int> tiles = gram_tiles(H, (int)W, ts);
+    const int ntiles = (int)tiles.size() / 2;
+    if ((rc = ensure(ctx, ctx->tmp5, tiles.size() * sizeof(int) + 256, s))) return rc;
+    if (hipMemcpyAsync(ctx->tmp5.ptr, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "tile list upload");
+    // the tile list is read by every tile's Gram; keep the host copy alive until queued work is done
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, BEM_EHIP, "tile list sync");
+    const int* dtiles = (const int*)ctx->tmp5.ptr;
+    for (int64_t t0 = 0; t0 < N; t0 += T) {
+        const int64_t n = N - t0 < T ? N - t0 : T;
+        const double* xt = x + 2 * t0;
+        if (gram == BEM_GRAM_FP64) {
+            double* Xt = (double*)ctx->tmp0.ptr;
+            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s))) return rc;
+            if ((rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles)))
+                return rc;
+            if ((rc = gemm_f64(ctx, (int)W, 3, (int)n, 1.0, Xt, T, false, r64 + 3 * t0, 3, false, 1.0, R, 3, s, nullptr, 0)))
+                return rc;
+        } else if (gram == BEM_GRAM_FP32_MFMA) {
+            float* Xt = (float*)ctx->tmp0.ptr;
+            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s))) return rc;
+            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
+            if ((rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
+        } else {
+            uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
+            uint16_t* Xl = Xh + (size_t)W * T;
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, T, s))) return rc;
+            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
+            if ((rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
+        }
+    }
+    // contraction per channel
+    const double sc = N > 0 ? 1.0 / (double)N : 0.0;
+    if ((rc = fill_f64(ctx, JtJ, P * P, 0.0, s))) return rc;
+    if ((rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
+    const size_t wc2 = (size_t)Wc * Wc;
+    const size_t szc = (size_t)M * n12;
+    if ((rc = ensure(ctx, ctx->tmp2, (wc2 + szc + 2 * (size_t)n12 * n12 + (size_t)M * n12 + (size_t)(N > 0 ? N : 1) * 3) *
+                                         sizeof(double), s)))
+        return rc;
+    double* Gc = (double*)ctx->tmp2.ptr + (size_t)(N > 0 ? N : 1) * 3;   // keep r64 (not needed anymore, but harmless)
+    double* Zc = Gc + wc2;
+    double* T1 = Zc + szc;
+    double* T2 = T1 + (size_t)n12 * n12;
+    double* W1 = T2 + (size_t)n12 * n12;
+    for (int c = 0; c < 3; ++c) {
+        hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, H, c, Wc, Gc);
+        hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, H, M, c, Zc);
+        if ((rc = check_launch(ctx, "gather"))) return rc;
+        // T1 = B_c Zc   (B_c = Gc[0:12H, 12H:Wc])
+        if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, T1, n12, s, nullptr, 0))) return rc;
+        // W1 = D Zc    (D = Gc[12H:, 12H:])
+        if ((rc = gemm_f64(ctx, M, n12, M, 1.0, Gc + (size_t)n12 * Wc + n12, Wc, false, Zc, n12, false, 0.0, W1, n12, s,
+                           nullptr, 0)))
+            return rc;
+        // T2 = Zc^T W1
+        if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Zc, n12, true, W1, n12, false, 0.0, T2, n12, s, nullptr, 0))) return rc;
+        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, T1, T2, H, c, sc, JtJ, P);
+        hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, H, M, c, sc, Jtr);
+        if ((rc = check_launch(ctx, "scatter"))) return rc;
+    }
+    return BEM_OK;
+}
+
+int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, double* J, hipStream_t s)
+{
+    int rc;
+    const int M = ctx->M;
+    const int64_t W = 28 * (int64_t)H + M;
+    if (H == 0 || N == 0) return BEM_OK;
+    if ((rc = prepare_forward_tables(ctx, theta, H, s))) return rc;
+    double* Z = nullptr;
+    if ((rc = boundary_derivatives(ctx, H, s, &Z))) return rc;
+    const int64_t ld = N;
+    if ((rc = ensure(ctx, ctx->tmp0, ((size_t)W * N + (size_t)N * 28 * H) * sizeof(double), s))) return rc;
+    double* Xt = (double*)ctx->tmp0.ptr;
+    double* BZ = Xt + (size_t)W * N;
+    if ((rc = launch_features<double>(ctx, x, N, H, false, true, Xt, nullptr, ld, s))) return rc;
+    // BZ[t][f] = sum_i beta_i(t) Z[i][f]  (beta rows of Xt transposed)
+    if ((rc = gemm_f64(ctx, (int)N, 28 * H, M, 1.0, Xt + (size_t)28 * H * ld, ld, true, Z, 28 * H, false, 0.0, BZ, 28 * H,
+                       s, nullptr, 0)))
+        return rc;
+    hipLaunchKernelGGL(k_assemble_jacobian, dim3(blocks_for(20 * H, 256), N), dim3(256), 0, s, Xt, ld, BZ, H, N, J);
+    return check_launch(ctx, "jacobian");
+}
+
+}  // namespace bem

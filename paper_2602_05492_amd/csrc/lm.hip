@@ -1,0 +1,206 @@
+// lm.hip - one Levenberg-Marquardt step (Eq. optimstep, Sec. 4.3) on the
+// samples of the call: mean colour, residual and loss, gradient by the
+// adjoint, approximate Hessian by the normal equations, damped Cholesky
+// solve, trial evaluation on the same samples, accept / reject and damping
+// update (lambda / 10 on a decrease of the loss, * 10 otherwise).
+#include <cmath>
+
+#include "common.hpp"
+#include "sweep_common.hpp"
+
+namespace bem {
+
+namespace {
+
+constexpr int kRedBlocks = 512;
+
+__global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// partial[b] = sums over a strided share of rows: mode 0: sum_c (u - T)^2 and r = u - T written;
+// mode 1: per-channel sums of T (3 partials); mode 2: per-channel sums of T - u.
+template <class UT>
+__global__ void __launch_bounds__(256) k_rowsum(const UT* __restrict__ u, const double* __restrict__ T, int64_t N,
+                                                int mode, UT* __restrict__ r, double* __restrict__ partial)
+{
+    __shared__ double red[3][256];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const double t0 = T[3 * i], t1 = T[3 * i + 1], t2 = T[3 * i + 2];
+        if (mode == 1) {
+            a0 += t0; a1 += t1; a2 += t2;
+            continue;
+        }
+        const double u0 = (double)u[3 * i], u1 = (double)u[3 * i + 1], u2 = (double)u[3 * i + 2];
+        if (mode == 2) {
+            a0 += t0 - u0; a1 += t1 - u1; a2 += t2 - u2;
+            continue;
+        }
+        const double r0 = u0 - t0, r1 = u1 - t1, r2 = u2 - t2;
+        if (r) { r[3 * i] = (UT)r0; r[3 * i + 1] = (UT)r1; r[3 * i + 2] = (UT)r2; }
+        a0 += r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    red[0][threadIdx.x] = a0; red[1][threadIdx.x] = a1; red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) partial[3 * blockIdx.x + c] = red[c][0];
+}
+
+__global__ void k_finish_sum(const double* __restrict__ partial, int nb, double* __restrict__ out)
+{
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[3 * b + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+__global__ void k_scale(double* __restrict__ v, int64_t n, double s)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] *= s;
+}
+
+__global__ void k_axpy_to(const double* __restrict__ a, const double* __restrict__ d, int64_t n, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - d[i];
+}
+
+__global__ void k_finite(const double* __restrict__ v, int64_t n, int* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(v[i])) flag[0] = 1;
+}
+
+}  // namespace
+
+int fill_i32(bem_ctx* ctx, int* p, int64_t n, int v, hipStream_t s)
+{
+    if (n <= 0) return BEM_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return check_launch(ctx, "fill_i32");
+}
+
+// Three-component sums over the N rows (mode as k_rowsum) into host out[3]; synchronises.
+static int row_sums(bem_ctx* ctx, const void* u, bool f32, const double* T, int64_t N, int mode, void* r, double* out,
+                    double* dpart, hipStream_t s)
+{
+    const int nb = N > 0 ? (int)((N + 255) / 256 < kRedBlocks ? (N + 255) / 256 : kRedBlocks) : 1;
+    if (N > 0) {
+        if (f32)
+            hipLaunchKernelGGL(k_rowsum<float>, dim3(nb), dim3(256), 0, s, (const float*)u, T, N, mode, (float*)r, dpart);
+        else
+            hipLaunchKernelGGL(k_rowsum<double>, dim3(nb), dim3(256), 0, s, (const double*)u, T, N, mode, (double*)r, dpart);
+        hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(64), 0, s, dpart, nb, dpart + 3 * kRedBlocks);
+    } else {
+        fill_f64(ctx, dpart + 3 * kRedBlocks, 3, 0.0, s);
+    }
+    int rc = check_launch(ctx, "row sums");
+    if (rc) return rc;
+    if (hipMemcpyAsync(out, dpart + 3 * kRedBlocks, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "row sums readback");
+    return BEM_OK;
+}
+
+int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,
+                int gram, bool mixed, hipStream_t s)
+{
+    int rc;
+    const int64_t P = 20 * (int64_t)H;
+    const size_t ue = mixed ? sizeof(float) : sizeof(double);
+    const int64_t n3 = 3 * (N > 0 ? N : 1);
+    // lm workspace layout (ctx->lmw): u | r | g | JtJ | Jtr | A | delta | theta' | partials | flag
+    const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)20 * H +
+                                                 3 * (size_t)kRedBlocks + 8) * sizeof(double) + 64;
+    if ((rc = ensure(ctx, ctx->lmw, bytes, s))) return rc;
+    char* base = (char*)ctx->lmw.ptr;
+    void* u = base;
+    void* r = base + (size_t)n3 * ue;
+    double* g = (double*)(base + 2 * (size_t)n3 * ue);
+    double* JtJ = g + P;
+    double* Jtr = JtJ + (size_t)P * P;
+    double* A = Jtr + P;
+    double* delta = A + (size_t)P * P;
+    double* th1 = delta + P;
+    double* dpart = th1 + (size_t)20 * H;
+    int* dflag = (int*)(dpart + 3 * kRedBlocks + 4);
+    const bem_prec prec = mixed ? BEM_PREC_MIXED : BEM_PREC_FP64;
+    st->accepted = 0;
+    st->chol_retries = 0;
+    // mean colour
+    double sums[3];
+    if (st->mean_rule == 0) {
+        if ((rc = row_sums(ctx, nullptr, false, T, N, 1, nullptr, sums, dpart, s))) return rc;
+        for (int c = 0; c < 3; ++c) st->cbar_sum[c] += sums[c];
+        st->cbar_count += N;
+        for (int c = 0; c < 3; ++c) st->cbar[c] = st->cbar_count > 0 ? st->cbar_sum[c] / (double)st->cbar_count : 0.0;
+    } else {
+        const double zero[3] = {0.0, 0.0, 0.0};
+        if ((rc = bem_eval(ctx, theta, H, x, N, zero, u, prec, s))) return rc;
+        if ((rc = row_sums(ctx, u, mixed, T, N, 2, nullptr, sums, dpart, s))) return rc;
+        for (int c = 0; c < 3; ++c) st->cbar[c] = N > 0 ? sums[c] / (double)N : 0.0;
+    }
+    // residual and loss at theta
+    if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) return rc;
+    if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
+    const double L0 = N > 0 ? 0.5 * sums[0] / (double)N : 0.0;
+    st->loss_before = L0;
+    st->loss_after = L0;
+    if (!std::isfinite(L0)) return set_error(ctx, BEM_ENUMERIC, "non-finite loss at the current parameters");
+    if (H == 0 || N == 0) return BEM_OK;
+    // gradient by the adjoint, Hessian by the normal equations
+    if ((rc = bem_vjp(ctx, theta, H, x, N, r, g, prec, s))) return rc;
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / (double)N);
+    if ((rc = bem_jtj(ctx, theta, H, x, N, r, JtJ, Jtr, (bem_gram)gram, prec, s))) return rc;
+    // damped Cholesky, raising lambda until it factors
+    double lam = st->lambda;
+    for (int attempt = 0;; ++attempt) {
+        rc = chol_factor(ctx, JtJ, P, lam, A, dflag, dpart, s);
+        if (rc == BEM_OK) break;
+        if (rc != BEM_ENOTPD) return rc;
+        if (attempt >= 10) {
+            st->lambda = lam;
+            return set_error(ctx, BEM_ENOTPD, "damped normal matrix not positive definite after %d retries", attempt);
+        }
+        lam = std::fmin(lam * 10.0, 1e12);
+        st->chol_retries++;
+    }
+    st->lambda = lam;
+    if (hipMemcpyAsync(delta, g, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "copy gradient");
+    if ((rc = chol_solve(ctx, A, P, delta, s))) return rc;
+    if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
+    hipLaunchKernelGGL(k_finite, dim3(blocks_for(P, 256)), dim3(256), 0, s, delta, P, dflag);
+    hipLaunchKernelGGL(k_axpy_to, dim3(blocks_for(P, 256)), dim3(256), 0, s, theta, delta, P, th1);
+    if ((rc = check_launch(ctx, "update"))) return rc;
+    // trial loss on the same samples and mean colour
+    if ((rc = bem_eval(ctx, th1, H, x, N, st->cbar, u, prec, s))) return rc;
+    if ((rc = row_sums(ctx, u, mixed, T, N, 0, nullptr, sums, dpart, s))) return rc;
+    int hflag = 0;
+    if (hipMemcpy(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "flag readback");
+    const double L1 = 0.5 * sums[0] / (double)N;
+    st->loss_after = L1;
+    if (!hflag && std::isfinite(L1) && L1 < L0) {
+        if (hipMemcpyAsync(theta, th1, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "accept copy");
+        st->accepted = 1;
+        st->lambda = std::fmax(lam / 10.0, 1e-12);
+    } else {
+        st->lambda = std::fmin(lam * 10.0, 1e12);
+    }
+    return BEM_OK;
+}
+
+}  // namespace bem

@@ -1,0 +1,177 @@
+"""GPU Jacobian, normal equations (bem_jtj) and LM step (lm_step) against the FP64 oracle.
+
+Bars: FP64 path within 1e-10 relative; the FP32-MFMA and split-BF16 Gram
+contractions are reported against FP64 (float32 accumulation within a
+sample tile) and must stay within 1e-4 relative on J^T J.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2602_05492_amd import bem as B
+from paper_2602_05492_amd import workload as W
+from helpers import ctx_for, dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_jacobian_tiny_matches_oracle():
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S)
+    x = wl.samples(0)[:64]
+    J = host(ctx.jacobian(dev(wl.theta_true), dev(x)))
+    Jo = O.jacobian(wl.theta_true, x, wl.S, wl.eps)
+    err = _rel(J, Jo)
+    log("jacobian rel err", err)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("tile_rows", [0, 320])
+def test_jtj_fp64_tiny_matches_oracle(tile_rows):
+    """Several sample tiles and a ragged tail (N = 2085) when tile_rows = 320."""
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S, tile_rows=tile_rows)
+    x = wl.samples(0)[:2085]
+    r = W.random_vector(51, (len(x), 3))
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r), "fp64", "fp64")
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log("jtj fp64 rel err", eh, "jtr", eg)
+    assert eh < 1e-10 and eg < 1e-10
+    assert np.array_equal(host(JtJ), host(JtJ).T) or _rel(host(JtJ), host(JtJ).T) < 1e-14
+
+
+@pytest.mark.parametrize("gram,prec", [("fp32_mfma", "mixed"), ("bf16x3_mfma", "mixed"), ("bf16x3_mfma", "fp64"),
+                                       ("fp64", "mixed")])
+def test_jtj_reduced_precision_modes(gram, prec):
+    wl = W.make_config(2)
+    ctx = ctx_for(wl.S, tile_rows=1024)
+    idx = wl.subsample(3000)
+    x = wl.samples(0)[idx]
+    r = W.random_vector(52, (len(x), 3))
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r, dt), gram, prec)
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"jtj {gram}/{prec}: rel err JtJ {eh:.3e} Jtr {eg:.3e}")
+    assert eh < 1e-4 and eg < 1e-3
+
+
+def test_jtj_medium_fp64_matches_oracle():
+    wl = W.make_config(2)
+    ctx = ctx_for(wl.S)
+    idx = wl.subsample(1500, step=3)
+    x = wl.samples(0)[idx]
+    r = W.random_vector(53, (len(x), 3))
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r), "fp64", "fp64")
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+    assert _rel(host(JtJ), Ho) < 1e-10 and _rel(host(Jtr), go) < 1e-10
+
+
+def test_jtj_full_size_properties():
+    """LM workload at full size (2,097,152 samples, P = 5,120), split-BF16 Gram on mixed tiles:
+    symmetry, positive semi-definiteness, additivity over two halves, and J^T r against the adjoint."""
+    wl = W.make_config(5)
+    ctx = ctx_for(wl.S)
+    x = dev(wl.samples(0))
+    th = dev(wl.theta0)
+    r32 = dev(0.2 * wl.noise(0), torch.float32)
+    JtJ, Jtr = ctx.jtj(th, x, r32, "bf16x3_mfma", "mixed")
+    Hh = host(JtJ)
+    assert np.isfinite(Hh).all()
+    assert _rel(Hh, Hh.T) < 1e-12
+    p = W.random_vector(54, (wl.P,))
+    assert p @ Hh @ p > 0
+    n1 = wl.N // 3
+    J1, g1 = ctx.jtj(th, x[:n1].contiguous(), r32[:n1].contiguous(), "bf16x3_mfma", "mixed")
+    J2, g2 = ctx.jtj(th, x[n1:].contiguous(), r32[n1:].contiguous(), "bf16x3_mfma", "mixed")
+    comb = (n1 * host(J1) + (wl.N - n1) * host(J2)) / wl.N
+    e_add = _rel(comb, Hh)
+    g_vjp = host(ctx.vjp(th, x, r32.double().contiguous(), "fp64")).reshape(-1) / wl.N
+    e_g = _rel(host(Jtr), g_vjp)
+    log(f"full-size jtj: additivity rel err {e_add:.3e}; Jtr vs fp64 adjoint {e_g:.3e}")
+    assert e_add < 1e-6
+    assert e_g < 1e-3
+
+
+def _lm_compare(wl, x, T, theta, lam, mean_rule, gram, prec, tol_theta):
+    ctx = ctx_for(wl.S)
+    st_o = O.LMState(lam=lam, mean_rule=mean_rule)
+    th_o, st_o = O.lm_step(theta, x, T, st_o, wl.S, wl.eps)
+    th_d = dev(theta)
+    st = B.new_lm_state(lam, mean_rule)
+    ctx.lm_step(th_d, dev(x), dev(T), st, gram, prec)
+    log(f"lm {gram}/{prec}: loss {st.loss_before:.12e} -> {st.loss_after:.12e} (oracle {st_o.loss_before:.12e} -> "
+        f"{st_o.loss_after:.12e}), accepted {st.accepted}/{st_o.accepted}, lambda {st.lam:.1e}/{st_o.lam:.1e}")
+    assert abs(st.loss_before - st_o.loss_before) <= 1e-10 * st_o.loss_before * (1 if prec == "fp64" else 1e6)
+    assert bool(st.accepted) == bool(st_o.accepted)
+    assert st.lam == pytest.approx(st_o.lam)
+    ctol = 1e-12 if prec == "fp64" else 1e-4            # the least-squares mean uses the float32 forward
+    assert np.allclose(np.array(st.cbar[:]), st_o.cbar, rtol=ctol, atol=ctol)
+    d_o = th_o - theta
+    d = host(th_d) - theta
+    e = float(np.abs(d - d_o).max() / max(np.abs(d_o).max(), 1e-300)) if st_o.accepted else float(np.abs(d).max())
+    log(f"lm step rel err {e:.3e}")
+    assert e < tol_theta
+    return st, st_o
+
+
+def test_lm_step_tiny_fp64_matches_oracle():
+    wl = W.make_config(1)
+    x = wl.samples(0)
+    T = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps) + wl.spec.sigma * wl.noise(0)
+    _lm_compare(wl, x, T, wl.theta0, 1e-3, 0, "fp64", "fp64", 1e-8)
+
+
+def test_lm_step_tiny_least_squares_mean_and_mixed():
+    wl = W.make_config(1)
+    x = wl.samples(0)[:8192]
+    T = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps) + wl.spec.sigma * wl.noise(0)[:8192]
+    _lm_compare(wl, x, T, wl.theta0, 1e-3, 1, "fp64", "fp64", 1e-8)
+    _lm_compare(wl, x, T, wl.theta0, 1e-3, 1, "bf16x3_mfma", "mixed", 1e-2)
+
+
+def test_lm_step_medium_matches_oracle():
+    wl = W.make_config(2)
+    idx = wl.subsample(4096)
+    x = wl.samples(0)[idx]
+    T = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps) + wl.spec.sigma * wl.noise(0)[idx]
+    _lm_compare(wl, x, T, wl.theta0, 1e-3, 0, "fp64", "fp64", 1e-7)
+
+
+def test_lm_iterations_medium_full_size_decrease():
+    """Medium workload at full size: 20 LM iterations with fresh samples each iteration, lambda x/10;
+    the loss on each iteration's samples never increases across an accepted step."""
+    wl = W.make_config(2)
+    ctx = ctx_for(wl.S)
+    th = dev(wl.theta0)
+    tht = dev(wl.theta_true)
+    st = B.new_lm_state(wl.lam0, 0)
+    acc = 0
+    for it in range(wl.spec.lm_iters):
+        x = dev(wl.samples(it))
+        T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * dev(wl.noise(it))
+        ctx.lm_step(th, x, T, st, "fp64", "fp64")
+        acc += st.accepted
+        assert (st.loss_after < st.loss_before) == bool(st.accepted)
+    log(f"20 LM iterations: {acc} accepted, last loss {st.loss_after:.6e}, lambda {st.lam:.1e}")
+    assert acc >= 10
+    assert st.loss_after < 0.5 * wl.spec.sigma ** 2 * 3 * 1.2
+
+
+def test_lm_step_rejects_non_finite_parameters():
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S)
+    th = wl.theta0.copy()
+    th[0, 3] = np.nan
+    x = dev(wl.samples(0)[:256])
+    T = dev(np.full((256, 3), 0.5))
+    st = B.new_lm_state(1e-3, 0)
+    with pytest.raises(B.BemError) as e:
+        ctx.lm_step(dev(th), x, T, st, "fp64", "fp64")
+    assert e.value.status == -6
