@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the differential-BEM Levenberg-Marquardt step on one MI355X.
+
+One step = one full LM iteration on a fresh batch of samples: mean colour,
+forward sweep, residual and loss, gradient by the adjoint, J tiles and Gram
+contraction for J^T J, float64 Cholesky solve, trial forward and
+accept/reject (the whole hot path).  Workload: 256 cubic handles x 32
+segments (P = 5,120 parameters), 2,097,152 uniform samples per step with
+Gaussian target noise sigma = 0.2, eps = 1e-2, 256 outer elements per side.
+Batches are generated and placed in HBM before the timed region.
+
+Prints one JSON line.  `roofline` is for the kernel family with the largest
+share of the timed region, from HIP events recorded by the library on its
+launch stream; `cpu_baseline` times the FP64 CPU oracle on a bounded sample of
+the same workload and extrapolates linearly.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sample×segment pairs/s and LM steps/s, FP32-mixed vs FP64 at 1e-4 color err"
+PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15}
+# algorithmic work per unit (float32 flops, FMA = 2)
+F_HANDLE_PAIR = 110.0      # forward: one sample x one handle segment
+F_BOUNDARY_PAIR = 40.0     # forward / adjoint: one sample x one outer element
+F_GRAD_PAIR = 300.0        # adjoint or J-tile: one sample x one handle segment
+
+
+def gram_entries(H: int, M: int) -> int:
+    """Distinct Gram entries J^T J needs per sample (symmetric blocks counted once)."""
+    g, s = 8 * H, 4 * H + M
+    return 3 * (g * (g + 1) // 2) + 3 * g * s + s * (s + 1) // 2
+
+
+def cpu_baseline(wl, x_host, budget_note: str) -> dict:
+    """Time the FP64 oracle on bounded pieces of one LM step and extrapolate to the full step."""
+    import numpy as np
+    import oracle as O
+    S, eps = wl.S, wl.eps
+    th = wl.theta0
+    bnd = O.boundary(wl.elems_per_side)                 # one-time factor, not part of a step
+    gp = bnd.gp.reshape(-1, 2)
+    n_eval, n_jac, n_gp = 256, 64, 192
+    xs = x_host[:n_eval]
+    t = time.perf_counter()
+    O.handle_term(xs, th, S, eps)
+    O.element_weights(xs, bnd)
+    t_eval = (time.perf_counter() - t) / n_eval          # per sample, forward
+    t = time.perf_counter()
+    O.handle_term(gp[:n_gp], th, S, eps)
+    t_rhs = (time.perf_counter() - t) / n_gp * len(gp)   # boundary right-hand side, per evaluation
+    t = time.perf_counter()
+    O.handle_term_jacobian(gp[:n_gp], th, S, eps)
+    t_z = (time.perf_counter() - t) / n_gp * len(gp)     # dF/dtheta at the Gauss points, per step
+    Z = np.zeros((bnd.M, 3, th.size))
+    t = time.perf_counter()
+    xj = x_host[:n_jac]
+    J = O.handle_term_jacobian(xj, th, S, eps) + np.einsum("nj,jcp->ncp", O.element_weights(xj, bnd), Z)
+    Jr = J.reshape(-1, th.size)
+    _ = Jr.T @ Jr
+    t_jac = (time.perf_counter() - t) / n_jac            # per sample: J rows + Gram update
+    N = wl.N
+    step = 2 * (N * t_eval + t_rhs) + t_z + N * t_jac
+    return {"value": 1.0 / step, "unit": "LM steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (numpy FP64, one process) timed on {n_eval} samples (forward), {n_jac} samples "
+                       f"(Jacobian rows + Gram) and {n_gp} of {len(gp)} boundary Gauss points of the LM workload, "
+                       f"extrapolated linearly to one step of {N:,} samples: {step:.3e} s/step. {budget_note}")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--gram", default="fp32_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
+    ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built "
+              "(every GPU box here has a single MI355X); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2602_05492_amd import bem as B
+    from paper_2602_05492_amd import workload as W
+
+    wl = W.make_config(5)
+    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
+    H, S, N, M = wl.H, wl.S, wl.N, ctx.M
+    K = H * S
+    nb = args.warmup + args.steps
+    tht = torch.from_numpy(wl.theta_true).cuda()
+    batches = []
+    x0_host = None
+    for i in range(nb):
+        xh = wl.samples(i)
+        if x0_host is None:
+            x0_host = xh
+        x = torch.from_numpy(xh).cuda()
+        T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(i)).cuda()
+        batches.append((x, T))
+    theta = torch.from_numpy(wl.theta0).cuda()
+    st = B.new_lm_state(wl.lam0, 0)
+    for i in range(args.warmup):
+        ctx.lm_step(theta, batches[i][0], batches[i][1], st, args.gram, args.prec)
+        print(f"warmup {i}: loss {st.loss_before:.6e} -> {st.loss_after:.6e} accepted {st.accepted}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    losses = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup, nb):
+        ctx.lm_step(theta, batches[i][0], batches[i][1], st, args.gram, args.prec)
+        losses.append((st.loss_before, st.loss_after, int(st.accepted)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    for i, l in enumerate(losses):
+        print(f"step {i}: loss {l[0]:.6e} -> {l[1]:.6e} accepted {l[2]}", file=sys.stderr, flush=True)
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = 1e3 / ms
+
+    # algorithmic work of each kernel family in the timed region
+    steps = args.steps
+    work = {
+        "sweep_mixed": prof["sweep_mixed"][1] * (F_HANDLE_PAIR * N * K + F_BOUNDARY_PAIR * N * M),
+        "sweep_f64": prof["sweep_f64"][1] * (F_HANDLE_PAIR * N * K + F_BOUNDARY_PAIR * N * M),
+        "vjp_segments": steps * F_GRAD_PAIR * (N + 3 * M) * K,
+        "vjp_elements": steps * F_BOUNDARY_PAIR * N * M,
+        "features": steps * F_GRAD_PAIR * (N + 3 * M) * K,
+        "gram_mfma": steps * 2.0 * N * gram_entries(H, M),
+        "gram_f64": steps * 2.0 * N * gram_entries(H, M),
+    }
+    peak_of = {"sweep_mixed": ("alu", PEAKS["fp32_vector"]), "sweep_f64": ("alu", PEAKS["fp64_vector"]),
+               "vjp_segments": ("alu", PEAKS["fp32_vector"] if args.prec == "mixed" else PEAKS["fp64_vector"]),
+               "vjp_elements": ("alu", PEAKS["fp32_vector"]),
+               "features": ("alu", PEAKS["fp32_vector"] if args.prec == "mixed" else PEAKS["fp64_vector"]),
+               "gram_mfma": ("mfma", PEAKS["bf16_mfma"] if args.gram == "bf16x3_mfma" else PEAKS["fp32_mfma"]),
+               "gram_f64": ("alu", PEAKS["fp64_vector"])}
+    timed = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max((k for k in timed if k in work), key=lambda k: timed[k][0])
+    tot_ms, launches = timed[dom]
+    achieved = work[dom] / (tot_ms * 1e-3) / 1e12
+    bound, peak = peak_of[dom]
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / (peak / 1e12), "traffic": None, "launches": launches,
+                "avg_launch_ms": tot_ms / launches}
+    fwd_ms = prof["sweep_mixed" if args.prec == "mixed" else "sweep_f64"]
+    pairs_fwd = (N * (K + M)) / (fwd_ms[0] / fwd_ms[1] * 1e-3) if fwd_ms[1] else None
+    vjp_ms = prof["vjp_segments"][0] + prof["vjp_elements"][0]
+    pairs_vjp = steps * (N * (K + M)) / (vjp_ms * 1e-3) if vjp_ms > 0 else None
+
+    speedup = None
+    fp64_ms = None
+    if args.fp64_ref and args.prec == "mixed":
+        th64 = torch.from_numpy(wl.theta0).cuda()
+        st64 = B.new_lm_state(wl.lam0, 0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.lm_step(th64, batches[0][0], batches[0][1], st64, "fp64", "fp64")
+        torch.cuda.synchronize()
+        fp64_ms = (time.perf_counter() - t) * 1e3
+        speedup = fp64_ms / ms
+        print(f"fp64 reference step: {fp64_ms:.1f} ms (loss {st64.loss_before:.6e} -> {st64.loss_after:.6e})",
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_baseline:
+        cpu = cpu_baseline(wl, x0_host, "")
+        cpu["sample"] = cpu["sample"].strip()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "LM steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "LM normal equations: 256 cubic handles x 32 segments (P = 5,120), "
+                               "2,097,152 uniform samples per step, sigma 0.2, eps 1e-2, 1,024 outer elements",
+                   "handles": H, "segs_per_handle": S, "samples": N, "params": wl.P, "outer_elements": M,
+                   "prec": args.prec, "gram": args.gram, "parallelism": "single GPU"},
+        "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
+        "fp64_gpu_ms_per_step": fp64_ms, "speedup_vs_fp64_gpu": speedup,
+        "kernel_ms_per_step": {k: v[0] / steps for k, v in timed.items()},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

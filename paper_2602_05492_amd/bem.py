@@ -58,6 +58,9 @@ _SIGS = {
     "bem_get_matrix": (ctypes.c_int, [P, I32, P, P]),
     "bem_num_elements": (I32, [P]),
     "bem_factor_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "bem_profile": (ctypes.c_int, [P, I32]),
+    "bem_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "bem_profile_name": (ctypes.c_char_p, [I32]),
     "bem_destroy": (None, [P]),
     "bem_last_error": (ctypes.c_char_p, [P]),
 }
@@ -158,6 +161,20 @@ class Context:
             if x.dim() != 2 or x.shape[1] != 2:
                 raise ValueError("x must be [N, 2]")
         return theta.shape[0], (x.shape[0] if x is not None else 0)
+
+    # -- kernel timing -----------------------------------------------------------
+    def profile(self, enable: bool = True):
+        self._check(lib().bem_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{family: (total_ms, launches)} of the kernels recorded since profile(True)."""
+        out = {}
+        for t in range(11):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            self._check(lib().bem_profile_read(self._h, t, ctypes.byref(ms), ctypes.byref(n)))
+            out[lib().bem_profile_name(t).decode()] = (ms.value, n.value)
+        return out
 
     # -- entry points ----------------------------------------------------------
     def factor_info(self):

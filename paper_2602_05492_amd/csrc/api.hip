@@ -50,6 +50,61 @@ int check_launch(bem_ctx* ctx, const char* what)
     return BEM_OK;
 }
 
+static hipEvent_t pool_get(bem_ctx* ctx)
+{
+    auto& P = ctx->prof.pool;
+    if (!P.empty()) {
+        hipEvent_t e = P.back();
+        P.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void prof_begin(bem_ctx* ctx, int, hipStream_t s, hipEvent_t* start)
+{
+    *start = nullptr;
+    if (!ctx || !ctx->prof.on) return;
+    hipEvent_t e = pool_get(ctx);
+    if (e && hipEventRecord(e, s) == hipSuccess) *start = e;
+}
+
+void prof_end(bem_ctx* ctx, int tag, hipStream_t s, hipEvent_t start)
+{
+    if (!ctx || !start) return;
+    hipEvent_t e = pool_get(ctx);
+    if (!e || hipEventRecord(e, s) != hipSuccess) {
+        ctx->prof.pool.push_back(start);
+        return;
+    }
+    ctx->prof.tags.push_back(tag);
+    ctx->prof.starts.push_back(start);
+    ctx->prof.stops.push_back(e);
+}
+
+static void prof_resolve(bem_ctx* ctx)
+{
+    auto& p = ctx->prof;
+    for (size_t i = 0; i < p.tags.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.stops[i]) == hipSuccess && hipEventElapsedTime(&ms, p.starts[i], p.stops[i]) == hipSuccess) {
+            p.total_ms[p.tags[i]] += ms;
+            p.launches[p.tags[i]] += 1;
+        }
+        p.pool.push_back(p.starts[i]);
+        p.pool.push_back(p.stops[i]);
+    }
+    p.tags.clear();
+    p.starts.clear();
+    p.stops.clear();
+    hipGetLastError();
+}
+
 static void release(DevBuf& b)
 {
     if (b.ptr) hipFree(b.ptr);
@@ -243,6 +298,34 @@ int bem_get_matrix(bem_ctx* ctx, int32_t which, double* out, hipStream_t stream)
 
 int32_t bem_num_elements(const bem_ctx* ctx) { return ctx ? ctx->M : 0; }
 
+int bem_profile(bem_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return BEM_EINVAL;
+    prof_resolve(ctx);
+    for (int t = 0; t < PT_COUNT; ++t) {
+        ctx->prof.total_ms[t] = 0.0;
+        ctx->prof.launches[t] = 0;
+    }
+    ctx->prof.on = enable != 0;
+    return BEM_OK;
+}
+
+int bem_profile_read(bem_ctx* ctx, int32_t tag, double* total_ms, int64_t* launches)
+{
+    if (!ctx || tag < 0 || tag >= PT_COUNT) return BEM_EINVAL;
+    prof_resolve(ctx);
+    if (total_ms) *total_ms = ctx->prof.total_ms[tag];
+    if (launches) *launches = ctx->prof.launches[tag];
+    return BEM_OK;
+}
+
+const char* bem_profile_name(int32_t tag)
+{
+    static const char* names[PT_COUNT] = {"sweep_f64", "sweep_mixed", "vjp_segments", "vjp_elements", "features",
+                                          "beta_rows", "gram_f64", "gram_mfma", "xr", "cholesky", "boundary"};
+    return (tag >= 0 && tag < PT_COUNT) ? names[tag] : "";
+}
+
 int bem_factor_info(const bem_ctx* ctx, double* sigma_n, double* shift)
 {
     if (!ctx || ctx->state < 2) return BEM_ESTATE;
@@ -260,6 +343,8 @@ void bem_destroy(bem_ctx* ctx)
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw};
     for (DevBuf* b : bufs) release(*b);
+    prof_resolve(ctx);
+    for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
     delete ctx;
 }
 

@@ -142,6 +142,7 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     hipLaunchKernelGGL(k_damp, dim3(blocks_for(P, 256), P), dim3(256), 0, s, H, P, lam, dscal, A);
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
     const int nblk = (int)((P + NB - 1) / NB);
+    ProfScope ps_(ctx, PT_CHOLESKY, s);
     for (int kb = 0; kb < nblk; ++kb) {
         hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb, dflag);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/bem.h"
 #include "seg_math.hpp"
@@ -53,6 +54,22 @@ struct DevBuf {
 
 }  // namespace bem
 
+namespace bem {
+// Kernel families timed with HIP events when profiling is on (bem_profile).
+enum ProfTag {
+    PT_SWEEP_F64 = 0, PT_SWEEP_MIXED, PT_VJP_SEGMENTS, PT_VJP_ELEMENTS, PT_FEATURES, PT_BETA_ROWS, PT_GRAM_F64,
+    PT_GRAM_MFMA, PT_XR, PT_CHOLESKY, PT_BOUNDARY, PT_COUNT
+};
+struct ProfState {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> tags;
+    std::vector<hipEvent_t> starts, stops;
+    double total_ms[PT_COUNT] = {};
+    int64_t launches[PT_COUNT] = {};
+};
+}  // namespace bem
+
 struct bem_ctx {
     bem_opts opts{};
     int M = 0;               // outer elements
@@ -61,6 +78,7 @@ struct bem_ctx {
     int device = 0;
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
+    bem::ProfState prof;
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
     // per-call workspaces
@@ -70,6 +88,18 @@ struct bem_ctx {
 namespace bem {
 
 int set_error(bem_ctx* ctx, int code, const char* fmt, ...);
+void prof_begin(bem_ctx* ctx, int tag, hipStream_t s, hipEvent_t* start);
+void prof_end(bem_ctx* ctx, int tag, hipStream_t s, hipEvent_t start);
+
+// Records HIP events around the launches of its scope when profiling is on.
+struct ProfScope {
+    bem_ctx* ctx;
+    int tag;
+    hipStream_t s;
+    hipEvent_t start = nullptr;
+    ProfScope(bem_ctx* c, int t, hipStream_t st) : ctx(c), tag(t), s(st) { prof_begin(ctx, tag, s, &start); }
+    ~ProfScope() { prof_end(ctx, tag, s, start); }
+};
 int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream);
 int check_launch(bem_ctx* ctx, const char* what);
 

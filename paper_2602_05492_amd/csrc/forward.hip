@@ -173,8 +173,11 @@ int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s)
 int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s)
 {
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
-    hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K, ctx->per_side,
-                       eps2, F);
+    {
+        ProfScope ps_(ctx, PT_BOUNDARY, s);
+        hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K, ctx->per_side,
+                           eps2, F);
+    }
     return check_launch(ctx, "boundary_rhs");
 }
 
@@ -199,8 +202,11 @@ int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const doub
 {
     if (N == 0) return BEM_OK;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
-    hipLaunchKernelGGL(k_sweep_f64, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const double*)ctx->seg64.ptr, K,
-                       (const double*)ctx->elem64.ptr, ctx->M, eps2, cbar[0], cbar[1], cbar[2], u);
+    {
+        ProfScope ps_(ctx, PT_SWEEP_F64, s);
+        hipLaunchKernelGGL(k_sweep_f64, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const double*)ctx->seg64.ptr, K,
+                           (const double*)ctx->elem64.ptr, ctx->M, eps2, cbar[0], cbar[1], cbar[2], u);
+    }
     return check_launch(ctx, "sweep_f64");
 }
 

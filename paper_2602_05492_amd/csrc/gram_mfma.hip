@@ -177,9 +177,15 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
 {
     if (n <= 0 || ntiles <= 0) return BEM_OK;
     if (gram == BEM_GRAM_BF16X3_MFMA)
-        hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, ld, W, n, tiles128, G);
+        {
+            ProfScope ps_(ctx, PT_GRAM_MFMA, s);
+            hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, ld, W, n, tiles128, G);
+        }
     else
-        hipLaunchKernelGGL(k_gram_f32, dim3(ntiles), dim3(256), 0, s, (const float*)Xhi, ld, W, n, tiles128, G);
+        {
+            ProfScope ps_(ctx, PT_GRAM_MFMA, s);
+            hipLaunchKernelGGL(k_gram_f32, dim3(ntiles), dim3(256), 0, s, (const float*)Xhi, ld, W, n, tiles128, G);
+        }
     return check_launch(ctx, "gram_mfma");
 }
 
@@ -188,9 +194,15 @@ int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int6
 {
     if (n <= 0) return BEM_OK;
     if (gram == BEM_GRAM_BF16X3_MFMA)
-        hipLaunchKernelGGL(k_xr<true>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
+        {
+            ProfScope ps_(ctx, PT_XR, s);
+            hipLaunchKernelGGL(k_xr<true>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
+        }
     else
-        hipLaunchKernelGGL(k_xr<false>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
+        {
+            ProfScope ps_(ctx, PT_XR, s);
+            hipLaunchKernelGGL(k_xr<false>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
+        }
     return check_launch(ctx, "xr");
 }
 

@@ -311,20 +311,32 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const dim3 grid(blocks_for(npts, 256), H);
     if (H > 0) {
         if (mixed)
-            hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+            {
+                ProfScope ps_(ctx, PT_FEATURES, s);
+                hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                                   (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+            }
         else
-            hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+            {
+                ProfScope ps_(ctx, PT_FEATURES, s);
+                hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                                   (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+            }
     }
     if (with_beta) {
         const dim3 gb(blocks_for(npts, 256), ctx->M);
         if (mixed)
-            hipLaunchKernelGGL((k_beta_rows<true, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+            {
+                ProfScope ps_(ctx, PT_BETA_ROWS, s);
+                hipLaunchKernelGGL((k_beta_rows<true, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+            }
         else
-            hipLaunchKernelGGL((k_beta_rows<false, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+            {
+                ProfScope ps_(ctx, PT_BETA_ROWS, s);
+                hipLaunchKernelGGL((k_beta_rows<false, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+            }
     }
     return check_launch(ctx, "features");
 }
@@ -424,8 +436,11 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         if (gram == BEM_GRAM_FP64) {
             double* Xt = (double*)ctx->tmp0.ptr;
             if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s))) return rc;
-            if ((rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles)))
-                return rc;
+            {
+                ProfScope ps_(ctx, PT_GRAM_F64, s);
+                rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
+            }
+            if (rc) return rc;
             if ((rc = gemm_f64(ctx, (int)W, 3, (int)n, 1.0, Xt, T, false, r64 + 3 * t0, 3, false, 1.0, R, 3, s, nullptr, 0)))
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {

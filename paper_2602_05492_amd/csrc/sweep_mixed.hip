@@ -71,9 +71,12 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     if (N == 0) return BEM_OK;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     const double nf = 2.0 * ctx->opts.near_factor;
-    hipLaunchKernelGGL(k_sweep_mixed, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
-                       (const double*)ctx->seg64.ptr, K, (const float*)ctx->elem32.ptr, (const double*)ctx->elem64.ptr,
-                       ctx->M, (float)eps2, eps2, (float)(nf * nf), cbar[0], cbar[1], cbar[2], u);
+    {
+        ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
+        hipLaunchKernelGGL(k_sweep_mixed, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
+                           (const double*)ctx->seg64.ptr, K, (const float*)ctx->elem32.ptr, (const double*)ctx->elem64.ptr,
+                           ctx->M, (float)eps2, eps2, (float)(nf * nf), cbar[0], cbar[1], cbar[2], u);
+    }
     return check_launch(ctx, "sweep_mixed");
 }
 

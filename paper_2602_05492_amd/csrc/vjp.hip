@@ -286,27 +286,42 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const float* seg32 = (const float*)ctx->seg32.ptr;
     if (N > 0) {
         if (!mixed)
-            hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ns), dim3(256), 0, s, x,
-                               (const double*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+            {
+                ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
+                hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ns), dim3(256), 0, s, x,
+                                   (const double*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+            }
         else
-            hipLaunchKernelGGL((k_vjp_segments<true, float>), dim3(kgroups, ns), dim3(256), 0, s, x,
-                               (const float*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+            {
+                ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
+                hipLaunchKernelGGL((k_vjp_segments<true, float>), dim3(kgroups, ns), dim3(256), 0, s, x,
+                                   (const float*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
+            }
         if (!mixed)
-            hipLaunchKernelGGL((k_vjp_elements<false, double>), dim3(mgroups, ne), dim3(256), 0, s, x,
-                               (const double*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, M, near2, epart);
+            {
+                ProfScope ps_(ctx, PT_VJP_ELEMENTS, s);
+                hipLaunchKernelGGL((k_vjp_elements<false, double>), dim3(mgroups, ne), dim3(256), 0, s, x,
+                                   (const double*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
+                                   (const float*)ctx->elem32.ptr, M, near2, epart);
+            }
         else
-            hipLaunchKernelGGL((k_vjp_elements<true, float>), dim3(mgroups, ne), dim3(256), 0, s, x,
-                               (const float*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, M, near2, epart);
+            {
+                ProfScope ps_(ctx, PT_VJP_ELEMENTS, s);
+                hipLaunchKernelGGL((k_vjp_elements<true, float>), dim3(mgroups, ne), dim3(256), 0, s, x,
+                                   (const float*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
+                                   (const float*)ctx->elem32.ptr, M, near2, epart);
+            }
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)M * 3, 256)), dim3(256), 0, s, epart, ne,
                            (int64_t)M * 3, psi);
         if ((rc = check_launch(ctx, "vjp sweeps"))) return rc;
         if ((rc = launch_boundary_solve(ctx, psi, mu, true, s))) return rc;
         hipLaunchKernelGGL(k_gauss_cotangent, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, mu, M, ctx->per_side, gx, gc);
-        hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ng), dim3(256), 0, s, gx, gc,
-                           (int64_t)3 * M, chunk_g, seg64, seg32, K, eps2, (float)eps2, near2,
-                           part + (size_t)ns * K * kV);
+        {
+            ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
+            hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ng), dim3(256), 0, s, gx, gc,
+                               (int64_t)3 * M, chunk_g, seg64, seg32, K, eps2, (float)eps2, near2,
+                               part + (size_t)ns * K * kV);
+        }
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, ns + ng,
                            (int64_t)K * kV, (double*)ctx->red.ptr);
     } else {
