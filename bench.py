@@ -80,7 +80,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--gram", default="fp32_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
+    ap.add_argument("--gram", default="bf16x3_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
     ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     args = ap.parse_args()

@@ -141,6 +141,114 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
     epilogue(acc, rbase, cbase, W, G);
 }
 
+// Split-bfloat16 Gram with LDS staging: a block of 8 wavefronts owns a 256x256
+// output tile (wavefront w: rows 64*(w/2).., cols 128*(w%2).., 2x4 MFMA tiles of
+// 32x32).  Each 32-sample stage of the four operand slabs (A hi/lo, B hi/lo,
+// 256 rows x 32 samples) is loaded into registers while the previous stage is
+// multiplied out of LDS, then stored to LDS (rows padded to 40 bf16 so the
+// 16-byte operand reads of 16 consecutive rows hit distinct banks).
+constexpr int G2_T = 256, G2_BK = 32, G2_LD = G2_BK + 8;
+
+__global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl,
+                                                         int ld, int W, int n, const int* __restrict__ tiles,
+                                                         double* __restrict__ G)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sm[4][G2_T * G2_LD];   // A hi, A lo, B hi, B lo
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 31, lk = lane >> 5;
+    const int row0 = tiles[2 * blockIdx.x] * G2_T;
+    const int col0 = tiles[2 * blockIdx.x + 1] * G2_T;
+    const int wr = wave >> 1, wc = wave & 1;
+    // global -> register staging: thread owns 16-byte chunk (tid & 3) of rows tid/4 and tid/4 + 128
+    const int c8 = (tid & 3) * 8;
+    const int r_a = tid >> 2;
+    int goff[2][2];            // [A/B][p] element offset of the chunk (row * ld + c8), -1 when the row is outside
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int ra = row0 + r_a + 128 * p, rb = col0 + r_a + 128 * p;
+        goff[0][p] = ra < W ? ra * ld + c8 : -1;
+        goff[1][p] = rb < W ? rb * ld + c8 : -1;
+    }
+    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+    u16x8 stage[2][2][2];      // [A/B][hi/lo][p]
+#define G2_LOAD_STAGE(K0)                                                                     \
+    {                                                                                         \
+        const int k0_ = (K0);                                                                 \
+        const bool full_ = k0_ + G2_BK <= n;                                                  \
+        _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                      \
+        _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                       \
+            const int o = goff[ab][p];                                                        \
+            if (o < 0) {                                                                      \
+                stage[ab][0][p] = z8;                                                         \
+                stage[ab][1][p] = z8;                                                         \
+            } else if (full_) {                                                               \
+                stage[ab][0][p] = *(const u16x8*)(Xh + o + k0_);                              \
+                stage[ab][1][p] = *(const u16x8*)(Xl + o + k0_);                              \
+            } else {                                                                          \
+                _Pragma("unroll") for (int e = 0; e < 8; ++e) {                               \
+                    const bool in = k0_ + c8 + e < n;                                         \
+                    stage[ab][0][p][e] = in ? Xh[o + k0_ + e] : (uint16_t)0;                  \
+                    stage[ab][1][p][e] = in ? Xl[o + k0_ + e] : (uint16_t)0;                  \
+                }                                                                             \
+            }                                                                                 \
+        }                                                                                     \
+    }
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 4; ++nj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
+    G2_LOAD_STAGE(0)
+    for (int k0 = 0; k0 < n; k0 += G2_BK) {
+        __syncthreads();                                  // previous stage fully consumed
+#pragma unroll
+        for (int ab = 0; ab < 2; ++ab)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    *(u16x8*)&sm[2 * ab + hl][(r_a + 128 * p) * G2_LD + c8] = stage[ab][hl][p];
+        __syncthreads();
+        if (k0 + G2_BK < n) G2_LOAD_STAGE(k0 + G2_BK)    // in flight during the MFMAs below
+#pragma unroll
+        for (int ks = 0; ks < G2_BK; ks += 16) {
+            const int kc = ks + 8 * lk;
+            bf16x8 ah[2], al[2];
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) {
+                const int r = wr * 64 + mi * 32 + li;
+                ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[0][r * G2_LD + kc]);
+                al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[1][r * G2_LD + kc]);
+            }
+#pragma unroll
+            for (int nj = 0; nj < 4; ++nj) {
+                const int r = wc * 128 + nj * 32 + li;
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[2][r * G2_LD + kc]);
+                const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[3][r * G2_LD + kc]);
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi) {
+                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0);
+                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0);
+                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh, acc[mi][nj], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 4; ++nj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = row0 + wr * 64 + 32 * mi + 8 * (r >> 2) + 4 * lk + (r & 3);
+                const int j = col0 + wc * 128 + 32 * nj + li;
+                if (i < W && j < W) G[(int64_t)i * W + j] += (double)acc[mi][nj][r];
+            }
+}
+
 // R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; X float or bf16 hi + lo)
 template <bool Bf16>
 __global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const uint16_t* __restrict__ Xlo, int64_t ld,
@@ -179,7 +287,9 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
     if (gram == BEM_GRAM_BF16X3_MFMA)
         {
             ProfScope ps_(ctx, PT_GRAM_MFMA, s);
-            hipLaunchKernelGGL(k_gram_bf16x3, dim3(ntiles), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, ld, W, n, tiles128, G);
+            // element offsets inside one operand array are 32-bit (W * ld < 2^31 is checked by the caller)
+            hipLaunchKernelGGL(k_gram_bf16x3_lds, dim3(ntiles), dim3(512), 0, s, (const uint16_t*)Xhi, Xlo, (int)ld, W,
+                               (int)n, tiles128, G);
         }
     else
         {

@@ -402,11 +402,16 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     double* Z = nullptr;
     if ((rc = boundary_derivatives(ctx, H, s, &Z))) return rc;
     // sample tiles
-    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : 16384;
+    // sample tile: large for the float64 Gram; for the MFMA Grams small enough that the tile of
+    // feature rows (W x T, 4 bytes per entry) stays resident in the last-level cache while every
+    // output tile re-reads it
+    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : (gram == BEM_GRAM_FP64 ? 16384 : 8192);
     const size_t elem = gram == BEM_GRAM_FP64 ? 8 : 4;
     while (T > 1024 && (size_t)W * T * elem > ((size_t)3 << 30)) T /= 2;
     if (T > N) T = N > 0 ? N : 1;
     T = (T + 63) / 64 * 64;
+    if (gram == BEM_GRAM_BF16X3_MFMA)
+        while (T > 64 && W * T >= ((int64_t)1 << 31)) T = (T / 2 + 63) / 64 * 64;   // 32-bit offsets in the Gram
     // tmp0: feature tile; tmp1: G [W][W] + R [W][3]; tmp2: residual in f64
     if ((rc = ensure(ctx, ctx->tmp0, (size_t)W * T * elem, s))) return rc;
     if ((rc = ensure(ctx, ctx->tmp1, ((size_t)W * W + (size_t)W * 3) * sizeof(double), s))) return rc;
@@ -421,7 +426,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         else
             hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)resid, 3 * N, r64);
     }
-    const int ts = gram == BEM_GRAM_FP64 ? 64 : 128;
+    const int ts = gram == BEM_GRAM_FP64 ? 64 : (gram == BEM_GRAM_FP32_MFMA ? 128 : 256);
     const std::vector<int> tiles = gram_tiles(H, (int)W, ts);
     const int ntiles = (int)tiles.size() / 2;
     if ((rc = ensure(ctx, ctx->tmp5, tiles.size() * sizeof(int) + 256, s))) return rc;
