@@ -193,9 +193,9 @@ int bem_factor_info(const bem_ctx* ctx, double* sigma_n, double* shift);
  * clears the accumulators and switches recording on (enable != 0) or off.
  * bem_profile_read waits for the recorded events and returns the total time in
  * milliseconds and the number of launches of one kernel family (tag in
- * [0, 11): 0 sweep_f64, 1 sweep_mixed, 2 vjp_segments, 3 vjp_elements,
+ * [0, 12): 0 sweep_f64, 1 sweep_mixed, 2 vjp_segments, 3 vjp_elements,
  * 4 features, 5 beta_rows, 6 gram_f64, 7 gram_mfma, 8 xr, 9 cholesky,
- * 10 boundary); bem_profile_name gives the family's name (static string,
+ * 10 boundary, 11 near_pairs); bem_profile_name gives the family's name (static string,
  * "" for a bad tag).  Errors: EINVAL (null context or bad tag). */
 int bem_profile(bem_ctx* ctx, int32_t enable);
 int bem_profile_read(bem_ctx* ctx, int32_t tag, double* total_ms, int64_t* launches);

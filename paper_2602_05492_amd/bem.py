@@ -169,7 +169,7 @@ class Context:
     def profile_read(self) -> dict:
         """{family: (total_ms, launches)} of the kernels recorded since profile(True)."""
         out = {}
-        for t in range(11):
+        for t in range(12):
             ms = ctypes.c_double()
             n = ctypes.c_int64()
             self._check(lib().bem_profile_read(self._h, t, ctypes.byref(ms), ctypes.byref(n)))

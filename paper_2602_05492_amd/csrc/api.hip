@@ -322,7 +322,8 @@ int bem_profile_read(bem_ctx* ctx, int32_t tag, double* total_ms, int64_t* launc
 const char* bem_profile_name(int32_t tag)
 {
     static const char* names[PT_COUNT] = {"sweep_f64", "sweep_mixed", "vjp_segments", "vjp_elements", "features",
-                                          "beta_rows", "gram_f64", "gram_mfma", "xr", "cholesky", "boundary"};
+                                          "beta_rows", "gram_f64", "gram_mfma", "xr", "cholesky", "boundary",
+                                          "near_pairs"};
     return (tag >= 0 && tag < PT_COUNT) ? names[tag] : "";
 }
 
@@ -341,7 +342,8 @@ void bem_destroy(bem_ctx* ctx)
     hipDeviceSynchronize();
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
-                      &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw};
+                      &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf};
     for (DevBuf* b : bufs) release(*b);
     prof_resolve(ctx);
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);

@@ -19,6 +19,8 @@ struct DevF64 {
     __device__ static double log(double x) { return ::log(x); }
     __device__ static double log1p(double x) { return ::log1p(x); }
     __device__ static double sqrt(double x) { return ::sqrt(x); }
+    __device__ static double rcp(double x) { return 1.0 / x; }
+    __device__ static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
     __device__ static double atan2(double y, double x) { return ::atan2(y, x); }
 };
 
@@ -30,21 +32,22 @@ struct DevF64 {
 constexpr double kDegenerateLength = 1e-12;
 
 // ---- layouts ----------------------------------------------------------------
-// Segment record: SegGeom (9 values) + wd_a, wd_b, wc_a, wc_b RGB (12) = 21, padded.
+// Segment record: SegGeom (9 values) + wd_a, wd_b, wc_a, wc_b RGB (12) + 1/L2 = 22, padded.
 constexpr int kSegStride = 24;
 // Element record: ax, ay, vx, vy, U0, U1, U2, pad.
 constexpr int kElemStride = 8;
+
+// density offsets inside a segment record, and the slot of 1/L2
+constexpr int kWdA = 9, kWdB = 12, kWcA = 15, kWcB = 18, kIL2 = 21;
 
 template <class T>
 __device__ inline SegGeom<T> load_geom(const T* __restrict__ s)
 {
     SegGeom<T> g;
     g.ax = s[0]; g.ay = s[1]; g.bx = s[2]; g.by = s[3];
-    g.vx = s[4]; g.vy = s[5]; g.L2 = s[6]; g.kd = s[7]; g.ks = s[8];
+    g.vx = s[4]; g.vy = s[5]; g.L2 = s[6]; g.kd = s[7]; g.ks = s[8]; g.iL2 = s[kIL2];
     return g;
 }
-// density offsets inside a segment record
-constexpr int kWdA = 9, kWdB = 12, kWcA = 15, kWcB = 18;
 
 // ---- device buffers -----------------------------------------------------------
 struct DevBuf {
@@ -58,7 +61,7 @@ namespace bem {
 // Kernel families timed with HIP events when profiling is on (bem_profile).
 enum ProfTag {
     PT_SWEEP_F64 = 0, PT_SWEEP_MIXED, PT_VJP_SEGMENTS, PT_VJP_ELEMENTS, PT_FEATURES, PT_BETA_ROWS, PT_GRAM_F64,
-    PT_GRAM_MFMA, PT_XR, PT_CHOLESKY, PT_BOUNDARY, PT_COUNT
+    PT_GRAM_MFMA, PT_XR, PT_CHOLESKY, PT_BOUNDARY, PT_NEAR, PT_COUNT
 };
 struct ProfState {
     bool on = false;
@@ -82,7 +85,7 @@ struct bem_ctx {
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf;
 };
 
 namespace bem {
@@ -116,6 +119,8 @@ int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpo
 int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
 int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s);
+struct NearList;
+int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
 // vjp.hip
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
             double* grad, hipStream_t s);
@@ -146,18 +151,42 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
 }  // namespace bem
 
 namespace bem {
-// float32 policy of the mixed sweeps: hardware log2 and square root;
-// log1p(z) = log(w) z / (w - 1) with w = 1 + z rounded (Goldberg 1991, the
-// rounding error of w cancels between the two factors), exact z when w == 1.
+// float32 policy of the mixed sweeps: hardware log2, reciprocal, reciprocal
+// square root and square root (about 1 ulp); log1p(z) = log(w) z / (w - 1) with
+// w = 1 + z rounded (Goldberg 1991: the rounding error of w cancels between the
+// two factors), z itself when w == 1; atan2 by reduction to [0, 1] and a
+// degree-7 odd minimax polynomial in z (relative error 1e-7; coefficients from
+// csrc/fit_atan.py), reflected about pi/4 and pi/2.
 struct DevF32 {
-    __device__ static float log(float x) { return __logf(x); }
+    // v_log_f32 (log2, ~1 ulp) times ln 2; arguments here are normal numbers (>= eps^2 or near 1)
+    __device__ static float log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    __device__ static float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     __device__ static float log1p(float z)
     {
         const float w = 1.0f + z;
         const float d = w - 1.0f;
-        return d == 0.0f ? z : __logf(w) * (z / d);
+        return d == 0.0f ? z : (__builtin_amdgcn_logf(w) * 0.693147180559945309f) * (z * __builtin_amdgcn_rcpf(d));
     }
-    __device__ static float sqrt(float x) { return __builtin_sqrtf(x); }
-    __device__ static float atan2(float y, float x) { return atan2f(y, x); }
+    __device__ static float atan2(float y, float x)
+    {
+        const float ax = fabsf(x), ay = fabsf(y);
+        const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+        const float z = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+        const float s = z * z;
+        float p = -4.693678257e-03f;
+        p = p * s + 2.425393176e-02f;
+        p = p * s - 5.948871678e-02f;
+        p = p * s + 9.914472679e-02f;
+        p = p * s - 1.401955544e-01f;
+        p = p * s + 1.996973974e-01f;
+        p = p * s - 3.333199223e-01f;
+        p = p * s + 9.999999014e-01f;
+        float r = z * p;
+        r = ay > ax ? 1.57079632679489662f - r : r;
+        r = x < 0.0f ? 3.14159265358979324f - r : r;
+        return __builtin_copysignf(r, y);
+    }
 };
 }  // namespace bem

@@ -47,10 +47,18 @@ __global__ void k_expand(const double* __restrict__ theta, int H, int S, double*
         rec[kWcA + c] = (1.0 - ta) * th[14 + c] + ta * th[17 + c];
         rec[kWcB + c] = (1.0 - tb) * th[14 + c] + tb * th[17 + c];
     }
-    rec[21] = rec[22] = rec[23] = 0.0;
+    rec[kIL2] = live ? 1.0 / L2 : 0.0;
+    rec[22] = rec[23] = 0.0;
     double* o = seg64 + (size_t)k * kSegStride;
     float* o32 = seg32 + (size_t)k * kSegStride;
     for (int c = 0; c < kSegStride; ++c) { o[c] = rec[c]; o32[c] = (float)rec[c]; }
+    if (!live) {
+        // float32 record of a degenerate segment: a point far outside the domain with zero
+        // weights, whose moments evaluate to exactly 0 without special cases in the sweeps
+        o32[0] = o32[2] = 1.0e6f;
+        o32[1] = o32[3] = 1.0e6f;
+        o32[4] = o32[5] = 0.0f;
+    }
 }
 
 __device__ inline double block_reduce(double v, double* red)

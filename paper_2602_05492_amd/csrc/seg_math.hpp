@@ -31,7 +31,9 @@
 // line.
 //
 // Everything is a template over the arithmetic type T and a math policy M
-// supplying log, log1p, sqrt and atan2 for T, so the same code runs on gfx950 and in
+// supplying log, log1p, rcp, rsqrt and atan2 for T (atan2 is only called with
+// a non-negative first argument: Q >= 0, and the subtended angle of an outer
+// element seen from inside the domain), so the same code runs on gfx950 and in
 // host-side unit tests.
 #pragma once
 
@@ -59,6 +61,7 @@ struct SegGeom {
     T L2;               // |b - a|^2
     T kd;               // 1 / (4 pi L2)
     T ks;               // 1 / (8 pi L2^1.5)
+    T iL2;              // 1 / L2 (0 for a degenerate segment)
 };
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
@@ -71,11 +74,11 @@ BEM_HD inline void log_pair(T R0, T R1, T dR, T& l0, T& ell)
 {
     if (!Guard) {
         l0 = M::log(R0);
-        ell = M::log1p(dR / R0);
+        ell = M::log1p(dR * M::rcp(R0));
         return;
     }
     l0 = R0 > T(0) ? M::log(R0) : T(0);
-    if (R0 > T(0) && R1 > T(0)) ell = M::log1p(dR / R0);
+    if (R0 > T(0) && R1 > T(0)) ell = M::log1p(dR * M::rcp(R0));
     else if (R0 > T(0)) ell = -l0;
     else ell = R1 > T(0) ? M::log(R1) : T(0);
 }
@@ -98,9 +101,10 @@ BEM_HD inline Moments<T> seg_moments(const SegGeom<T>& g, T X, T Y, T eps2)
     T l0, ell;
     log_pair<T, M, Guard>(R0, R1, dR, l0, ell);
     const T Q2 = C * C + eps2 * g.L2;
-    const T Q = M::sqrt(Q2);
+    const T iQ = Q2 > T(0) ? M::rsqrt(Q2) : T(0);     // eps = 0 on the segment line: principal value 0
+    const T Q = Q2 * iQ;
     const T Dl = M::atan2(Q, P + eps2);
-    const T gq = (!Guard || Q2 > T(0)) ? Dl / Q : T(0);
+    const T gq = Dl * iQ;
     const T kd = C * g.kd;
     Moments<T> m;
     m.db = kd * (ell - T(2) * D0 * gq);
@@ -135,16 +139,16 @@ BEM_HD inline PairState<T> pair_forward(const SegGeom<T>& g, T X, T Y, T eps2)
     p.dR = T(2) * p.D0 + g.L2;
     log_pair<T, M, Guard>(p.R0, p.R1, p.dR, p.l0, p.ell);
     const T Q2 = p.C * p.C + eps2 * g.L2;
-    p.Q = M::sqrt(Q2);
+    p.iQ = Q2 > T(0) ? M::rsqrt(Q2) : T(0);
+    p.Q = Q2 * p.iQ;
     p.Pe = P + eps2;
     p.Dl = M::atan2(p.Q, p.Pe);
-    p.iQ = (!Guard || Q2 > T(0)) ? T(1) / p.Q : T(0);
     p.gq = p.Dl * p.iQ;
     p.kdC = p.C * g.kd;
     p.S0 = g.L2 * p.l0 + p.D1 * p.ell - T(2) * g.L2 + T(2) * p.Q * p.Dl;
     p.S1 = p.dR * (p.l0 - T(1)) + p.R1 * p.ell;
-    p.iR0 = (!Guard || p.R0 > T(0)) ? T(1) / p.R0 : T(0);
-    p.iR1 = (!Guard || p.R1 > T(0)) ? T(1) / p.R1 : T(0);
+    p.iR0 = (!Guard || p.R0 > T(0)) ? M::rcp(p.R0) : T(0);
+    p.iR1 = (!Guard || p.R1 > T(0)) ? M::rcp(p.R1) : T(0);
     return p;
 }
 
@@ -164,7 +168,7 @@ BEM_HD inline Moments<T> pair_moments(const SegGeom<T>& g, const PairState<T>& p
 template <class T>
 BEM_HD inline Grad4<T> pair_backward(const SegGeom<T>& g, const PairState<T>& p, T eps2, T wa, T wb, T sa, T sb)
 {
-    const T iL2 = T(1) / g.L2;
+    const T iL2 = g.iL2;
     // double layer: F_d = (C kd0) Ad,  kd0 = 1/(4 pi L2)
     const T Ad = (wb - wa) * p.ell + T(2) * p.gq * (wa * p.D1 - wb * p.D0);
     // single layer: F_s = ks As,  ks = 1/(8 pi L2^1.5)

@@ -24,4 +24,48 @@ __device__ inline void square_element(int i, int m, double& ax, double& ay, doub
     bx = cx0 + t1 * dx; by = cy0 + t1 * dy;
 }
 
+// ---- near-singular pairs of the mixed-precision sweeps ---------------------------
+// A pair is near when both end points of the segment lie within 2*near_factor*L
+// of the sample (this contains every sample closer than near_factor*L to the
+// segment).  The test is written with explicit roundings so that every kernel
+// that classifies a pair takes the same decision.
+__device__ inline bool near_segment(float ax, float ay, float bx, float by, float L2, float X, float Y, float near2)
+{
+    const float dx = __fsub_rn(ax, X), dy = __fsub_rn(ay, Y), ex = __fsub_rn(bx, X), ey = __fsub_rn(by, Y);
+    const float lim = __fmul_rn(near2, L2);
+    const float dd = __fmaf_rn(dx, dx, __fmul_rn(dy, dy));
+    const float ee = __fmaf_rn(ex, ex, __fmul_rn(ey, ey));
+    return (dd < lim) & (ee < lim);
+}
+// Outer element stored as start point a and direction v.
+__device__ inline bool near_element(float ax, float ay, float vx, float vy, float X, float Y, float near2)
+{
+    const float dx = __fsub_rn(ax, X), dy = __fsub_rn(ay, Y);
+    const float ex = __fadd_rn(dx, vx), ey = __fadd_rn(dy, vy);
+    const float lim = __fmul_rn(near2, __fmaf_rn(vx, vx, __fmul_rn(vy, vy)));
+    const float dd = __fmaf_rn(dx, dx, __fmul_rn(dy, dy));
+    const float ee = __fmaf_rn(ex, ex, __fmul_rn(ey, ey));
+    return (dd < lim) & (ee < lim);
+}
+
+struct NearPair {
+    int32_t sample;   // index within the launch's sample range
+    int32_t seg;      // < K: handle segment, else outer element seg - K
+};
+
+// Each wavefront of 64 consecutive samples owns kWaveSlots list slots; entries
+// are appended in increasing segment order, so the entries of one handle form a
+// contiguous run of a slice.
+constexpr int kNearPerSample = 16;
+constexpr int kWaveSlots = kNearPerSample * 64;
+
+// Workspace of one classification: slices, per-wavefront counts, per-sample
+// overflow flags.
+struct NearList {
+    NearPair* list = nullptr;
+    int* count = nullptr;
+    uint8_t* flag = nullptr;
+    int64_t nwaves = 0;
+};
+
 }  // namespace bem

@@ -1,24 +1,168 @@
 // sweep_mixed.hip - mixed-precision forward sweep (Sec. 3.1.3 evaluation of
-// u(x) at every sample).  Far pairs run in float32 from the float32 copies of
-// the segment and element tables; a pair whose two end points both lie within
-// 2*near_factor*L of the sample (a set containing every sample closer than
-// near_factor*L to the segment) is evaluated in float64 from the float64
-// tables and the float64 sample.  Far and near sums are kept apart and added
-// in float64 at the end.
+// u(x) at every sample).
+//
+// Far pairs run in float32 from the float32 copies of the segment and element
+// tables.  A pair whose two end points both lie within 2*near_factor*L of the
+// sample (a set containing every sample closer than near_factor*L to the
+// segment) is not evaluated there: the wavefront appends (sample, segment) to its
+// own slice of a list, and a second kernel evaluates the listed
+// pairs in float64 from the float64 tables and the float64 sample, adding into
+// float64 per-sample sums.  Keeping float64 code out of the float32 sweep keeps
+// its register count (and occupancy) at that of the float32 arithmetic.
+// Should a wavefront's slice overflow, the samples whose pairs did not fit are
+// flagged and recomputed by a sweep that evaluates near pairs inline.
 #include "common.hpp"
+#include "sweep_common.hpp"
 
 namespace bem {
 
 namespace {
 
-__global__ void __launch_bounds__(256) k_sweep_mixed(const double* __restrict__ x, int64_t N,
-                                                     const float* __restrict__ seg32, const double* __restrict__ seg64,
-                                                     int K, const float* __restrict__ el32, const double* __restrict__ el64,
-                                                     int M, float eps2f, double eps2, float near2, double c0, double c1,
-                                                     double c2, float* __restrict__ u)
+
+// Appending needs no atomics: each wavefront owns a slice and counts its entries
+// in a wave-uniform register.
+
+__device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearPair* __restrict__ slice, int& used,
+                                   bool& overflow)
+{
+    const uint64_t mask = __ballot(near);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    if (near) {
+        const int slot = used + __popcll(mask & ((1ull << lane) - 1ull));
+        if (slot < kWaveSlots) slice[slot] = NearPair{sample, seg};
+        else overflow = true;
+    }
+    used += __popcll(mask);
+}
+
+// The float32 record of a degenerate segment evaluates to exactly zero and is
+// never near (its L2 is 0), so the segment loop needs no branch for it.
+__global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x, int64_t N,
+                                                   const float* __restrict__ seg32, int K,
+                                                   const float* __restrict__ el32, int M, float eps2f, float near2,
+                                                   float* __restrict__ u, NearPair* __restrict__ list,
+                                                   int* __restrict__ wave_count, uint8_t* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t wave = i >> 6;
+    NearPair* slice = list + wave * kWaveSlots;
+    const bool live = i < N;                       // the tail wave keeps its idle lanes for the ballots
+    const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    bool overflow = false;
+    int used = 0;
+    for (int k = 0; k < K; ++k) {
+        const float* s = seg32 + (size_t)k * kSegStride;
+        const SegGeom<float> g = load_geom(s);
+        float w[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
+        const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
+        append_near(near, (int32_t)i, k, slice, used, overflow);
+        const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
+        const float on = near ? 0.0f : 1.0f;
+        f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
+        f1 += on * (m.da * w[1] + m.db * w[4] + m.sa * w[7] + m.sb * w[10]);
+        f2 += on * (m.da * w[2] + m.db * w[5] + m.sa * w[8] + m.sb * w[11]);
+    }
+    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    for (int j = 0; j < M; ++j) {
+        const float* e = el32 + (size_t)j * kElemStride;
+        const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
+        append_near(near, (int32_t)i, K + j, slice, used, overflow);
+        const float beta = near ? 0.0f : element_beta<float, DevF32>(e[0], e[1], e[2], e[3], Xf, Yf);
+        b0 += beta * e[4]; b1 += beta * e[5]; b2 += beta * e[6];
+    }
+    if ((threadIdx.x & 63) == 0) wave_count[wave] = used < kWaveSlots ? used : kWaveSlots;
+    if (!live) return;
+    u[3 * i + 0] = b0 + f0;
+    u[3 * i + 1] = b1 + f1;
+    u[3 * i + 2] = b2 + f2;
+    flag[i] = overflow ? 1 : 0;
+}
+
+// Near-pair classification only (for the adjoint and the J tiles): the same
+// wavefront slices and predicate as the float32 forward sweep.
+__global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, int64_t N,
+                                                  const float* __restrict__ seg32, int K,
+                                                  const float* __restrict__ el32, int M, float near2,
+                                                  NearPair* __restrict__ list, int* __restrict__ wave_count,
+                                                  uint8_t* __restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t wave = i >> 6;
+    NearPair* slice = list + wave * kWaveSlots;
+    const bool live = i < N;
+    const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
+    bool overflow = false;
+    int used = 0;
+    for (int k = 0; k < K; ++k) {
+        const float* s = seg32 + (size_t)k * kSegStride;
+        const bool near = live & near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2);
+        append_near(near, (int32_t)i, k, slice, used, overflow);
+    }
+    for (int j = 0; j < M; ++j) {
+        const float* e = el32 + (size_t)j * kElemStride;
+        const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
+        append_near(near, (int32_t)i, K + j, slice, used, overflow);
+    }
+    if ((threadIdx.x & 63) == 0) wave_count[wave] = used < kWaveSlots ? used : kWaveSlots;
+    if (live) flag[i] = overflow ? 1 : 0;
+}
+
+// Listed near pairs in float64, added into acc[3 * sample + c]; thread per slot.
+__global__ void __launch_bounds__(256) k_near_pairs(const NearPair* __restrict__ list,
+                                                    const int* __restrict__ wave_count, int64_t nslots,
+                                                    const double* __restrict__ x, const double* __restrict__ seg64,
+                                                    int K, const double* __restrict__ el64, double eps2,
+                                                    double* __restrict__ acc)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    if ((int)(t % kWaveSlots) >= wave_count[t / kWaveSlots]) return;
+    const NearPair p = list[t];
+    const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
+    double v0, v1, v2;
+    if (p.seg < K) {
+        const double* s = seg64 + (size_t)p.seg * kSegStride;
+        const SegGeom<double> g = load_geom(s);
+        const Moments<double> m = seg_moments<double, DevF64>(g, X, Y, eps2);
+        v0 = m.da * s[kWdA + 0] + m.db * s[kWdB + 0] + m.sa * s[kWcA + 0] + m.sb * s[kWcB + 0];
+        v1 = m.da * s[kWdA + 1] + m.db * s[kWdB + 1] + m.sa * s[kWcA + 1] + m.sb * s[kWcB + 1];
+        v2 = m.da * s[kWdA + 2] + m.db * s[kWdB + 2] + m.sa * s[kWcA + 2] + m.sb * s[kWcB + 2];
+    } else {
+        const double* e = el64 + (size_t)(p.seg - K) * kElemStride;
+        const double beta = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+        v0 = beta * e[4]; v1 = beta * e[5]; v2 = beta * e[6];
+    }
+    atomicAdd(acc + 3 * (int64_t)p.sample + 0, v0);
+    atomicAdd(acc + 3 * (int64_t)p.sample + 1, v1);
+    atomicAdd(acc + 3 * (int64_t)p.sample + 2, v2);
+}
+
+__global__ void k_combine(float* __restrict__ u, const double* __restrict__ acc, int64_t N, double c0, double c1,
+                          double c2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    u[3 * i + 0] = (float)(c0 + ((double)u[3 * i + 0] + acc[3 * i + 0]));
+    u[3 * i + 1] = (float)(c1 + ((double)u[3 * i + 1] + acc[3 * i + 1]));
+    u[3 * i + 2] = (float)(c2 + ((double)u[3 * i + 2] + acc[3 * i + 2]));
+}
+
+// Whole-sample mixed evaluation with near pairs inline, for flagged samples only
+// (the list overflowed for them).
+__global__ void __launch_bounds__(256) k_sweep_inline(const double* __restrict__ x, int64_t N,
+                                                      const uint8_t* __restrict__ flag,
+                                                      const float* __restrict__ seg32, const double* __restrict__ seg64,
+                                                      int K, const float* __restrict__ el32,
+                                                      const double* __restrict__ el64, int M, float eps2f, double eps2,
+                                                      float near2, double c0, double c1, double c2,
+                                                      float* __restrict__ u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || !flag[i]) return;
     const double X = x[2 * i], Y = x[2 * i + 1];
     const float Xf = (float)X, Yf = (float)Y;
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
@@ -26,11 +170,7 @@ __global__ void __launch_bounds__(256) k_sweep_mixed(const double* __restrict__ 
     for (int k = 0; k < K; ++k) {
         const float* s = seg32 + (size_t)k * kSegStride;
         const SegGeom<float> g = load_geom(s);
-        if (g.L2 == 0.0f) continue;                    // degenerate segment (wave-uniform branch)
-        const float dx = g.ax - Xf, dy = g.ay - Yf, ex = g.bx - Xf, ey = g.by - Yf;
-        const float lim = near2 * g.L2;
-        const bool near = (dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim);
-        if (near) {
+        if (near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2)) {
             const double* s64 = seg64 + (size_t)k * kSegStride;
             const SegGeom<double> g64 = load_geom(s64);
             const Moments<double> m = seg_moments<double, DevF64>(g64, X, Y, eps2);
@@ -47,10 +187,7 @@ __global__ void __launch_bounds__(256) k_sweep_mixed(const double* __restrict__ 
     float b0 = 0.f, b1 = 0.f, b2 = 0.f;
     for (int j = 0; j < M; ++j) {
         const float* e = el32 + (size_t)j * kElemStride;
-        const float dx = e[0] - Xf, dy = e[1] - Yf;
-        const float ex = dx + e[2], ey = dy + e[3];
-        const float lim = near2 * (e[2] * e[2] + e[3] * e[3]);
-        if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim)) {
+        if (near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2)) {
             const double* e64 = el64 + (size_t)j * kElemStride;
             const double beta = element_beta<double, DevF64>(e64[0], e64[1], e64[2], e64[3], X, Y);
             n0 += beta * e64[4]; n1 += beta * e64[5]; n2 += beta * e64[6];
@@ -66,17 +203,61 @@ __global__ void __launch_bounds__(256) k_sweep_mixed(const double* __restrict__ 
 
 }  // namespace
 
+// Classify the near pairs of samples x[0..N) (segments, and outer elements when M > 0) into buf.
+int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s)
+{
+    int rc;
+    const double nf = 2.0 * ctx->opts.near_factor;
+    const int64_t nwaves = N > 0 ? (int64_t)blocks_for(N, 256) * 4 : 0;
+    const size_t list_bytes = ((size_t)nwaves * kWaveSlots * sizeof(NearPair) + 255) / 256 * 256;
+    const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
+    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + (size_t)N + 256, s))) return rc;
+    char* base = (char*)buf.ptr;
+    out->list = (NearPair*)base;
+    out->count = (int*)(base + list_bytes);
+    out->flag = (uint8_t*)(base + list_bytes + cnt_bytes);
+    out->nwaves = nwaves;
+    if (N == 0) return BEM_OK;
+    ProfScope ps_(ctx, PT_NEAR, s);
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, K,
+                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), out->list, out->count, out->flag);
+    return check_launch(ctx, "classify");
+}
+
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar, float* u, hipStream_t s)
 {
     if (N == 0) return BEM_OK;
+    int rc;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     const double nf = 2.0 * ctx->opts.near_factor;
+    const float near2 = (float)(nf * nf);
+    // per-wavefront near-pair slices, their counts, float64 sums, overflow flags
+    const int64_t nwaves = (int64_t)blocks_for(N, 256) * 4;     // every launched wavefront, idle tail ones too
+    const int64_t nslots = nwaves * kWaveSlots;
+    const size_t list_bytes = (size_t)nslots * sizeof(NearPair);
+    const size_t acc_bytes = (size_t)N * 3 * sizeof(double);
+    const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
+    if ((rc = ensure(ctx, ctx->nearw, list_bytes + acc_bytes + cnt_bytes + (size_t)N + 256, s))) return rc;
+    char* base = (char*)ctx->nearw.ptr;
+    NearPair* list = (NearPair*)base;
+    double* acc = (double*)(base + list_bytes);
+    int* wave_count = (int*)(base + list_bytes + acc_bytes);
+    uint8_t* flag = (uint8_t*)(base + list_bytes + acc_bytes + cnt_bytes);
+    if ((rc = fill_f64(ctx, acc, 3 * N, 0.0, s))) return rc;
     {
         ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
-        hipLaunchKernelGGL(k_sweep_mixed, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
-                           (const double*)ctx->seg64.ptr, K, (const float*)ctx->elem32.ptr, (const double*)ctx->elem64.ptr,
-                           ctx->M, (float)eps2, eps2, (float)(nf * nf), cbar[0], cbar[1], cbar[2], u);
+        hipLaunchKernelGGL(k_sweep_far, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
+                           K, (const float*)ctx->elem32.ptr, ctx->M, (float)eps2, near2, u, list, wave_count, flag);
     }
+    {
+        ProfScope ps_(ctx, PT_NEAR, s);
+        hipLaunchKernelGGL(k_near_pairs, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, list, wave_count, nslots, x,
+                           (const double*)ctx->seg64.ptr, K, (const double*)ctx->elem64.ptr, eps2, acc);
+    }
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(N, 256)), dim3(256), 0, s, u, acc, N, cbar[0], cbar[1], cbar[2]);
+    hipLaunchKernelGGL(k_sweep_inline, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, flag,
+                       (const float*)ctx->seg32.ptr, (const double*)ctx->seg64.ptr, K, (const float*)ctx->elem32.ptr,
+                       (const double*)ctx->elem64.ptr, ctx->M, (float)eps2, eps2, near2, cbar[0], cbar[1], cbar[2], u);
     return check_launch(ctx, "sweep_mixed");
 }
 

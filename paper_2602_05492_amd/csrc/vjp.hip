@@ -76,38 +76,29 @@ __global__ void __launch_bounds__(256) k_vjp_segments(const double* __restrict__
                     add_pair(acc, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
                 }
             } else {
+                // float32 far pairs; near pairs are evaluated in float64 by k_vjp_near
+                // (listed pairs) and k_vjp_flagged (samples whose list slice overflowed)
                 const float* s32 = seg32 + (size_t)k * kSegStride;
                 const SegGeom<float> gf = load_geom(s32);
                 float wf[12];
                 for (int c = 0; c < 12; ++c) wf[c] = s32[kWdA + c];
-                const float lim = near2 * gf.L2;
                 for (int64_t s0 = n0 + wave; s0 < n1; s0 += 4 * 64) {
                     // float sums over at most 64 samples, then folded into the float64 sums
                     float af[kV];
                     for (int v = 0; v < kV; ++v) af[v] = 0.0f;
                     const int64_t s1 = s0 + 4 * 64 < n1 ? s0 + 4 * 64 : n1;
                     for (int64_t s = s0; s < s1; s += 4) {
-                        const double X = x[2 * s], Y = x[2 * s + 1];
-                        double g0, g1, g2;
-                        load_cot(gbar, s, g0, g1, g2);
-                        const float Xf = (float)X, Yf = (float)Y;
-                        const float dx = gf.ax - Xf, dy = gf.ay - Yf, ex = gf.bx - Xf, ey = gf.by - Yf;
-                        if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim)) {
-                            const double wa = g0 * w[0] + g1 * w[1] + g2 * w[2];
-                            const double wb = g0 * w[3] + g1 * w[4] + g2 * w[5];
-                            const double sa = g0 * w[6] + g1 * w[7] + g2 * w[8];
-                            const double sb = g0 * w[9] + g1 * w[10] + g2 * w[11];
-                            const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
-                            add_pair(acc, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
-                        } else {
-                            const float f0 = (float)g0, f1 = (float)g1, f2 = (float)g2;
-                            const float wa = f0 * wf[0] + f1 * wf[1] + f2 * wf[2];
-                            const float wb = f0 * wf[3] + f1 * wf[4] + f2 * wf[5];
-                            const float sa = f0 * wf[6] + f1 * wf[7] + f2 * wf[8];
-                            const float sb = f0 * wf[9] + f1 * wf[10] + f2 * wf[11];
-                            const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-                            add_pair(af, pair_backward(gf, st, eps2f, wa, wb, sa, sb), pair_moments(gf, st), f0, f1, f2);
-                        }
+                        const float Xf = (float)x[2 * s], Yf = (float)x[2 * s + 1];
+                        const float f0 = (float)gbar[3 * s], f1 = (float)gbar[3 * s + 1], f2 = (float)gbar[3 * s + 2];
+                        const bool skip = near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2);
+                        const float wa = f0 * wf[0] + f1 * wf[1] + f2 * wf[2];
+                        const float wb = f0 * wf[3] + f1 * wf[4] + f2 * wf[5];
+                        const float sa = f0 * wf[6] + f1 * wf[7] + f2 * wf[8];
+                        const float sb = f0 * wf[9] + f1 * wf[10] + f2 * wf[11];
+                        const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                        const float on = skip ? 0.0f : 1.0f;
+                        add_pair(af, pair_backward(gf, st, eps2f, on * wa, on * wb, on * sa, on * sb),
+                                 pair_moments(gf, st), on * f0, on * f1, on * f2);
                     }
                     for (int v = 0; v < kV; ++v) acc[v] += (double)af[v];
                 }
@@ -150,23 +141,14 @@ __global__ void __launch_bounds__(256) k_vjp_elements(const double* __restrict__
         } else {
             const float* ef = el32 + (size_t)j * kElemStride;
             const float fax = ef[0], fay = ef[1], fvx = ef[2], fvy = ef[3];
-            const float lim = near2 * (fvx * fvx + fvy * fvy);
             for (int64_t s0 = n0 + wave; s0 < n1; s0 += 4 * 64) {
                 float b0 = 0.f, b1 = 0.f, b2 = 0.f;
                 const int64_t s1 = s0 + 4 * 64 < n1 ? s0 + 4 * 64 : n1;
                 for (int64_t s = s0; s < s1; s += 4) {
-                    const double X = x[2 * s], Y = x[2 * s + 1];
-                    double g0, g1, g2;
-                    load_cot(gbar, s, g0, g1, g2);
-                    const float Xf = (float)X, Yf = (float)Y;
-                    const float dx = fax - Xf, dy = fay - Yf, ex = dx + fvx, ey = dy + fvy;
-                    if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim)) {
-                        const double b = element_beta<double, DevF64>(ax, ay, vx, vy, X, Y);
-                        a0 += b * g0; a1 += b * g1; a2 += b * g2;
-                    } else {
-                        const float b = element_beta<float, DevF32>(fax, fay, fvx, fvy, Xf, Yf);
-                        b0 += b * (float)g0; b1 += b * (float)g1; b2 += b * (float)g2;
-                    }
+                    const float Xf = (float)x[2 * s], Yf = (float)x[2 * s + 1];
+                    const bool skip = near_element(fax, fay, fvx, fvy, Xf, Yf, near2);
+                    const float b = skip ? 0.0f : element_beta<float, DevF32>(fax, fay, fvx, fvy, Xf, Yf);
+                    b0 += b * (float)gbar[3 * s]; b1 += b * (float)gbar[3 * s + 1]; b2 += b * (float)gbar[3 * s + 2];
                 }
                 a0 += (double)b0; a1 += (double)b1; a2 += (double)b2;
             }
@@ -179,6 +161,83 @@ __global__ void __launch_bounds__(256) k_vjp_elements(const double* __restrict__
         o[0] = ((a0 + red[0][lane][0]) + red[1][lane][0]) + red[2][lane][0];
         o[1] = ((a1 + red[0][lane][1]) + red[1][lane][1]) + red[2][lane][1];
         o[2] = ((a2 + red[0][lane][2]) + red[1][lane][2]) + red[2][lane][2];
+    }
+}
+
+// Float64 adjoint of one near (sample, segment) pair, added into segsum[seg][16].
+__device__ inline void near_segment_adjoint(const double* __restrict__ s, double X, double Y, double g0, double g1,
+                                            double g2, double eps2, double* __restrict__ o)
+{
+    const SegGeom<double> g = load_geom(s);
+    if (g.L2 == 0.0) return;
+    const double wa = g0 * s[kWdA] + g1 * s[kWdA + 1] + g2 * s[kWdA + 2];
+    const double wb = g0 * s[kWdB] + g1 * s[kWdB + 1] + g2 * s[kWdB + 2];
+    const double sa = g0 * s[kWcA] + g1 * s[kWcA + 1] + g2 * s[kWcA + 2];
+    const double sb = g0 * s[kWcB] + g1 * s[kWcB + 1] + g2 * s[kWcB + 2];
+    const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+    double a[kV];
+    for (int v = 0; v < kV; ++v) a[v] = 0.0;
+    add_pair(a, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
+    for (int v = 0; v < kV; ++v) atomicAdd(o + v, a[v]);
+}
+
+// Float64 beta of one near (sample, outer element) pair times the cotangent, added into psisum[j][3].
+__device__ inline void near_element_adjoint(const double* __restrict__ e, double X, double Y, double g0, double g1,
+                                            double g2, double* __restrict__ o)
+{
+    const double b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+    atomicAdd(o + 0, b * g0);
+    atomicAdd(o + 1, b * g1);
+    atomicAdd(o + 2, b * g2);
+}
+
+// Listed near pairs of the mixed adjoint (thread per list slot).  Pairs of flagged
+// samples are left to k_vjp_flagged, which redoes all near pairs of such a sample.
+// Results land in one extra partial row of each fixed-order reduction.
+__global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ list, const int* __restrict__ wave_count,
+                                                  const uint8_t* __restrict__ flag, int64_t nslots,
+                                                  const double* __restrict__ x, const float* __restrict__ gbar,
+                                                  const double* __restrict__ seg64, int K,
+                                                  const double* __restrict__ el64, double eps2,
+                                                  double* __restrict__ segsum, double* __restrict__ psisum)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nslots) return;
+    if ((int)(t % kWaveSlots) >= wave_count[t / kWaveSlots]) return;
+    const NearPair p = list[t];
+    const int64_t i = p.sample;
+    if (flag[i]) return;
+    const double X = x[2 * i], Y = x[2 * i + 1];
+    const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
+    if (p.seg < K)
+        near_segment_adjoint(seg64 + (size_t)p.seg * kSegStride, X, Y, g0, g1, g2, eps2, segsum + (size_t)p.seg * kV);
+    else
+        near_element_adjoint(el64 + (size_t)(p.seg - K) * kElemStride, X, Y, g0, g1, g2,
+                             psisum + 3 * (size_t)(p.seg - K));
+}
+
+// Every near pair of each flagged sample (thread per sample; flagged samples are rare).
+__global__ void __launch_bounds__(256) k_vjp_flagged(const uint8_t* __restrict__ flag, int64_t N,
+                                                     const double* __restrict__ x, const float* __restrict__ gbar,
+                                                     const float* __restrict__ seg32, const double* __restrict__ seg64,
+                                                     int K, const float* __restrict__ el32,
+                                                     const double* __restrict__ el64, int M, double eps2, float near2,
+                                                     double* __restrict__ segsum, double* __restrict__ psisum)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || !flag[i]) return;
+    const double X = x[2 * i], Y = x[2 * i + 1];
+    const float Xf = (float)X, Yf = (float)Y;
+    const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
+    for (int k = 0; k < K; ++k) {
+        const float* s = seg32 + (size_t)k * kSegStride;
+        if (near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2))
+            near_segment_adjoint(seg64 + (size_t)k * kSegStride, X, Y, g0, g1, g2, eps2, segsum + (size_t)k * kV);
+    }
+    for (int j = 0; j < M; ++j) {
+        const float* e = el32 + (size_t)j * kElemStride;
+        if (near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2))
+            near_element_adjoint(el64 + (size_t)j * kElemStride, X, Y, g0, g1, g2, psisum + 3 * (size_t)j);
     }
 }
 
@@ -270,48 +329,63 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int ns = N > 0 ? chunks_for(N, kgroups, chunk_s) : 0;
     const int ng = chunks_for(3 * (int64_t)M, kgroups, chunk_g);
     const int ne = N > 0 ? chunks_for(N, mgroups, chunk_e) : 0;
-    const size_t seg_part = (size_t)(ns + ng) * K * kV;
+    const int extra = mixed && N > 0 ? 1 : 0;           // one partial row for the float64 near pairs
+    const size_t seg_part = (size_t)(ns + ng + extra) * K * kV;
+    const size_t el_rows = (size_t)(ne > 0 ? ne : 1) + extra;
     // workspaces: tmp1 segment partials, tmp2 element partials + psi + mu, tmp3 Gauss points, red segment sums
     if ((rc = ensure(ctx, ctx->tmp1, seg_part * sizeof(double), s))) return rc;
-    if ((rc = ensure(ctx, ctx->tmp2, ((size_t)(ne > 0 ? ne : 1) * M * 3 + 2 * (size_t)M * 3) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp2, (el_rows * M * 3 + 2 * (size_t)M * 3) * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->tmp3, (size_t)3 * M * 5 * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->red, (size_t)K * kV * sizeof(double), s))) return rc;
     double* part = (double*)ctx->tmp1.ptr;
     double* epart = (double*)ctx->tmp2.ptr;
-    double* psi = epart + (size_t)(ne > 0 ? ne : 1) * M * 3;
+    double* psi = epart + el_rows * M * 3;
     double* mu = psi + (size_t)M * 3;
     double* gx = (double*)ctx->tmp3.ptr;
     double* gc = gx + (size_t)3 * M * 2;
     const double* seg64 = (const double*)ctx->seg64.ptr;
     const float* seg32 = (const float*)ctx->seg32.ptr;
+    const double* el64 = (const double*)ctx->elem64.ptr;
+    const float* el32 = (const float*)ctx->elem32.ptr;
     if (N > 0) {
-        if (!mixed)
+        if (!mixed) {
             {
                 ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
                 hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ns), dim3(256), 0, s, x,
                                    (const double*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
             }
-        else
+            {
+                ProfScope ps_(ctx, PT_VJP_ELEMENTS, s);
+                hipLaunchKernelGGL((k_vjp_elements<false, double>), dim3(mgroups, ne), dim3(256), 0, s, x,
+                                   (const double*)gbar, N, chunk_e, el64, el32, M, near2, epart);
+            }
+        } else {
+            double* segnear = part + (size_t)(ns + ng) * K * kV;
+            double* psinear = epart + (size_t)ne * M * 3;
+            NearList nl;
+            if ((rc = near_classify(ctx, ctx->nearv, x, N, K, M, &nl, s))) return rc;
+            if ((rc = fill_f64(ctx, segnear, (int64_t)K * kV, 0.0, s))) return rc;
+            if ((rc = fill_f64(ctx, psinear, (int64_t)M * 3, 0.0, s))) return rc;
             {
                 ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
                 hipLaunchKernelGGL((k_vjp_segments<true, float>), dim3(kgroups, ns), dim3(256), 0, s, x,
                                    (const float*)gbar, N, chunk_s, seg64, seg32, K, eps2, (float)eps2, near2, part);
             }
-        if (!mixed)
-            {
-                ProfScope ps_(ctx, PT_VJP_ELEMENTS, s);
-                hipLaunchKernelGGL((k_vjp_elements<false, double>), dim3(mgroups, ne), dim3(256), 0, s, x,
-                                   (const double*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, M, near2, epart);
-            }
-        else
             {
                 ProfScope ps_(ctx, PT_VJP_ELEMENTS, s);
                 hipLaunchKernelGGL((k_vjp_elements<true, float>), dim3(mgroups, ne), dim3(256), 0, s, x,
-                                   (const float*)gbar, N, chunk_e, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, M, near2, epart);
+                                   (const float*)gbar, N, chunk_e, el64, el32, M, near2, epart);
             }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)M * 3, 256)), dim3(256), 0, s, epart, ne,
+            {
+                ProfScope ps_(ctx, PT_NEAR, s);
+                const int64_t nslots = nl.nwaves * kWaveSlots;
+                hipLaunchKernelGGL(k_vjp_near, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nl.list, nl.count,
+                                   nl.flag, nslots, x, (const float*)gbar, seg64, K, el64, eps2, segnear, psinear);
+                hipLaunchKernelGGL(k_vjp_flagged, dim3(blocks_for(N, 256)), dim3(256), 0, s, nl.flag, N, x,
+                                   (const float*)gbar, seg32, seg64, K, el32, el64, M, eps2, near2, segnear, psinear);
+            }
+        }
+        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)M * 3, 256)), dim3(256), 0, s, epart, ne + extra,
                            (int64_t)M * 3, psi);
         if ((rc = check_launch(ctx, "vjp sweeps"))) return rc;
         if ((rc = launch_boundary_solve(ctx, psi, mu, true, s))) return rc;
@@ -322,8 +396,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                                (int64_t)3 * M, chunk_g, seg64, seg32, K, eps2, (float)eps2, near2,
                                part + (size_t)ns * K * kV);
         }
-        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, ns + ng,
-                           (int64_t)K * kV, (double*)ctx->red.ptr);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part,
+                           ns + ng + extra, (int64_t)K * kV, (double*)ctx->red.ptr);
     } else {
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, 0,
                            (int64_t)K * kV, (double*)ctx->red.ptr);

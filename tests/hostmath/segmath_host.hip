@@ -11,6 +11,8 @@ template <class T>
 struct HostM {
     static T log(T x) { return std::log(x); }
     static T log1p(T x) { return std::log1p(x); }
+    static T rcp(T x) { return T(1) / x; }
+    static T rsqrt(T x) { return T(1) / std::sqrt(x); }
     static T sqrt(T x) { return std::sqrt(x); }
     static T atan2(T y, T x) { return std::atan2(y, x); }
 };
@@ -25,6 +27,7 @@ bem::SegGeom<T> geom(const double* s)
     g.vx = (T)vx; g.vy = (T)vy; g.L2 = (T)L2;
     g.kd = L2 > 0.0 ? (T)(1.0 / (4.0 * bem::kPi * L2)) : T(0);
     g.ks = L2 > 0.0 ? (T)(1.0 / (8.0 * bem::kPi * L2 * std::sqrt(L2))) : T(0);
+    g.iL2 = L2 > 0.0 ? (T)(1.0 / L2) : T(0);
     return g;
 }
 
