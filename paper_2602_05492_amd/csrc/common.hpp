@@ -118,21 +118,28 @@ int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s);
 int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpose, hipStream_t s);
 int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
 int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
-int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s);
+// The mixed sweeps share one near-pair list layout (sweep_common.hpp).  The
+// forward sweep returns the list it built (valid until the next mixed sweep);
+// the adjoint and the normal equations take such a list for the same samples
+// and parameters, or classify the samples themselves when given none.
 struct NearList;
+int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s,
+                       NearList* out = nullptr);
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
 // vjp.hip
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
-            double* grad, hipStream_t s);
-// api.hip: expand + element tables (no boundary solve)
+            double* grad, hipStream_t s, const NearList* pre = nullptr);
+// api.hip: expand + element tables (no boundary solve); and the whole forward set-up
+// (expand, boundary right-hand side, boundary solve, element tables)
 int prepare_forward_tables(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
+int prepare_forward(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
 // gemm.hip
 int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta, const double* B,
              int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles);
 // jtj.hip
 int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s);
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
-            int gram, double* JtJ, double* Jtr, hipStream_t s);
+            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre = nullptr);
 int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, double* J, hipStream_t s);
 // gram_mfma.hip
 int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,

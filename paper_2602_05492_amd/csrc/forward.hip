@@ -53,8 +53,9 @@ __global__ void k_expand(const double* __restrict__ theta, int H, int S, double*
     float* o32 = seg32 + (size_t)k * kSegStride;
     for (int c = 0; c < kSegStride; ++c) { o[c] = rec[c]; o32[c] = (float)rec[c]; }
     if (!live) {
-        // float32 record of a degenerate segment: a point far outside the domain with zero
-        // weights, whose moments evaluate to exactly 0 without special cases in the sweeps
+        // float32 record of a degenerate segment: a point far outside the domain with
+        // v = 0 and kd = ks = 0, whose moments evaluate to exactly 0 without special cases
+        // in the forward sweeps (the derivative sweeps skip it by its L2 = 0)
         o32[0] = o32[2] = 1.0e6f;
         o32[1] = o32[3] = 1.0e6f;
         o32[4] = o32[5] = 0.0f;

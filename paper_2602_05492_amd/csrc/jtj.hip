@@ -57,16 +57,21 @@ template <> struct Store<uint16_t> {
 //   rows 24H + 4h + m       : coefficient of wd0, wd1, wc0, wc1 of handle h (any channel)
 // The vertex gradient of the polyline is chained to control points with the
 // Bernstein weights of the vertex parameter t_k = k/S.
+//
+// Float64 (Mixed = false), or mixed with near pairs inline in float64: the latter
+// runs only for the samples flagged in `only` (their near-pair list overflowed).
 template <bool Mixed, class OutT>
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, int64_t npts,
                                                   const double* __restrict__ seg64, const float* __restrict__ seg32,
                                                   int H, int S, double eps2, float eps2f, float near2,
+                                                  const uint8_t* __restrict__ only,
                                                   OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
 {
     using A = typename std::conditional<Mixed, float, double>::type;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = blockIdx.y;
     if (t >= npts) return;
+    if (only && !only[t]) return;
     const double X = x[2 * t], Y = x[2 * t + 1];
     const float Xf = (float)X, Yf = (float)Y;
     A geo[3][8];
@@ -91,9 +96,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
             if (!done && Mixed) {
                 const float* s32 = seg32 + (size_t)k * kSegStride;
                 const SegGeom<float> gf = load_geom(s32);
-                const float dx = gf.ax - Xf, dy = gf.ay - Yf, ex = gf.bx - Xf, ey = gf.by - Yf;
-                const float lim = near2 * gf.L2;
-                if (!((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim))) {
+                if (!near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
                     const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
                     const Moments<float> mf = pair_moments(gf, st);
                     m = Moments<A>{(A)mf.da, (A)mf.db, (A)mf.sa, (A)mf.sb};
@@ -139,6 +142,133 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
     for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (size_t)((size_t)24 * H + 4 * h + q) * ld + t, (double)col[q]);
 }
 
+constexpr int kFeatVals = 28;   // chained contributions of one pair to the 28 handle rows
+
+// Mixed handle features: float32 pairs, near pairs skipped (same predicate as the
+// classification), then the float64 contributions of this sample's listed near pairs
+// with this handle's segments are added.  List entries of a wavefront are sorted by
+// segment, so the handle's entries are found by bisection.  x points at the tile's
+// first sample, whose global index is t0 (a multiple of 64); flagged samples are
+// rewritten afterwards by k_features<true>.
+template <class OutT>
+__global__ void __launch_bounds__(256) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
+                                                      const float* __restrict__ seg32, int H, int S, float eps2f,
+                                                      float near2, const NearPair* __restrict__ list,
+                                                      const int* __restrict__ wave_count,
+                                                      const uint8_t* __restrict__ flag, const float* __restrict__ corr,
+                                                      OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int h = blockIdx.y;
+    if (t >= npts) return;
+    const float Xf = (float)x[2 * t], Yf = (float)x[2 * t + 1];
+    float geo[3][8];
+    float col[4] = {0.f, 0.f, 0.f, 0.f};
+    float pv[3][2];
+    for (int c = 0; c < 3; ++c) {
+        for (int q = 0; q < 8; ++q) geo[c][q] = 0.f;
+        pv[c][0] = pv[c][1] = 0.f;
+    }
+    for (int j = 0; j <= S; ++j) {
+        float va[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+        float vb[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+        if (j < S) {
+            const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
+            const SegGeom<float> gf = load_geom(s32);
+            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
+            if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
+                const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                const Moments<float> m = pair_moments(gf, st);
+                for (int c = 0; c < 3; ++c) {
+                    const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
+                                                          s32[kWcA + c], s32[kWcB + c]);
+                    va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
+                }
+                const float ta = (float)j / (float)S, tb = (float)(j + 1) / (float)S;
+                col[0] += m.da * (1.0f - ta) + m.db * (1.0f - tb);
+                col[1] += m.da * ta + m.db * tb;
+                col[2] += m.sa * (1.0f - ta) + m.sb * (1.0f - tb);
+                col[3] += m.sa * ta + m.sb * tb;
+            }
+        }
+        double B[4];
+        bernstein3((double)j / (double)S, B);
+        for (int c = 0; c < 3; ++c) {
+            const float gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
+            for (int q = 0; q < 4; ++q) {
+                geo[c][2 * q] += (float)B[q] * gx;
+                geo[c][2 * q + 1] += (float)B[q] * gy;
+            }
+            pv[c][0] = vb[c][0];
+            pv[c][1] = vb[c][1];
+        }
+    }
+    const int64_t i = t0 + t;
+    if (!flag[i]) {
+        const int64_t w = i >> 6;
+        const NearPair* sl = list + w * kWaveSlots;
+        const int cnt = wave_count[w];
+        const int k0 = h * S, k1 = k0 + S;
+        int lo = 0, hi = cnt;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sl[mid].seg < k0) lo = mid + 1;
+            else hi = mid;
+        }
+        for (int e = lo; e < cnt && sl[e].seg < k1; ++e) {
+            if (sl[e].sample != (int32_t)i) continue;
+            const float* cr = corr + ((size_t)(w - (t0 >> 6)) * kWaveSlots + e) * kFeatVals;
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 8; ++q) geo[c][q] += cr[8 * c + q];
+            for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
+        }
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int q = 0; q < 8; ++q)
+            Store<OutT>::put(Xt, Xlo, (size_t)((size_t)c * 8 * H + 8 * h + q) * ld + t, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (size_t)((size_t)24 * H + 4 * h + q) * ld + t, (double)col[q]);
+}
+
+// Float64 contributions of the listed near (sample, segment) pairs of one tile
+// (wavefronts w0 .. w0 + nw - 1) to the 28 handle rows: thread per list slot,
+// corr[slot][28], geometry rows already chained to control points.
+__global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list,
+                                                       const int* __restrict__ wave_count,
+                                                       const uint8_t* __restrict__ flag, int64_t w0, int64_t nw,
+                                                       const double* __restrict__ x, const double* __restrict__ seg64,
+                                                       int K, int S, double eps2, float* __restrict__ corr)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nw * kWaveSlots) return;
+    const int64_t w = w0 + t / kWaveSlots;
+    const int e = (int)(t % kWaveSlots);
+    if (e >= wave_count[w]) return;
+    const NearPair p = list[w * kWaveSlots + e];
+    if (p.seg >= K || flag[p.sample]) return;
+    const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
+    const double* s64 = seg64 + (size_t)p.seg * kSegStride;
+    const SegGeom<double> g = load_geom(s64);
+    const int j = p.seg % S;
+    const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
+    double Ba[4], Bb[4];
+    bernstein3(ta, Ba);
+    bernstein3(tb, Bb);
+    float* o = corr + (size_t)t * kFeatVals;
+    const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+    const Moments<double> m = pair_moments(g, st);
+    for (int c = 0; c < 3; ++c) {
+        const Grad4<double> gr = pair_backward(g, st, eps2, s64[kWdA + c], s64[kWdB + c], s64[kWcA + c], s64[kWcB + c]);
+        for (int q = 0; q < 4; ++q) {
+            o[8 * c + 2 * q] = (float)(Ba[q] * gr.ax + Bb[q] * gr.bx);
+            o[8 * c + 2 * q + 1] = (float)(Ba[q] * gr.ay + Bb[q] * gr.by);
+        }
+    }
+    o[24] = (float)(m.da * (1.0 - ta) + m.db * (1.0 - tb));
+    o[25] = (float)(m.da * ta + m.db * tb);
+    o[26] = (float)(m.sa * (1.0 - ta) + m.sb * (1.0 - tb));
+    o[27] = (float)(m.sa * ta + m.sb * tb);
+}
+
 // beta rows: Xt[row0 + j][t] = beta_j(x_t); thread per (point, element).
 template <bool Mixed, class OutT>
 __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x, int64_t npts,
@@ -155,9 +285,7 @@ __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x,
     if (Mixed) {
         const float* f = el32 + (size_t)j * kElemStride;
         const float Xf = (float)X, Yf = (float)Y;
-        const float dx = f[0] - Xf, dy = f[1] - Yf, ex = dx + f[2], ey = dy + f[3];
-        const float lim = near2 * (f[2] * f[2] + f[3] * f[3]);
-        if ((dx * dx + dy * dy < lim) && (ex * ex + ey * ey < lim))
+        if (near_element(f[0], f[1], f[2], f[3], Xf, Yf, near2))
             b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
         else
             b = (double)element_beta<float, DevF32>(f[0], f[1], f[2], f[3], Xf, Yf);
@@ -299,9 +427,13 @@ int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
 
 // Feature rows of npts points into Xt (ld = row stride); rows 0..28H-1 handle
 // features, rows 28H.. beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
+// Mixed precision needs the near-pair list of the whole sample set (nl), the tile's
+// first global sample index t0 (a multiple of 64), the global samples xg and a
+// correction buffer of ceil(npts / 64) * kWaveSlots * 28 floats.
 template <class OutT>
 static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
-                           uint16_t* Xlo, int64_t ld, hipStream_t s)
+                           uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
+                           const double* xg = nullptr, float* corr = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -309,19 +441,29 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const double nf = 2.0 * ctx->opts.near_factor;
     const float near2 = (float)(nf * nf);
     const dim3 grid(blocks_for(npts, 256), H);
+    if (mixed && (!nl || !xg || !corr || (t0 & 63)))
+        return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
     if (H > 0) {
-        if (mixed)
+        if (mixed) {
+            const int64_t nw = (npts + 63) / 64;
             {
-                ProfScope ps_(ctx, PT_FEATURES, s);
-                hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                                   (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
+                ProfScope ps_(ctx, PT_NEAR, s);
+                hipLaunchKernelGGL(k_features_near, dim3(blocks_for(nw * kWaveSlots, 256)), dim3(256), 0, s, nl->list,
+                                   nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, eps2,
+                                   corr);
             }
-        else
-            {
-                ProfScope ps_(ctx, PT_FEATURES, s);
-                hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                                   (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, Xt, Xlo, ld);
-            }
+            ProfScope ps_(ctx, PT_FEATURES, s);
+            hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
+                               H, S, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, Xt, Xlo, ld);
+            hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, nl->flag + t0, Xt, Xlo,
+                               ld);
+        } else {
+            ProfScope ps_(ctx, PT_FEATURES, s);
+            hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, (const uint8_t*)nullptr,
+                               Xt, Xlo, ld);
+        }
     }
     if (with_beta) {
         const dim3 gb(blocks_for(npts, 256), ctx->M);
@@ -389,7 +531,7 @@ static std::vector<int> gram_tiles(int H, int W, int ts)
 }
 
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
-            int gram, double* JtJ, double* Jtr, hipStream_t s)
+            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre)
 {
     int rc;
     const int M = ctx->M;
@@ -429,7 +571,16 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int ts = gram == BEM_GRAM_FP64 ? 64 : (gram == BEM_GRAM_FP32_MFMA ? 128 : 256);
     const std::vector<int> tiles = gram_tiles(H, (int)W, ts);
     const int ntiles = (int)tiles.size() / 2;
-    if ((rc = ensure(ctx, ctx->tmp5, tiles.size() * sizeof(int) + 256, s))) return rc;
+    // tmp5: tile list, then the near-pair corrections of one sample tile
+    const size_t tiles_bytes = (tiles.size() * sizeof(int) + 255) / 256 * 256;
+    const size_t corr_floats = mixed ? (size_t)((T + 63) / 64) * kWaveSlots * kFeatVals : 0;
+    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + corr_floats * sizeof(float) + 256, s))) return rc;
+    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes) : nullptr;
+    NearList nl{};
+    if (mixed && N > 0) {
+        if (pre) nl = *pre;
+        else if ((rc = near_classify(ctx, ctx->nearf, x, N, H * ctx->opts.segs_per_handle, 0, &nl, s))) return rc;
+    }
     if (hipMemcpyAsync(ctx->tmp5.ptr, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "tile list upload");
     // the tile list is read by every tile's Gram; keep the host copy alive until queued work is done
@@ -440,7 +591,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         const double* xt = x + 2 * t0;
         if (gram == BEM_GRAM_FP64) {
             double* Xt = (double*)ctx->tmp0.ptr;
-            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s))) return rc;
+            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
@@ -450,13 +601,13 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)ctx->tmp0.ptr;
-            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s))) return rc;
+            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
             if ((rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
         } else {
             uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
             uint16_t* Xl = Xh + (size_t)W * T;
-            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, T, s))) return rc;
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, T, s, &nl, t0, x, corr))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
             if ((rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
         }

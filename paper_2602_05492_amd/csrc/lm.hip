@@ -150,8 +150,15 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         if ((rc = row_sums(ctx, u, mixed, T, N, 2, nullptr, sums, dpart, s))) return rc;
         for (int c = 0; c < 3; ++c) st->cbar[c] = N > 0 ? sums[c] / (double)N : 0.0;
     }
-    // residual and loss at theta
-    if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) return rc;
+    // residual and loss at theta; the mixed sweep's near-pair list serves the adjoint and the
+    // normal equations below (same samples, same parameters)
+    NearList nl{};
+    if (mixed) {
+        if ((rc = prepare_forward(ctx, theta, H, s))) return rc;
+        if ((rc = launch_sweep_mixed(ctx, x, N, H * ctx->opts.segs_per_handle, st->cbar, (float*)u, s, &nl))) return rc;
+    } else if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) {
+        return rc;
+    }
     if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
     const double L0 = N > 0 ? 0.5 * sums[0] / (double)N : 0.0;
     st->loss_before = L0;
@@ -159,9 +166,9 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     if (!std::isfinite(L0)) return set_error(ctx, BEM_ENUMERIC, "non-finite loss at the current parameters");
     if (H == 0 || N == 0) return BEM_OK;
     // gradient by the adjoint, Hessian by the normal equations
-    if ((rc = bem_vjp(ctx, theta, H, x, N, r, g, prec, s))) return rc;
+    if ((rc = run_vjp(ctx, theta, H, x, N, r, mixed, g, s, mixed ? &nl : nullptr))) return rc;
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / (double)N);
-    if ((rc = bem_jtj(ctx, theta, H, x, N, r, JtJ, Jtr, (bem_gram)gram, prec, s))) return rc;
+    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, Jtr, s, mixed ? &nl : nullptr))) return rc;
     // damped Cholesky, raising lambda until it factors
     double lam = st->lambda;
     for (int attempt = 0;; ++attempt) {

@@ -224,8 +224,10 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     return check_launch(ctx, "classify");
 }
 
-int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar, float* u, hipStream_t s)
+int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar, float* u, hipStream_t s,
+                       NearList* out)
 {
+    if (out) *out = NearList{};
     if (N == 0) return BEM_OK;
     int rc;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
@@ -244,6 +246,7 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     int* wave_count = (int*)(base + list_bytes + acc_bytes);
     uint8_t* flag = (uint8_t*)(base + list_bytes + acc_bytes + cnt_bytes);
     if ((rc = fill_f64(ctx, acc, 3 * N, 0.0, s))) return rc;
+    if (out) *out = NearList{list, wave_count, flag, nwaves};
     {
         ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
         hipLaunchKernelGGL(k_sweep_far, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,

@@ -311,7 +311,7 @@ int chunks_for(int64_t N, int groups, int64_t& chunk)
 }  // namespace
 
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
-            double* grad, hipStream_t s)
+            double* grad, hipStream_t s, const NearList* pre)
 {
     int rc;
     const int S = ctx->opts.segs_per_handle;
@@ -363,7 +363,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             double* segnear = part + (size_t)(ns + ng) * K * kV;
             double* psinear = epart + (size_t)ne * M * 3;
             NearList nl;
-            if ((rc = near_classify(ctx, ctx->nearv, x, N, K, M, &nl, s))) return rc;
+            if (pre) nl = *pre;
+            else if ((rc = near_classify(ctx, ctx->nearv, x, N, K, M, &nl, s))) return rc;
             if ((rc = fill_f64(ctx, segnear, (int64_t)K * kV, 0.0, s))) return rc;
             if ((rc = fill_f64(ctx, psinear, (int64_t)M * 3, 0.0, s))) return rc;
             {
