@@ -1,0 +1,117 @@
+"""Mixed precision with every branch of the near-pair lists: listed pairs, and
+wavefronts whose list slice overflows (their samples are flagged and redone
+with the near pairs inline).
+
+The mixed path evaluates a pair in float64 when both segment end points lie
+within 2 * near_factor * L of the sample.  near_factor = 1.5 overflows the
+slices of most wavefronts of the medium workload (within such a wavefront some
+samples' pairs are listed, the rest flagged); near_factor = 60 makes every
+pair near, so every slice overflows and every sample takes the flagged path.
+Each case is compared with the FP64 oracle at the mixed-precision bars of the
+other GPU tests (colour 1e-4 absolute, gradient 1e-3 relative, J^T J 1e-4 and
+J^T r 1e-3 relative, LM step 1e-2 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2602_05492_amd import bem as B
+from paper_2602_05492_amd import workload as W
+from helpers import ctx_for, dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+SLOTS_PER_WAVE = 1024          # list capacity of one 64-sample wavefront
+FACTORS = [1.5, 60.0]
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _overflowing_waves(theta, x, S, nf):
+    """Fraction of 64-sample wavefronts whose near handle-segment pairs (float64 reading of the
+    predicate) exceed one slice; the outer elements only add to the count."""
+    t = np.arange(S + 1) / S
+    B3 = np.stack([(1 - t) ** 3, 3 * t * (1 - t) ** 2, 3 * t ** 2 * (1 - t), t ** 3], 1)
+    P = np.einsum("tc,hcd->htd", B3, theta[:, :8].reshape(-1, 4, 2))
+    a, b = P[:, :-1].reshape(-1, 2), P[:, 1:].reshape(-1, 2)
+    L2 = ((b - a) ** 2).sum(1)
+    r2 = (2 * nf) ** 2 * L2
+    da = ((a[None] - x[:, None]) ** 2).sum(2)
+    db = ((b[None] - x[:, None]) ** 2).sum(2)
+    near = (da < r2[None]) & (db < r2[None])
+    per_wave = near.sum(1)[: len(x) // 64 * 64].reshape(-1, 64).sum(1)
+    return float((per_wave > SLOTS_PER_WAVE).mean())
+
+
+def _case(n):
+    wl = W.make_config(2)
+    idx = wl.subsample(n)
+    return wl, wl.samples(0)[idx]
+
+
+@pytest.mark.parametrize("nf", FACTORS)
+def test_overflow_is_exercised(nf):
+    wl, x = _case(2048)
+    frac = _overflowing_waves(wl.theta_true, x, wl.S, nf)
+    log(f"near_factor {nf}: {frac:.2f} of the wavefronts overflow")
+    assert (0.0 < frac < 1.0) if nf == 1.5 else frac == 1.0
+
+
+@pytest.mark.parametrize("nf", FACTORS)
+def test_eval_mixed_near_lists(nf):
+    wl, x = _case(3000)
+    ctx = ctx_for(wl.S, near_factor=nf)
+    got = host(ctx.eval(dev(wl.theta_true), dev(x), wl.cbar_true, "mixed"))
+    ref = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps)
+    err = float(np.abs(got - ref).max())
+    log(f"near_factor {nf}: mixed eval max abs err {err:.3e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("nf", FACTORS)
+def test_vjp_mixed_near_lists(nf):
+    wl, x = _case(3000)
+    ctx = ctx_for(wl.S, near_factor=nf)
+    g = W.random_vector(61, (len(x), 3))
+    got = host(ctx.vjp(dev(wl.theta_true), dev(x), dev(g, torch.float32), "mixed"))
+    ref = O.vjp(wl.theta_true, x, g, wl.S, wl.eps)
+    err = _rel(got, ref)
+    log(f"near_factor {nf}: mixed vjp rel err {err:.3e}")
+    assert err < 1e-3
+
+
+@pytest.mark.parametrize("nf", FACTORS)
+def test_jtj_mixed_near_lists(nf):
+    """Several sample tiles (1024 rows each, the last ragged), so tiles start at non-zero wavefronts."""
+    wl, x = _case(3000)
+    ctx = ctx_for(wl.S, near_factor=nf, tile_rows=1024)
+    r = W.random_vector(62, (len(x), 3))
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+    for gram in ["bf16x3_mfma", "fp64"]:
+        JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r, torch.float32), gram, "mixed")
+        eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+        log(f"near_factor {nf}: jtj {gram}/mixed rel err JtJ {eh:.3e} Jtr {eg:.3e}")
+        assert eh < 1e-4 and eg < 1e-3
+
+
+@pytest.mark.parametrize("nf", FACTORS)
+def test_lm_step_mixed_near_lists(nf):
+    """lm_step hands the forward sweep's list to the adjoint and the J tiles."""
+    wl, x = _case(4096)
+    T = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps) + wl.spec.sigma * W.random_vector(63, (len(x), 3))
+    ctx = ctx_for(wl.S, near_factor=nf, tile_rows=1024)
+    st_o = O.LMState(lam=1e-3, mean_rule=0)
+    th_o, st_o = O.lm_step(wl.theta0, x, T, st_o, wl.S, wl.eps)
+    th = dev(wl.theta0)
+    st = B.new_lm_state(1e-3, 0)
+    ctx.lm_step(th, dev(x), dev(T), st, "bf16x3_mfma", "mixed")
+    assert bool(st.accepted) == bool(st_o.accepted)
+    assert abs(st.loss_before - st_o.loss_before) <= 1e-4 * st_o.loss_before
+    d_o = th_o - wl.theta0
+    d = host(th) - wl.theta0
+    e = float(np.abs(d - d_o).max() / np.abs(d_o).max()) if st_o.accepted else float(np.abs(d).max())
+    log(f"near_factor {nf}: lm step rel err {e:.3e}, accepted {st.accepted}")
+    assert e < 1e-2
