@@ -1,15 +1,15 @@
 // gram_mfma.hip - the normal-equation contraction on the matrix cores (Eq.
 // losshessian): G += X X^T over one sample tile, X the feature-major tile
-// [W rows x n samples], only the needed 128x128 output tiles.
+// [W rows x n samples], only the needed output tiles (256x256 split-BF16,
+// 128x128 FP32).
 //
 //   FP32_MFMA   : v_mfma_f32_32x32x2_f32 on float rows
 //   BF16X3_MFMA : rows split x = hi + lo (bfloat16); hi*hi + hi*lo + lo*hi on
 //                 v_mfma_f32_32x32x16_bf16 (the lo*lo term is below float32
 //                 rounding of the product)
-// Accumulation is float32 over the tile's samples and float64 across tiles
-// (the epilogue adds into the float64 Gram).  A block of 4 wavefronts owns a
-// 128x128 tile; each wavefront a 64x64 quarter as 2x2 MFMA 32x32 tiles.  The
-// A and B operands of every MFMA come from rows of the same matrix with the
+// Accumulation is float32 over one part of the tile's samples and float64
+// across tiles and parts (the epilogue adds into the float64 Gram of the part).
+// The A and B operands of every MFMA come from rows of the same matrix with the
 // same lane -> (row, k-slot) assignment, so each k of the slab is summed once.
 #include "common.hpp"
 #include "sweep_common.hpp"
@@ -22,17 +22,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
-__device__ inline bf16x8 load_bf16x8(const uint16_t* __restrict__ p, int64_t k, int64_t n)
-{
-    u16x8 v;
-    if (k + 8 <= n) {
-        v = *(const u16x8*)(p + k);
-    } else {
-        for (int e = 0; e < 8; ++e) v[e] = (k + e < n) ? p[k + e] : (uint16_t)0;
-    }
-    return __builtin_bit_cast(bf16x8, v);
-}
 
 __device__ inline floatx4 load_f32x4(const float* __restrict__ p, int64_t k, int64_t n)
 {
@@ -58,59 +47,31 @@ __device__ inline void epilogue(const floatx16 (&acc)[2][2], int64_t rbase, int6
             }
 }
 
-__global__ void __launch_bounds__(256) k_gram_bf16x3(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl,
-                                                     int64_t ld, int W, int64_t n, const int* __restrict__ tiles,
-                                                     double* __restrict__ G)
+// Block -> work entry: blocks are handed to the 8 XCDs round-robin (block b runs
+// on XCD b mod 8), so XCD x is given the contiguous run of entries
+// [x * per, (x + 1) * per) of the work list; entries ordered by super-tiles keep
+// the operand panels of the blocks running together on one XCD few, and they
+// are then served from that XCD's L2.
+__device__ inline int work_index(int nwork)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = lane & 31, lk = lane >> 5;
-    const int64_t rbase = (int64_t)tiles[2 * blockIdx.x] * 128 + 64 * (wave >> 1);
-    const int64_t cbase = (int64_t)tiles[2 * blockIdx.x + 1] * 128 + 64 * (wave & 1);
-    floatx16 acc[2][2];
-    for (int mi = 0; mi < 2; ++mi)
-        for (int nj = 0; nj < 2; ++nj)
-            for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
-    const uint16_t* ah[2];
-    const uint16_t* al[2];
-    const uint16_t* bh[2];
-    const uint16_t* bl[2];
-    bool arow[2], bcol[2];
-    for (int q = 0; q < 2; ++q) {
-        const int64_t ra = rbase + 32 * q + li, cb = cbase + 32 * q + li;
-        arow[q] = ra < W;
-        bcol[q] = cb < W;
-        ah[q] = Xh + (arow[q] ? ra : 0) * ld;
-        al[q] = Xl + (arow[q] ? ra : 0) * ld;
-        bh[q] = Xh + (bcol[q] ? cb : 0) * ld;
-        bl[q] = Xl + (bcol[q] ? cb : 0) * ld;
-    }
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u16x8{0, 0, 0, 0, 0, 0, 0, 0});
-    for (int64_t k0 = 0; k0 < n; k0 += 16) {
-        const int64_t k = k0 + 8 * lk;
-        bf16x8 a_hi[2], a_lo[2], b_hi[2], b_lo[2];
-        for (int q = 0; q < 2; ++q) {
-            a_hi[q] = arow[q] ? load_bf16x8(ah[q], k, n) : zero;
-            a_lo[q] = arow[q] ? load_bf16x8(al[q], k, n) : zero;
-            b_hi[q] = bcol[q] ? load_bf16x8(bh[q], k, n) : zero;
-            b_lo[q] = bcol[q] ? load_bf16x8(bl[q], k, n) : zero;
-        }
-        for (int mi = 0; mi < 2; ++mi)
-            for (int nj = 0; nj < 2; ++nj) {
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[mi], b_hi[nj], acc[mi][nj], 0, 0, 0);
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[mi], b_lo[nj], acc[mi][nj], 0, 0, 0);
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo[mi], b_hi[nj], acc[mi][nj], 0, 0, 0);
-            }
-    }
-    epilogue(acc, rbase, cbase, W, G);
+    const int per = (nwork + 7) >> 3;
+    return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
-__global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, int64_t ld, int W, int64_t n,
-                                                  const int* __restrict__ tiles, double* __restrict__ G)
+__global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, int64_t ld, int W, int64_t n_all,
+                                                  const int* __restrict__ work, int nwork, int64_t kchunk,
+                                                  double* __restrict__ G, int64_t gstride)
 {
+    const int wi = work_index(nwork);
+    if (wi >= nwork) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 31, lk = lane >> 5;
-    const int64_t rbase = (int64_t)tiles[2 * blockIdx.x] * 128 + 64 * (wave >> 1);
-    const int64_t cbase = (int64_t)tiles[2 * blockIdx.x + 1] * 128 + 64 * (wave & 1);
+    const int64_t rbase = (int64_t)work[3 * wi] * 128 + 64 * (wave >> 1);
+    const int64_t cbase = (int64_t)work[3 * wi + 1] * 128 + 64 * (wave & 1);
+    const int64_t kb = (int64_t)work[3 * wi + 2] * kchunk;
+    const int64_t n = kb + kchunk < n_all ? kb + kchunk : n_all;
+    if (kb >= n) return;
+    G += (int64_t)work[3 * wi + 2] * gstride;
     floatx16 acc[2][2];
     for (int mi = 0; mi < 2; ++mi)
         for (int nj = 0; nj < 2; ++nj)
@@ -126,7 +87,7 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
         bp[q] = X + (bcol[q] ? cb : 0) * ld;
     }
     const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = 0; k0 < n; k0 += 8) {
+    for (int64_t k0 = kb; k0 < n; k0 += 8) {
         const int64_t k = k0 + 4 * lk;
         floatx4 a[2], b[2];
         for (int q = 0; q < 2; ++q) {
@@ -146,29 +107,40 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
 // 32x32).  Each 32-sample stage of the four operand slabs (A hi/lo, B hi/lo,
 // 256 rows x 32 samples) is loaded into registers while the previous stage is
 // multiplied out of LDS, then stored to LDS (rows padded to 40 bf16 so the
-// 16-byte operand reads of 16 consecutive rows hit distinct banks).
+// 16-byte operand reads of 16 consecutive rows hit distinct banks).  The tile
+// is in 32-sample blocks ([t / 32][row][t % 32]), so a stage of a slab is one
+// contiguous 16 KiB run and every 128-byte line fetched is used whole.
 constexpr int G2_T = 256, G2_BK = 32, G2_LD = G2_BK + 8;
 
 __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl,
-                                                         int ld, int W, int n, const int* __restrict__ tiles,
-                                                         double* __restrict__ G)
+                                                         int W, int n_all, const int* __restrict__ work,
+                                                         int nwork, int kchunk, double* __restrict__ G,
+                                                         int64_t gstride)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sm[4][G2_T * G2_LD];   // A hi, A lo, B hi, B lo
+    const int wi = work_index(nwork);
+    if (wi >= nwork) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int li = lane & 31, lk = lane >> 5;
-    const int row0 = tiles[2 * blockIdx.x] * G2_T;
-    const int col0 = tiles[2 * blockIdx.x + 1] * G2_T;
+    const int row0 = work[3 * wi] * G2_T;
+    const int col0 = work[3 * wi + 1] * G2_T;
+    // samples [kb, n) of this entry's part; partial Gram of the part
+    const int kb = work[3 * wi + 2] * kchunk;
+    const int n = kb + kchunk < n_all ? kb + kchunk : n_all;
+    if (kb >= n) return;                                   // part beyond a ragged last tile
+    G += (int64_t)work[3 * wi + 2] * gstride;
     const int wr = wave >> 1, wc = wave & 1;
     // global -> register staging: thread owns 16-byte chunk (tid & 3) of rows tid/4 and tid/4 + 128
     const int c8 = (tid & 3) * 8;
     const int r_a = tid >> 2;
-    int goff[2][2];            // [A/B][p] element offset of the chunk (row * ld + c8), -1 when the row is outside
+    const int W32 = W << 5;    // elements per 32-sample block of the tile
+    int goff[2][2];            // [A/B][p] element offset of the chunk in a block (row * 32 + c8), -1 outside
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const int ra = row0 + r_a + 128 * p, rb = col0 + r_a + 128 * p;
-        goff[0][p] = ra < W ? ra * ld + c8 : -1;
-        goff[1][p] = rb < W ? rb * ld + c8 : -1;
+        goff[0][p] = ra < W ? (ra << 5) + c8 : -1;
+        goff[1][p] = rb < W ? (rb << 5) + c8 : -1;
     }
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     u16x8 stage[2][2][2];      // [A/B][hi/lo][p]
@@ -176,6 +148,7 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
     {                                                                                         \
         const int k0_ = (K0);                                                                 \
         const bool full_ = k0_ + G2_BK <= n;                                                  \
+        const int kb_ = (k0_ >> 5) * W32;                                                     \
         _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                      \
         _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                       \
             const int o = goff[ab][p];                                                        \
@@ -183,13 +156,13 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
                 stage[ab][0][p] = z8;                                                         \
                 stage[ab][1][p] = z8;                                                         \
             } else if (full_) {                                                               \
-                stage[ab][0][p] = *(const u16x8*)(Xh + o + k0_);                              \
-                stage[ab][1][p] = *(const u16x8*)(Xl + o + k0_);                              \
+                stage[ab][0][p] = *(const u16x8*)(Xh + kb_ + o);                              \
+                stage[ab][1][p] = *(const u16x8*)(Xl + kb_ + o);                              \
             } else {                                                                          \
                 _Pragma("unroll") for (int e = 0; e < 8; ++e) {                               \
                     const bool in = k0_ + c8 + e < n;                                         \
-                    stage[ab][0][p][e] = in ? Xh[o + k0_ + e] : (uint16_t)0;                  \
-                    stage[ab][1][p][e] = in ? Xl[o + k0_ + e] : (uint16_t)0;                  \
+                    stage[ab][0][p][e] = in ? Xh[kb_ + o + e] : (uint16_t)0;                  \
+                    stage[ab][1][p][e] = in ? Xl[kb_ + o + e] : (uint16_t)0;                  \
                 }                                                                             \
             }                                                                                 \
         }                                                                                     \
@@ -201,8 +174,8 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
         for (int nj = 0; nj < 4; ++nj)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
-    G2_LOAD_STAGE(0)
-    for (int k0 = 0; k0 < n; k0 += G2_BK) {
+    G2_LOAD_STAGE(kb)
+    for (int k0 = kb; k0 < n; k0 += G2_BK) {
         __syncthreads();                                  // previous stage fully consumed
 #pragma unroll
         for (int ab = 0; ab < 2; ++ab)
@@ -249,7 +222,8 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
             }
 }
 
-// R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; X float or bf16 hi + lo)
+// R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; X float rows of stride ld, or the
+// blocked bf16 hi + lo tile with ld = its row count)
 template <bool Bf16>
 __global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const uint16_t* __restrict__ Xlo, int64_t ld,
                                             int64_t n, const double* __restrict__ r, double* __restrict__ R)
@@ -260,7 +234,8 @@ __global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const 
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
         double v;
         if (Bf16) {
-            const uint16_t h = ((const uint16_t*)Xhi)[f * ld + t], l = Xlo[f * ld + t];
+            const int64_t i = (t >> 5) * (ld << 5) + (f << 5) + (t & 31);
+            const uint16_t h = ((const uint16_t*)Xhi)[i], l = Xlo[i];
             v = (double)__uint_as_float((uint32_t)h << 16) + (double)__uint_as_float((uint32_t)l << 16);
         } else {
             v = (double)((const float*)Xhi)[f * ld + t];
@@ -280,21 +255,26 @@ __global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const 
 
 }  // namespace
 
+// G[part] += X X^T over the work entries (row tile, column tile, part): part p covers
+// samples [p * kchunk, (p + 1) * kchunk) of the tile and adds into G + p * gstride.
 int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-                     const int* tiles128, int ntiles, double* G, hipStream_t s)
+                     const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, hipStream_t s)
 {
-    if (n <= 0 || ntiles <= 0) return BEM_OK;
+    if (n <= 0 || nwork <= 0) return BEM_OK;
+    const int grid = 8 * ((nwork + 7) / 8);
     if (gram == BEM_GRAM_BF16X3_MFMA)
         {
             ProfScope ps_(ctx, PT_GRAM_MFMA, s);
-            // element offsets inside one operand array are 32-bit (W * ld < 2^31 is checked by the caller)
-            hipLaunchKernelGGL(k_gram_bf16x3_lds, dim3(ntiles), dim3(512), 0, s, (const uint16_t*)Xhi, Xlo, (int)ld, W,
-                               (int)n, tiles128, G);
+            // blocked tile (ld unused); element offsets inside one operand array are 32-bit
+            // (W * tile rows < 2^31 is checked by the caller)
+            hipLaunchKernelGGL(k_gram_bf16x3_lds, dim3(grid), dim3(512), 0, s, (const uint16_t*)Xhi, Xlo, W, (int)n,
+                               work, nwork, (int)kchunk, G, gstride);
         }
     else
         {
             ProfScope ps_(ctx, PT_GRAM_MFMA, s);
-            hipLaunchKernelGGL(k_gram_f32, dim3(ntiles), dim3(256), 0, s, (const float*)Xhi, ld, W, n, tiles128, G);
+            hipLaunchKernelGGL(k_gram_f32, dim3(grid), dim3(256), 0, s, (const float*)Xhi, ld, W, n, work, nwork, kchunk,
+                               G, gstride);
         }
     return check_launch(ctx, "gram_mfma");
 }
@@ -306,7 +286,7 @@ int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int6
     if (gram == BEM_GRAM_BF16X3_MFMA)
         {
             ProfScope ps_(ctx, PT_XR, s);
-            hipLaunchKernelGGL(k_xr<true>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
+            hipLaunchKernelGGL(k_xr<true>, dim3(W), dim3(256), 0, s, Xhi, Xlo, (int64_t)W, n, r, R);
         }
     else
         {

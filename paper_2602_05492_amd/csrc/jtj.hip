@@ -13,6 +13,8 @@
 // R = sum_x Xt r.  Afterwards, per channel,
 //   J^T J += E_c^T A_c E_c + sym(E_c^T B_c Z_c') + Z_c'^T D Z_c'
 // with A_c, B_c, D the channel's blocks of G, and J^T r likewise.
+#include <algorithm>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -34,21 +36,29 @@ __device__ inline uint16_t bf16_bits(float v)
 }
 __device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// Feature element (f, t) of a tile.  float64 / float32 tiles are row-major with
+// row stride ld; the split-bfloat16 tile is stored in blocks of 32 samples,
+// [t / 32][f][t % 32] with ld = the number of rows, so that one 32-sample stage
+// of consecutive rows is one contiguous run of memory for the Gram kernel.
 template <class OutT> struct Store;
 template <> struct Store<double> {
-    __device__ static void put(double* hi, uint16_t*, size_t i, double v) { hi[i] = v; }
+    __device__ static void put(double* hi, uint16_t*, int64_t f, int64_t t, int64_t ld, double v) { hi[f * ld + t] = v; }
 };
 template <> struct Store<float> {
-    __device__ static void put(float* hi, uint16_t*, size_t i, double v) { hi[i] = (float)v; }
+    __device__ static void put(float* hi, uint16_t*, int64_t f, int64_t t, int64_t ld, double v)
+    {
+        hi[f * ld + t] = (float)v;
+    }
 };
 // hi + lo bfloat16 split of the float value
 template <> struct Store<uint16_t> {
-    __device__ static void put(uint16_t* hi, uint16_t* lo, size_t i, double v)
+    __device__ static void put(uint16_t* hi, uint16_t* lo, int64_t f, int64_t t, int64_t ld, double v)
     {
-        const float f = (float)v;
-        const uint16_t h = bf16_bits(f);
+        const size_t i = (size_t)(t >> 5) * (size_t)(ld << 5) + (size_t)(f << 5) + (size_t)(t & 31);
+        const float x = (float)v;
+        const uint16_t h = bf16_bits(x);
         hi[i] = h;
-        lo[i] = bf16_bits(f - bf16_value(h));
+        lo[i] = bf16_bits(x - bf16_value(h));
     }
 };
 
@@ -138,8 +148,8 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
     }
     for (int c = 0; c < 3; ++c)
         for (int q = 0; q < 8; ++q)
-            Store<OutT>::put(Xt, Xlo, (size_t)((size_t)c * 8 * H + 8 * h + q) * ld + t, (double)geo[c][q]);
-    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (size_t)((size_t)24 * H + 4 * h + q) * ld + t, (double)col[q]);
+            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
 }
 
 constexpr int kFeatVals = 28;   // chained contributions of one pair to the 28 handle rows
@@ -225,8 +235,8 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
     }
     for (int c = 0; c < 3; ++c)
         for (int q = 0; q < 8; ++q)
-            Store<OutT>::put(Xt, Xlo, (size_t)((size_t)c * 8 * H + 8 * h + q) * ld + t, (double)geo[c][q]);
-    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (size_t)((size_t)24 * H + 4 * h + q) * ld + t, (double)col[q]);
+            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
 }
 
 // Float64 contributions of the listed near (sample, segment) pairs of one tile
@@ -292,7 +302,7 @@ __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x,
     } else {
         b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
     }
-    Store<OutT>::put(Xt, Xlo, (size_t)(row0 + j) * ld + t, b);
+    Store<OutT>::put(Xt, Xlo, row0 + j, t, ld, b);
 }
 
 __global__ void k_gauss_points(int M, int m, double* __restrict__ gx)
@@ -425,7 +435,8 @@ int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
     return check_launch(ctx, "fill");
 }
 
-// Feature rows of npts points into Xt (ld = row stride); rows 0..28H-1 handle
+// Feature rows of npts points into Xt (ld: row stride of float64 / float32 tiles,
+// row count of the blocked bfloat16 tile); rows 0..28H-1 handle
 // features, rows 28H.. beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
 // Mixed precision needs the near-pair list of the whole sample set (nl), the tile's
 // first global sample index t0 (a multiple of 64), the global samples xg and a
@@ -530,6 +541,43 @@ static std::vector<int> gram_tiles(int H, int W, int ts)
     return t;
 }
 
+// Work list of the MFMA Grams: (row tile, column tile, sample part) for every
+// needed tile and part, part-major, then by super-tiles of 4 x 8 output tiles,
+// then row and column.  Consecutive entries share operand panels (the Gram
+// kernels give each XCD a contiguous run of entries).
+static std::vector<int> gram_work(const std::vector<int>& tiles, int parts)
+{
+    const int nt = (int)tiles.size() / 2;
+    std::vector<int> order(nt);
+    for (int t = 0; t < nt; ++t) order[t] = t;
+    auto key = [&](int t) {
+        const int i = tiles[2 * t], j = tiles[2 * t + 1];
+        return std::make_tuple(i / 4, j / 8, i, j);
+    };
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    std::vector<int> w;
+    w.reserve((size_t)3 * nt * parts);
+    for (int p = 0; p < parts; ++p)
+        for (int t : order) {
+            w.push_back(tiles[2 * t]);
+            w.push_back(tiles[2 * t + 1]);
+            w.push_back(p);
+        }
+    return w;
+}
+
+namespace {
+// G[0] += G[1] + ... + G[parts - 1] (fixed order)
+__global__ void k_sum_parts(double* __restrict__ G, int parts, int64_t len)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = G[i];
+        for (int p = 1; p < parts; ++p) v += G[(size_t)p * len + i];
+        G[i] = v;
+    }
+}
+}  // namespace
+
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
             int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre)
 {
@@ -547,21 +595,26 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // sample tile: large for the float64 Gram; for the MFMA Grams small enough that the tile of
     // feature rows (W x T, 4 bytes per entry) stays resident in the last-level cache while every
     // output tile re-reads it
-    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : (gram == BEM_GRAM_FP64 ? 16384 : 8192);
+    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : (gram == BEM_GRAM_FP32_MFMA ? 8192 : 16384);
     const size_t elem = gram == BEM_GRAM_FP64 ? 8 : 4;
     while (T > 1024 && (size_t)W * T * elem > ((size_t)3 << 30)) T /= 2;
     if (T > N) T = N > 0 ? N : 1;
     T = (T + 63) / 64 * 64;
     if (gram == BEM_GRAM_BF16X3_MFMA)
         while (T > 64 && W * T >= ((int64_t)1 << 31)) T = (T / 2 + 63) / 64 * 64;   // 32-bit offsets in the Gram
-    // tmp0: feature tile; tmp1: G [W][W] + R [W][3]; tmp2: residual in f64
+    // split-BF16 Gram: the sample tile is split into 2 parts with partial Grams of their own,
+    // so that a launch has twice the blocks (fewer idle CUs in its last round) and stays
+    // deterministic (no atomics)
+    const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 2 : 1;
+    const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
+    // tmp0: feature tile; tmp1: R [W][3] + G [parts][W][W]; tmp2: residual in f64
     if ((rc = ensure(ctx, ctx->tmp0, (size_t)W * T * elem, s))) return rc;
-    if ((rc = ensure(ctx, ctx->tmp1, ((size_t)W * W + (size_t)W * 3) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp1, ((size_t)parts * W * W + (size_t)W * 3) * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->tmp2, (size_t)(N > 0 ? N : 1) * 3 * sizeof(double), s))) return rc;
-    double* G = (double*)ctx->tmp1.ptr;
-    double* R = G + (size_t)W * W;
+    double* R = (double*)ctx->tmp1.ptr;
+    double* G = R + (size_t)W * 3;
     double* r64 = (double*)ctx->tmp2.ptr;
-    if ((rc = fill_f64(ctx, G, W * W + W * 3, 0.0, s))) return rc;
+    if ((rc = fill_f64(ctx, R, (int64_t)parts * W * W + W * 3, 0.0, s))) return rc;
     if (N > 0) {
         if (mixed)
             hipLaunchKernelGGL(k_to_f64<float>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const float*)resid, 3 * N, r64);
@@ -569,8 +622,9 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)resid, 3 * N, r64);
     }
     const int ts = gram == BEM_GRAM_FP64 ? 64 : (gram == BEM_GRAM_FP32_MFMA ? 128 : 256);
-    const std::vector<int> tiles = gram_tiles(H, (int)W, ts);
-    const int ntiles = (int)tiles.size() / 2;
+    const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(H, (int)W, ts)
+                                                         : gram_work(gram_tiles(H, (int)W, ts), parts);
+    const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
     // tmp5: tile list, then the near-pair corrections of one sample tile
     const size_t tiles_bytes = (tiles.size() * sizeof(int) + 255) / 256 * 256;
     const size_t corr_floats = mixed ? (size_t)((T + 63) / 64) * kWaveSlots * kFeatVals : 0;
@@ -602,15 +656,22 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)ctx->tmp0.ptr;
             if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
-            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
+            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
+                return rc;
             if ((rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
         } else {
             uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
             uint16_t* Xl = Xh + (size_t)W * T;
-            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, T, s, &nl, t0, x, corr))) return rc;
-            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, G, s))) return rc;
+            // blocked layout: ld is the row count
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr))) return rc;
+            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
+                return rc;
             if ((rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
         }
+    }
+    if (parts > 1) {
+        hipLaunchKernelGGL(k_sum_parts, dim3(4096), dim3(256), 0, s, G, parts, W * W);
+        if ((rc = check_launch(ctx, "gram parts"))) return rc;
     }
     // contraction per channel
     const double sc = N > 0 ? 1.0 / (double)N : 0.0;
