@@ -104,20 +104,28 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
 
 // Split-bfloat16 Gram with LDS staging: a block of 8 wavefronts owns a 256x256
 // output tile (wavefront w: rows 64*(w/2).., cols 128*(w%2).., 2x4 MFMA tiles of
-// 32x32).  Each 32-sample stage of the four operand slabs (A hi/lo, B hi/lo,
-// 256 rows x 32 samples) is loaded into registers while the previous stage is
-// multiplied out of LDS, then stored to LDS (rows padded to 40 bf16 so the
-// 16-byte operand reads of 16 consecutive rows hit distinct banks).  The tile
-// is in 32-sample blocks ([t / 32][row][t % 32]), so a stage of a slab is one
-// contiguous 16 KiB run and every 128-byte line fetched is used whole.
-constexpr int G2_T = 256, G2_BK = 32, G2_LD = G2_BK + 8;
+// 32x32).  The tile is in 32-sample blocks ([t / 32][row][t % 32]), so one
+// 32-sample stage of a 256-row operand slab (A hi/lo, B hi/lo) is a contiguous
+// 16 KiB run and every 128-byte line fetched is used whole.  Stages are double
+// buffered in LDS (2 x 64 KiB): while stage k is multiplied out of one buffer,
+// stage k+1 goes from registers into the other and stage k+2 is fetched into
+// registers, with one barrier per stage.  LDS rows are 64 bytes (4 chunks of 8
+// samples); chunk c of row r sits at position c ^ swz(r), swz(r) = ((r >> 1) ^
+// (r >> 2)) & 3, so that the 16-byte operand reads of 16 consecutive rows fall
+// in distinct banks.
+constexpr int G2_T = 256, G2_BK = 32;
+
+__device__ inline int g2_lds(int r, int c)   // element offset of chunk c of row r in one slab
+{
+    return (r << 5) + ((c ^ (((r >> 1) ^ (r >> 2)) & 3)) << 3);
+}
 
 __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl,
                                                          int W, int n_all, const int* __restrict__ work,
                                                          int nwork, int kchunk, double* __restrict__ G,
                                                          int64_t gstride)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sm[4][G2_T * G2_LD];   // A hi, A lo, B hi, B lo
+    __shared__ __attribute__((aligned(16))) uint16_t sm[2][4][G2_T * G2_BK];   // [buffer][A hi, A lo, B hi, B lo]
     const int wi = work_index(nwork);
     if (wi >= nwork) return;
     const int tid = threadIdx.x;
@@ -132,15 +140,26 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
     G += (int64_t)work[3 * wi + 2] * gstride;
     const int wr = wave >> 1, wc = wave & 1;
     // global -> register staging: thread owns 16-byte chunk (tid & 3) of rows tid/4 and tid/4 + 128
-    const int c8 = (tid & 3) * 8;
+    const int cq = tid & 3, c8 = cq * 8;
     const int r_a = tid >> 2;
     const int W32 = W << 5;    // elements per 32-sample block of the tile
     int goff[2][2];            // [A/B][p] element offset of the chunk in a block (row * 32 + c8), -1 outside
+    int soff[2];               // LDS offset of the chunk for p = 0, 1
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const int ra = row0 + r_a + 128 * p, rb = col0 + r_a + 128 * p;
         goff[0][p] = ra < W ? (ra << 5) + c8 : -1;
         goff[1][p] = rb < W ? (rb << 5) + c8 : -1;
+        soff[p] = g2_lds(r_a + 128 * p, cq);
+    }
+    // operand read offsets: rows of this lane, chunk 2 * (ks / 16) + lk
+    int aoff[2][2], boff[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) aoff[h][mi] = g2_lds(wr * 64 + mi * 32 + li, 2 * h + lk);
+#pragma unroll
+        for (int nj = 0; nj < 4; ++nj) boff[h][nj] = g2_lds(wc * 128 + nj * 32 + li, 2 * h + lk);
     }
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     u16x8 stage[2][2][2];      // [A/B][hi/lo][p]
@@ -167,6 +186,31 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
             }                                                                                 \
         }                                                                                     \
     }
+#define G2_STORE_STAGE(BUF)                                                                   \
+    {                                                                                         \
+        _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                      \
+        _Pragma("unroll") for (int hl = 0; hl < 2; ++hl)                                      \
+        _Pragma("unroll") for (int p = 0; p < 2; ++p)                                         \
+            *(u16x8*)&sm[BUF][2 * ab + hl][soff[p]] = stage[ab][hl][p];                       \
+    }
+// multiply half h (samples 16h .. 16h + 15) of the stage in buffer BUF
+#define G2_MULTIPLY(BUF, h)                                                                   \
+    {                                                                                         \
+        bf16x8 ah[2], al[2];                                                                  \
+        _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                    \
+            ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][0][aoff[h][mi]]);     \
+            al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][1][aoff[h][mi]]);     \
+        }                                                                                     \
+        _Pragma("unroll") for (int nj = 0; nj < 4; ++nj) {                                    \
+            const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][2][boff[h][nj]]); \
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][3][boff[h][nj]]); \
+            _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                \
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0); \
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0); \
+                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh, acc[mi][nj], 0, 0, 0); \
+            }                                                                                 \
+        }                                                                                     \
+    }
     floatx16 acc[2][4];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -175,41 +219,30 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
     G2_LOAD_STAGE(kb)
-    for (int k0 = kb; k0 < n; k0 += G2_BK) {
-        __syncthreads();                                  // previous stage fully consumed
-#pragma unroll
-        for (int ab = 0; ab < 2; ++ab)
-#pragma unroll
-            for (int hl = 0; hl < 2; ++hl)
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-                    *(u16x8*)&sm[2 * ab + hl][(r_a + 128 * p) * G2_LD + c8] = stage[ab][hl][p];
-        __syncthreads();
-        if (k0 + G2_BK < n) G2_LOAD_STAGE(k0 + G2_BK)    // in flight during the MFMAs below
-#pragma unroll
-        for (int ks = 0; ks < G2_BK; ks += 16) {
-            const int kc = ks + 8 * lk;
-            bf16x8 ah[2], al[2];
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi) {
-                const int r = wr * 64 + mi * 32 + li;
-                ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[0][r * G2_LD + kc]);
-                al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[1][r * G2_LD + kc]);
-            }
-#pragma unroll
-            for (int nj = 0; nj < 4; ++nj) {
-                const int r = wc * 128 + nj * 32 + li;
-                const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[2][r * G2_LD + kc]);
-                const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[3][r * G2_LD + kc]);
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi) {
-                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0);
-                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0);
-                    acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh, acc[mi][nj], 0, 0, 0);
-                }
-            }
+    G2_STORE_STAGE(0)
+    if (kb + G2_BK < n) G2_LOAD_STAGE(kb + G2_BK)
+    __syncthreads();
+    // stage k0 is in buffer it & 1 (loop unrolled by two so the buffer index is constant)
+    for (int k0 = kb; k0 < n; k0 += 2 * G2_BK) {
+        G2_MULTIPLY(0, 0)
+        if (k0 + G2_BK < n) {
+            G2_STORE_STAGE(1)
+            if (k0 + 2 * G2_BK < n) G2_LOAD_STAGE(k0 + 2 * G2_BK)
         }
+        G2_MULTIPLY(0, 1)
+        __syncthreads();
+        if (k0 + G2_BK >= n) break;
+        G2_MULTIPLY(1, 0)
+        if (k0 + 2 * G2_BK < n) {
+            G2_STORE_STAGE(0)
+            if (k0 + 3 * G2_BK < n) G2_LOAD_STAGE(k0 + 3 * G2_BK)
+        }
+        G2_MULTIPLY(1, 1)
+        __syncthreads();
     }
+#undef G2_LOAD_STAGE
+#undef G2_STORE_STAGE
+#undef G2_MULTIPLY
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
