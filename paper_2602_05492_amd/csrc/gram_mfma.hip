@@ -255,24 +255,15 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
             }
 }
 
-// R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; X float rows of stride ld, or the
-// blocked bf16 hi + lo tile with ld = its row count)
-template <bool Bf16>
-__global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const uint16_t* __restrict__ Xlo, int64_t ld,
-                                            int64_t n, const double* __restrict__ r, double* __restrict__ R)
+// R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; float rows of stride ld)
+__global__ void __launch_bounds__(256) k_xr_f32(const float* __restrict__ X, int64_t ld, int64_t n,
+                                                const double* __restrict__ r, double* __restrict__ R)
 {
     __shared__ double red[3][256];
     const int64_t f = blockIdx.x;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
-        double v;
-        if (Bf16) {
-            const int64_t i = (t >> 5) * (ld << 5) + (f << 5) + (t & 31);
-            const uint16_t h = ((const uint16_t*)Xhi)[i], l = Xlo[i];
-            v = (double)__uint_as_float((uint32_t)h << 16) + (double)__uint_as_float((uint32_t)l << 16);
-        } else {
-            v = (double)((const float*)Xhi)[f * ld + t];
-        }
+        const double v = (double)X[f * ld + t];
         s0 += v * r[3 * t]; s1 += v * r[3 * t + 1]; s2 += v * r[3 * t + 2];
     }
     red[0][threadIdx.x] = s0; red[1][threadIdx.x] = s1; red[2][threadIdx.x] = s2;
@@ -284,6 +275,58 @@ __global__ void __launch_bounds__(256) k_xr(const void* __restrict__ Xhi, const 
     }
     if (threadIdx.x == 0)
         for (int c = 0; c < 3; ++c) R[f * 3 + c] += red[c][0];
+}
+
+// Blocked split-bfloat16 tile: partial sums over sample-block group g,
+// Rp[g][f][c] = sum over the group's samples of (hi + lo)[f][t] r[t][c].  A
+// wavefront reads 16 rows x 4 chunks of 8 samples of one 32-sample block (1 KiB
+// contiguous); the 4 chunk lanes of a row are summed by shuffles.
+constexpr int kXrGroups = kXrPartials;
+
+__global__ void __launch_bounds__(256) k_xr_bf16(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl, int W,
+                                                 int64_t n, int64_t blocks_per_group, const double* __restrict__ r,
+                                                 double* __restrict__ Rp)
+{
+    const int lane = threadIdx.x & 63;
+    const int f = blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + (lane >> 2);
+    const int cq = lane & 3;
+    const int64_t nb = (n + 31) / 32;
+    const int64_t b0 = (int64_t)blockIdx.y * blocks_per_group;
+    const int64_t b1 = b0 + blocks_per_group < nb ? b0 + blocks_per_group : nb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (f < W) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const size_t i = (size_t)b * ((size_t)W << 5) + ((size_t)f << 5) + (size_t)(cq << 3);
+            const u16x8 h = *(const u16x8*)(Xh + i);
+            const u16x8 l = *(const u16x8*)(Xl + i);
+            const int64_t t0 = b * 32 + cq * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t t = t0 + e;
+                if (t < n) {
+                    const double v = (double)__uint_as_float((uint32_t)h[e] << 16) +
+                                     (double)__uint_as_float((uint32_t)l[e] << 16);
+                    s0 += v * r[3 * t]; s1 += v * r[3 * t + 1]; s2 += v * r[3 * t + 2];
+                }
+            }
+        }
+    }
+    s0 += __shfl_xor(s0, 1); s1 += __shfl_xor(s1, 1); s2 += __shfl_xor(s2, 1);
+    s0 += __shfl_xor(s0, 2); s1 += __shfl_xor(s1, 2); s2 += __shfl_xor(s2, 2);
+    if (cq == 0 && f < W) {
+        double* o = Rp + ((size_t)blockIdx.y * W + f) * 3;
+        o[0] = s0; o[1] = s1; o[2] = s2;
+    }
+}
+
+// R[f][c] += sum_g Rp[g][f][c] (fixed order)
+__global__ void k_xr_finish(const double* __restrict__ Rp, int W, int groups, double* __restrict__ R)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * W) return;
+    double v = 0.0;
+    for (int g = 0; g < groups; ++g) v += Rp[(size_t)g * 3 * W + i];
+    R[i] += v;
 }
 
 }  // namespace
@@ -312,20 +355,21 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
     return check_launch(ctx, "gram_mfma");
 }
 
+// R += X r over one sample tile; Rp is a workspace of kXrGroups * W * 3 doubles (split-BF16 only).
 int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-              const double* r, double* R, hipStream_t s)
+              const double* r, double* R, double* Rp, hipStream_t s)
 {
     if (n <= 0) return BEM_OK;
-    if (gram == BEM_GRAM_BF16X3_MFMA)
-        {
-            ProfScope ps_(ctx, PT_XR, s);
-            hipLaunchKernelGGL(k_xr<true>, dim3(W), dim3(256), 0, s, Xhi, Xlo, (int64_t)W, n, r, R);
-        }
-    else
-        {
-            ProfScope ps_(ctx, PT_XR, s);
-            hipLaunchKernelGGL(k_xr<false>, dim3(W), dim3(256), 0, s, Xhi, Xlo, ld, n, r, R);
-        }
+    ProfScope ps_(ctx, PT_XR, s);
+    if (gram == BEM_GRAM_BF16X3_MFMA) {
+        const int64_t nb = (n + 31) / 32;
+        const int64_t per = (nb + kXrGroups - 1) / kXrGroups;
+        hipLaunchKernelGGL(k_xr_bf16, dim3((W + 63) / 64, kXrGroups), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, W, n,
+                           per, r, Rp);
+        hipLaunchKernelGGL(k_xr_finish, dim3((3 * W + 255) / 256), dim3(256), 0, s, (const double*)Rp, W, kXrGroups, R);
+    } else {
+        hipLaunchKernelGGL(k_xr_f32, dim3(W), dim3(256), 0, s, (const float*)Xhi, ld, n, r, R);
+    }
     return check_launch(ctx, "xr");
 }
 

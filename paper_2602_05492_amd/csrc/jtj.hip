@@ -602,20 +602,25 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     T = (T + 63) / 64 * 64;
     if (gram == BEM_GRAM_BF16X3_MFMA)
         while (T > 64 && W * T >= ((int64_t)1 << 31)) T = (T / 2 + 63) / 64 * 64;   // 32-bit offsets in the Gram
-    // split-BF16 Gram: the sample tile is split into 2 parts with partial Grams of their own,
-    // so that a launch has twice the blocks (fewer idle CUs in its last round) and stays
+    // split-BF16 Gram: the sample tile is split into 3 parts with partial Grams of their own,
+    // so that a launch has 3x the blocks (fewer idle CUs in its last round) and stays
     // deterministic (no atomics)
-    const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 2 : 1;
+    const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 3 : 1;
     const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
-    // tmp0: feature tile; tmp1: R [W][3] + G [parts][W][W]; tmp2: residual in f64
+    // tmp0: feature tile; tmp1: R [W][3] + G [parts][W][W] + X r partials; tmp2: residual in f64
     if ((rc = ensure(ctx, ctx->tmp0, (size_t)W * T * elem, s))) return rc;
-    if ((rc = ensure(ctx, ctx->tmp1, ((size_t)parts * W * W + (size_t)W * 3) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp1,
+                     ((size_t)parts * W * W + (size_t)W * 3 + (size_t)kXrPartials * W * 3) * sizeof(double), s)))
+        return rc;
     if ((rc = ensure(ctx, ctx->tmp2, (size_t)(N > 0 ? N : 1) * 3 * sizeof(double), s))) return rc;
     double* R = (double*)ctx->tmp1.ptr;
     double* G = R + (size_t)W * 3;
+    double* Rp = G + (size_t)parts * W * W;
     double* r64 = (double*)ctx->tmp2.ptr;
     if ((rc = fill_f64(ctx, R, (int64_t)parts * W * W + W * 3, 0.0, s))) return rc;
-    if (N > 0) {
+    // Jtr == nullptr: J^T J only (the LM step takes its gradient from the adjoint)
+    const bool want_r = Jtr != nullptr;
+    if (N > 0 && want_r) {
         if (mixed)
             hipLaunchKernelGGL(k_to_f64<float>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const float*)resid, 3 * N, r64);
         else
@@ -651,14 +656,15 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
             }
             if (rc) return rc;
-            if ((rc = gemm_f64(ctx, (int)W, 3, (int)n, 1.0, Xt, T, false, r64 + 3 * t0, 3, false, 1.0, R, 3, s, nullptr, 0)))
+            if (want_r &&
+                (rc = gemm_f64(ctx, (int)W, 3, (int)n, 1.0, Xt, T, false, r64 + 3 * t0, 3, false, 1.0, R, 3, s, nullptr, 0)))
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)ctx->tmp0.ptr;
             if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
                 return rc;
-            if ((rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
         } else {
             uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
             uint16_t* Xl = Xh + (size_t)W * T;
@@ -666,7 +672,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
                 return rc;
-            if ((rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, s))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
         }
     }
     if (parts > 1) {
@@ -676,7 +682,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // contraction per channel
     const double sc = N > 0 ? 1.0 / (double)N : 0.0;
     if ((rc = fill_f64(ctx, JtJ, P * P, 0.0, s))) return rc;
-    if ((rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
+    if (want_r && (rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
     const size_t wc2 = (size_t)Wc * Wc;
     const size_t szc = (size_t)M * n12;
     if ((rc = ensure(ctx, ctx->tmp2, (wc2 + szc + 2 * (size_t)n12 * n12 + (size_t)M * n12 + (size_t)(N > 0 ? N : 1) * 3) *
@@ -700,7 +706,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         // T2 = Zc^T W1
         if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Zc, n12, true, W1, n12, false, 0.0, T2, n12, s, nullptr, 0))) return rc;
         hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, T1, T2, H, c, sc, JtJ, P);
-        hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, H, M, c, sc, Jtr);
+        if (want_r)
+            hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, H, M, c, sc, Jtr);
         if ((rc = check_launch(ctx, "scatter"))) return rc;
     }
     return BEM_OK;

@@ -119,7 +119,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     const int64_t P = 20 * (int64_t)H;
     const size_t ue = mixed ? sizeof(float) : sizeof(double);
     const int64_t n3 = 3 * (N > 0 ? N : 1);
-    // lm workspace layout (ctx->lmw): u | r | g | JtJ | Jtr | A | delta | theta' | partials | flag
+    // lm workspace layout (ctx->lmw): u | r | g | JtJ | (spare P) | A | delta | theta' | partials | flag
     const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)20 * H +
                                                  3 * (size_t)kRedBlocks + 8) * sizeof(double) + 64;
     if ((rc = ensure(ctx, ctx->lmw, bytes, s))) return rc;
@@ -128,8 +128,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     void* r = base + (size_t)n3 * ue;
     double* g = (double*)(base + 2 * (size_t)n3 * ue);
     double* JtJ = g + P;
-    double* Jtr = JtJ + (size_t)P * P;
-    double* A = Jtr + P;
+    double* A = JtJ + (size_t)P * P + P;
     double* delta = A + (size_t)P * P;
     double* th1 = delta + P;
     double* dpart = th1 + (size_t)20 * H;
@@ -168,7 +167,8 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     // gradient by the adjoint, Hessian by the normal equations
     if ((rc = run_vjp(ctx, theta, H, x, N, r, mixed, g, s, mixed ? &nl : nullptr))) return rc;
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / (double)N);
-    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, Jtr, s, mixed ? &nl : nullptr))) return rc;
+    // the step's right-hand side is the adjoint gradient above, so J^T r is not formed
+    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr))) return rc;
     // damped Cholesky, raising lambda until it factors
     double lam = st->lambda;
     for (int attempt = 0;; ++attempt) {
