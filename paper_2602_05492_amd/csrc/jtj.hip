@@ -166,7 +166,8 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
                                                       float near2, const NearPair* __restrict__ list,
                                                       const int* __restrict__ wave_count,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
-                                                      OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
+                                                      const float* __restrict__ vtab, OutT* __restrict__ Xt,
+                                                      uint16_t* __restrict__ Xlo, int64_t ld)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = blockIdx.y;
@@ -194,20 +195,20 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
                                                           s32[kWcA + c], s32[kWcB + c]);
                     va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
                 }
-                const float ta = (float)j / (float)S, tb = (float)(j + 1) / (float)S;
-                col[0] += m.da * (1.0f - ta) + m.db * (1.0f - tb);
+                const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
+                const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
+                col[0] += m.da * sa_ + m.db * sb_;
                 col[1] += m.da * ta + m.db * tb;
-                col[2] += m.sa * (1.0f - ta) + m.sb * (1.0f - tb);
+                col[2] += m.sa * sa_ + m.sb * sb_;
                 col[3] += m.sa * ta + m.sb * tb;
             }
         }
-        double B[4];
-        bernstein3((double)j / (double)S, B);
+        const float* B = vtab + 8 * j;
         for (int c = 0; c < 3; ++c) {
             const float gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
             for (int q = 0; q < 4; ++q) {
-                geo[c][2 * q] += (float)B[q] * gx;
-                geo[c][2 * q + 1] += (float)B[q] * gy;
+                geo[c][2 * q] += B[q] * gx;
+                geo[c][2 * q + 1] += B[q] * gy;
             }
             pv[c][0] = vb[c][0];
             pv[c][1] = vb[c][1];
@@ -237,6 +238,21 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
         for (int q = 0; q < 8; ++q)
             Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
     for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
+}
+
+// Vertex table of the float32 feature kernel: vtab[8 j + q] = B_q(t_j) (cubic
+// Bernstein weights), vtab[8 j + 4] = t_j, vtab[8 j + 5] = 1 - t_j, t_j = j / S.
+__global__ void k_vertex_table(int S, float* __restrict__ vtab)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > S) return;
+    const double t = (double)j / (double)S;
+    double B[4];
+    bernstein3(t, B);
+    for (int q = 0; q < 4; ++q) vtab[8 * j + q] = (float)B[q];
+    vtab[8 * j + 4] = (float)t;
+    vtab[8 * j + 5] = (float)(1.0 - t);
+    vtab[8 * j + 6] = vtab[8 * j + 7] = 0.0f;
 }
 
 // Float64 contributions of the listed near (sample, segment) pairs of one tile
@@ -444,7 +460,7 @@ int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
 template <class OutT>
 static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
                            uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
-                           const double* xg = nullptr, float* corr = nullptr)
+                           const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -452,7 +468,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const double nf = 2.0 * ctx->opts.near_factor;
     const float near2 = (float)(nf * nf);
     const dim3 grid(blocks_for(npts, 256), H);
-    if (mixed && (!nl || !xg || !corr || (t0 & 63)))
+    if (mixed && (!nl || !xg || !corr || !vtab || (t0 & 63)))
         return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
     if (H > 0) {
         if (mixed) {
@@ -465,7 +481,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             }
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
-                               H, S, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, Xt, Xlo, ld);
+                               H, S, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo, ld);
             hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, nl->flag + t0, Xt, Xlo,
                                ld);
@@ -630,11 +646,15 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(H, (int)W, ts)
                                                          : gram_work(gram_tiles(H, (int)W, ts), parts);
     const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
-    // tmp5: tile list, then the near-pair corrections of one sample tile
+    // tmp5: tile list, the vertex table, then the near-pair corrections of one sample tile
+    const int S = ctx->opts.segs_per_handle;
     const size_t tiles_bytes = (tiles.size() * sizeof(int) + 255) / 256 * 256;
+    const size_t vtab_bytes = ((size_t)(S + 1) * 8 * sizeof(float) + 255) / 256 * 256;
     const size_t corr_floats = mixed ? (size_t)((T + 63) / 64) * kWaveSlots * kFeatVals : 0;
-    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + corr_floats * sizeof(float) + 256, s))) return rc;
-    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes) : nullptr;
+    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + vtab_bytes + corr_floats * sizeof(float) + 256, s))) return rc;
+    float* vtab = (float*)((char*)ctx->tmp5.ptr + tiles_bytes);
+    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes) : nullptr;
+    hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, vtab);
     NearList nl{};
     if (mixed && N > 0) {
         if (pre) nl = *pre;
@@ -650,7 +670,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         const double* xt = x + 2 * t0;
         if (gram == BEM_GRAM_FP64) {
             double* Xt = (double*)ctx->tmp0.ptr;
-            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
+            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
@@ -661,7 +681,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)ctx->tmp0.ptr;
-            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr))) return rc;
+            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
                 return rc;
             if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
@@ -669,7 +689,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
-            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr))) return rc;
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab))) return rc;
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
                 return rc;
             if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
