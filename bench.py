@@ -17,6 +17,7 @@ the same workload and extrapolates linearly.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sample×segment pairs/s and LM steps/s, FP32-mixed vs FP64 at 1e-4 color err"
 PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15}
+# HBM byte counters of the split-BF16 Gram kernel, taken with rocprofv3 --pmc on the
+# --pmc-probe run (two sample tiles of the LM workload plus a 256 MiB copy for calibration)
+PMC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_lm_workload_pmc.json")
+CSRC = os.path.join(ROOT, "paper_2602_05492_amd", "csrc")
+GRAM_SOURCES = ["gram_mfma.hip"]
+SWEEP_SOURCES = ["sweep_mixed.hip", "sweep_common.hpp", "seg_math.hpp"]
+
+
+def sources_sha(names) -> str:
+    h = hashlib.sha256()
+    for nm in names:
+        h.update(open(os.path.join(CSRC, nm), "rb").read())
+    return h.hexdigest()
+
+
+def pmc_record():
+    try:
+        return json.load(open(PMC_FILE))
+    except (OSError, ValueError):
+        return None
 # algorithmic work per unit (float32 flops, FMA = 2)
 F_HANDLE_PAIR = 110.0      # forward: one sample x one handle segment
 F_BOUNDARY_PAIR = 40.0     # forward / adjoint: one sample x one outer element
@@ -37,6 +58,47 @@ def gram_entries(H: int, M: int) -> int:
     """Distinct Gram entries J^T J needs per sample (symmetric blocks counted once)."""
     g, s = 8 * H, 4 * H + M
     return 3 * (g * (g + 1) // 2) + 3 * g * s + s * (s + 1) // 2
+
+
+def gram_traffic(samples_per_launch: int):
+    """HBM bytes per Gram launch from the committed counter run, or None when there is none
+    or the kernel source has changed since it was taken."""
+    rec = pmc_record()
+    g = rec.get("gram") if rec else None
+    if not g or g.get("source_sha256") != sources_sha(GRAM_SOURCES) or g.get("samples_per_dispatch") != samples_per_launch:
+        return None
+    return 1024.0 * (g["fetch_kib_per_dispatch"] * rec["fetch_scale"] + g["write_kib_per_dispatch"] * rec["write_scale"])
+
+
+def sweep_flops_per_pair():
+    """float32 flops per sample x segment pair of the mixed forward sweep (VALU FLOPS counters of
+    the committed counter run), or None when the sweep source has changed since."""
+    rec = pmc_record()
+    sw = rec.get("sweep") if rec else None
+    if not sw or sw.get("source_sha256") != sources_sha(SWEEP_SOURCES):
+        return None
+    return sw["fp32_flops_per_pair"]
+
+
+def pmc_probe() -> int:
+    """Small run for byte counters: J^T J on two 16,384-sample tiles of the LM workload, then a
+    plain 256 MiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    from paper_2602_05492_amd import bem as B
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(5)
+    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
+    n = 2 * 16384
+    x = torch.from_numpy(wl.samples(0)[:n]).cuda()
+    r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
+    ctx.eval(torch.from_numpy(wl.theta0).cuda(), x, wl.cbar_true, "mixed")
+    ctx.jtj(torch.from_numpy(wl.theta0).cuda(), x, r, "bf16x3_mfma", "mixed")
+    a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("pmc probe done", flush=True)
+    return 0
 
 
 def cpu_baseline(wl, x_host, budget_note: str) -> dict:
@@ -83,7 +145,10 @@ def main() -> int:
     ap.add_argument("--gram", default="bf16x3_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
     ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
     args = ap.parse_args()
+    if args.pmc_probe:
+        return pmc_probe()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built "
@@ -154,13 +219,24 @@ def main() -> int:
     tot_ms, launches = timed[dom]
     achieved = work[dom] / (tot_ms * 1e-3) / 1e12
     bound, peak = peak_of[dom]
+    traffic = gram_traffic(16384) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma") else None
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / (peak / 1e12), "traffic": None, "launches": launches,
+                "frac": achieved / (peak / 1e12), "traffic": traffic, "launches": launches,
                 "avg_launch_ms": tot_ms / launches}
     fwd_ms = prof["sweep_mixed" if args.prec == "mixed" else "sweep_f64"]
     pairs_fwd = (N * (K + M)) / (fwd_ms[0] / fwd_ms[1] * 1e-3) if fwd_ms[1] else None
     vjp_ms = prof["vjp_segments"][0] + prof["vjp_elements"][0]
     pairs_vjp = steps * (N * (K + M)) / (vjp_ms * 1e-3) if vjp_ms > 0 else None
+
+    # forward sweep against the float32 vector peak (packed FP32 counts twice; without it the
+    # vector ceiling is half of that)
+    fpp = sweep_flops_per_pair() if args.prec == "mixed" else None
+    sweep_valu = None
+    if fpp and pairs_fwd:
+        tf = fpp * pairs_fwd / 1e12
+        sweep_valu = {"kernel": "sweep_mixed", "pairs_per_s": pairs_fwd, "fp32_flops_per_pair": fpp, "achieved": tf,
+                      "unit": "TFLOP/s", "peak": PEAKS["fp32_vector"] / 1e12, "frac": tf / (PEAKS["fp32_vector"] / 1e12),
+                      "frac_of_unpacked_peak": tf / (PEAKS["fp32_vector"] / 2e12)}
 
     speedup = None
     fp64_ms = None
@@ -192,7 +268,7 @@ def main() -> int:
         "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
         "fp64_gpu_ms_per_step": fp64_ms, "speedup_vs_fp64_gpu": speedup,
         "kernel_ms_per_step": {k: v[0] / steps for k, v in timed.items()},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "sweep_valu": sweep_valu, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
