@@ -164,10 +164,11 @@ __global__ void __launch_bounds__(256) k_vjp_elements(const double* __restrict__
     }
 }
 
-// Float64 adjoint of one near (sample, segment) pair, added into segsum[seg][16].
-__device__ inline void near_segment_adjoint(const double* __restrict__ s, double X, double Y, double g0, double g1,
-                                            double g2, double eps2, double* __restrict__ o)
+// Float64 adjoint of one near (sample, segment) pair: the 16 per-segment sums of the pair in a[].
+__device__ inline void near_segment_values(const double* __restrict__ s, double X, double Y, double g0, double g1,
+                                           double g2, double eps2, double* __restrict__ a)
 {
+    for (int v = 0; v < kV; ++v) a[v] = 0.0;
     const SegGeom<double> g = load_geom(s);
     if (g.L2 == 0.0) return;
     const double wa = g0 * s[kWdA] + g1 * s[kWdA + 1] + g2 * s[kWdA + 2];
@@ -175,9 +176,15 @@ __device__ inline void near_segment_adjoint(const double* __restrict__ s, double
     const double sa = g0 * s[kWcA] + g1 * s[kWcA + 1] + g2 * s[kWcA + 2];
     const double sb = g0 * s[kWcB] + g1 * s[kWcB + 1] + g2 * s[kWcB + 2];
     const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
-    double a[kV];
-    for (int v = 0; v < kV; ++v) a[v] = 0.0;
     add_pair(a, pair_backward(g, st, eps2, wa, wb, sa, sb), pair_moments(g, st), g0, g1, g2);
+}
+
+// Same, added into segsum[seg][16] (atomics).
+__device__ inline void near_segment_adjoint(const double* __restrict__ s, double X, double Y, double g0, double g1,
+                                            double g2, double eps2, double* __restrict__ o)
+{
+    double a[kV];
+    near_segment_values(s, X, Y, g0, g1, g2, eps2, a);
     for (int v = 0; v < kV; ++v) atomicAdd(o + v, a[v]);
 }
 
@@ -191,9 +198,12 @@ __device__ inline void near_element_adjoint(const double* __restrict__ e, double
     atomicAdd(o + 2, b * g2);
 }
 
-// Listed near pairs of the mixed adjoint (thread per list slot).  Pairs of flagged
-// samples are left to k_vjp_flagged, which redoes all near pairs of such a sample.
-// Results land in one extra partial row of each fixed-order reduction.
+// Listed near pairs of the mixed adjoint (thread per list slot; a wavefront covers
+// 64 consecutive slots of one slice).  Entries of a slice are sorted by segment, so
+// the wavefront first sums equal segments by a segmented scan over its lanes and
+// one lane per segment adds the sums (atomics into one extra partial row of each
+// fixed-order reduction).  Pairs of flagged samples are left to k_vjp_flagged,
+// which redoes all near pairs of such a sample.
 __global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ list, const int* __restrict__ wave_count,
                                                   const uint8_t* __restrict__ flag, int64_t nslots,
                                                   const double* __restrict__ x, const float* __restrict__ gbar,
@@ -201,19 +211,51 @@ __global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ l
                                                   const double* __restrict__ el64, double eps2,
                                                   double* __restrict__ segsum, double* __restrict__ psisum)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nslots) return;
-    if ((int)(t % kWaveSlots) >= wave_count[t / kWaveSlots]) return;
-    const NearPair p = list[t];
-    const int64_t i = p.sample;
-    if (flag[i]) return;
-    const double X = x[2 * i], Y = x[2 * i + 1];
-    const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
-    if (p.seg < K)
-        near_segment_adjoint(seg64 + (size_t)p.seg * kSegStride, X, Y, g0, g1, g2, eps2, segsum + (size_t)p.seg * kV);
-    else
-        near_element_adjoint(el64 + (size_t)(p.seg - K) * kElemStride, X, Y, g0, g1, g2,
-                             psisum + 3 * (size_t)(p.seg - K));
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // nslots is a multiple of the block size
+    const int e = (int)(t % kWaveSlots);
+    const int cnt = wave_count[t / kWaveSlots];
+    if ((e & ~63) >= cnt) return;                     // the whole wavefront lies past the slice's entries
+    const int lane = threadIdx.x & 63;
+    constexpr int kNone = 0x7fffffff;                 // key of an empty slot: after every entry
+    double v[kV];
+    for (int c = 0; c < kV; ++c) v[c] = 0.0;
+    int key = kNone;
+    if (e < cnt && t < nslots) {
+        const NearPair p = list[t];
+        key = p.seg;
+        const int64_t i = p.sample;
+        if (!flag[i]) {
+            const double X = x[2 * i], Y = x[2 * i + 1];
+            const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
+            if (p.seg < K) {
+                near_segment_values(seg64 + (size_t)p.seg * kSegStride, X, Y, g0, g1, g2, eps2, v);
+            } else {
+                const double* el = el64 + (size_t)(p.seg - K) * kElemStride;
+                const double b = element_beta<double, DevF64>(el[0], el[1], el[2], el[3], X, Y);
+                v[0] = b * g0; v[1] = b * g1; v[2] = b * g2;
+            }
+        }
+    }
+    // inclusive segmented scan: after the step with offset o, v holds the sum over the lanes
+    // (l - 2o, l] with the same key (keys ascend along the lanes)
+    for (int o = 1; o < 64; o <<= 1) {
+        const int ko = __shfl_up(key, o);
+        const bool take = lane >= o && ko == key;
+        for (int c = 0; c < kV; ++c) {
+            const double w = __shfl_up(v[c], o);
+            if (take) v[c] += w;
+        }
+    }
+    const int kn = __shfl_down(key, 1);
+    if ((lane == 63 || kn != key) && key != kNone) {
+        if (key < K) {
+            double* o = segsum + (size_t)key * kV;
+            for (int c = 0; c < kV; ++c) atomicAdd(o + c, v[c]);
+        } else {
+            double* o = psisum + 3 * (size_t)(key - K);
+            for (int c = 0; c < 3; ++c) atomicAdd(o + c, v[c]);
+        }
+    }
 }
 
 // Every near pair of each flagged sample (thread per sample; flagged samples are rare).
