@@ -48,6 +48,8 @@ def pmc_record():
         return json.load(open(PMC_FILE))
     except (OSError, ValueError):
         return None
+
+
 # algorithmic work per unit (float32 flops, FMA = 2)
 F_HANDLE_PAIR = 110.0      # forward: one sample x one handle segment
 F_BOUNDARY_PAIR = 40.0     # forward / adjoint: one sample x one outer element
@@ -101,6 +103,39 @@ def pmc_probe() -> int:
     return 0
 
 
+def lm_curve(steps: int, gram: str, prec: str) -> int:
+    """LM iterations of the LM workload with fresh samples per step; one JSON line per step."""
+    import numpy as np
+    import torch
+    from paper_2602_05492_amd import bem as B
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(5)
+    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
+    tht = torch.from_numpy(wl.theta_true).cuda()
+    c = (np.arange(512) + 0.5) / 512
+    grid = torch.from_numpy(np.stack(np.meshgrid(c, c, indexing="xy"), -1).reshape(-1, 2).copy()).cuda()
+    truth = ctx.eval(tht, grid, wl.cbar_true, "fp64")
+    theta = torch.from_numpy(wl.theta0).cuda()
+    st = B.new_lm_state(wl.lam0, 0)
+
+    def rmse(cbar):
+        u = ctx.eval(theta, grid, tuple(cbar), "fp64")
+        return float(torch.sqrt(((u - truth) ** 2).mean()))
+
+    for i in range(steps):
+        x = torch.from_numpy(wl.samples(i)).cuda()
+        T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(i)).cuda()
+        if i == 0:   # the start, with the mean colour the first step will use
+            print(json.dumps({"step": 0, "rmse": rmse(T.mean(0).tolist())}), flush=True)
+        t = time.perf_counter()
+        ctx.lm_step(theta, x, T, st, gram, prec)
+        torch.cuda.synchronize()
+        print(json.dumps({"step": i + 1, "loss_before": st.loss_before, "loss_after": st.loss_after,
+                          "accepted": int(st.accepted), "lambda": st.lam, "ms": (time.perf_counter() - t) * 1e3,
+                          "rmse": rmse(st.cbar)}), flush=True)
+    return 0
+
+
 def cpu_baseline(wl, x_host, budget_note: str) -> dict:
     """Time the FP64 oracle on bounded pieces of one LM step and extrapolate to the full step."""
     import numpy as np
@@ -146,9 +181,14 @@ def main() -> int:
     ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
+    ap.add_argument("--lm-curve", type=int, default=0,
+                    help="instead of timing: run this many LM steps (fresh samples each) and print loss, lambda and "
+                         "RMSE against the noise-free truth on the 512 x 512 pixel-centre grid per step")
     args = ap.parse_args()
     if args.pmc_probe:
         return pmc_probe()
+    if args.lm_curve:
+        return lm_curve(args.lm_curve, args.gram, args.prec)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built "
@@ -240,6 +280,7 @@ def main() -> int:
 
     speedup = None
     fp64_ms = None
+    step_err = None
     if args.fp64_ref and args.prec == "mixed":
         th64 = torch.from_numpy(wl.theta0).cuda()
         st64 = B.new_lm_state(wl.lam0, 0)
@@ -251,6 +292,17 @@ def main() -> int:
         speedup = fp64_ms / ms
         print(f"fp64 reference step: {fp64_ms:.1f} ms (loss {st64.loss_before:.6e} -> {st64.loss_after:.6e})",
               file=sys.stderr, flush=True)
+        # step direction of the reduced-precision Grams against the FP64 step (same batch, same start)
+        step_err = {}
+        d64 = (th64 - torch.from_numpy(wl.theta0).cuda()).flatten()
+        for gm in ["bf16x3_mfma", "fp32_mfma"]:
+            thg = torch.from_numpy(wl.theta0).cuda()
+            stg = B.new_lm_state(wl.lam0, 0)
+            ctx.lm_step(thg, batches[0][0], batches[0][1], stg, gm, "mixed")
+            dg = (thg - torch.from_numpy(wl.theta0).cuda()).flatten()
+            step_err[gm] = (float(torch.linalg.vector_norm(dg - d64) / torch.linalg.vector_norm(d64))
+                            if (st64.accepted and stg.accepted) else None)
+        print(f"step direction vs fp64: {step_err}", file=sys.stderr, flush=True)
 
     cpu = None
     if args.cpu_baseline:
@@ -267,6 +319,7 @@ def main() -> int:
                    "prec": args.prec, "gram": args.gram, "parallelism": "single GPU"},
         "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
         "fp64_gpu_ms_per_step": fp64_ms, "speedup_vs_fp64_gpu": speedup,
+        "step_direction_rel_err_vs_fp64": step_err,
         "kernel_ms_per_step": {k: v[0] / steps for k, v in timed.items()},
         "sweep_valu": sweep_valu, "roofline": roofline, "cpu_baseline": cpu,
     }
