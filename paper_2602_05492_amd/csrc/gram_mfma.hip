@@ -104,15 +104,17 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
 
 // Split-bfloat16 Gram with LDS staging: a block of 8 wavefronts owns a 256x256
 // output tile (wavefront w: rows 64*(w/2).., cols 128*(w%2).., 2x4 MFMA tiles of
-// 32x32).  The tile is in 32-sample blocks ([t / 32][row][t % 32]), so one
-// 32-sample stage of a 256-row operand slab (A hi/lo, B hi/lo) is a contiguous
-// 16 KiB run and every 128-byte line fetched is used whole.  Stages are double
-// buffered in LDS (2 x 64 KiB): while stage k is multiplied out of one buffer,
-// stage k+1 goes from registers into the other and stage k+2 is fetched into
-// registers, with one barrier per stage.  LDS rows are 64 bytes (4 chunks of 8
-// samples); chunk c of row r sits at position c ^ swz(r), swz(r) = ((r >> 1) ^
-// (r >> 2)) & 3, so that the 16-byte operand reads of 16 consecutive rows fall
-// in distinct banks.
+// 32x32).  The tile is in 32-sample blocks ([t / 32][row][t % 32], zero beyond
+// the last sample), so one 32-sample stage of a 256-row operand slab (A hi/lo,
+// B hi/lo) is a contiguous 16 KiB run and every 128-byte line fetched is used
+// whole.  Stages go from global memory straight into LDS (global_load_lds, 16
+// bytes per lane, no staging registers) and are double buffered (2 x 64 KiB):
+// stage k+1 is in flight while stage k is multiplied, one barrier per stage.
+// LDS rows are 64 bytes (4 chunks of 8 samples); chunk c of row r sits at
+// position c ^ swz(r), swz(r) = ((r >> 1) ^ (r >> 2)) & 3, so that the 16-byte
+// operand reads of 16 consecutive rows fall in distinct banks.  A wavefront's
+// load instruction fills 1 KiB of LDS (16 rows) in lane order, so each lane
+// fetches the global chunk whose swizzled position is its own.
 constexpr int G2_T = 256, G2_BK = 32;
 
 __device__ inline int g2_lds(int r, int c)   // element offset of chunk c of row r in one slab
@@ -125,7 +127,8 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
                                                          int nwork, int kchunk, double* __restrict__ G,
                                                          int64_t gstride)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sm[2][4][G2_T * G2_BK];   // [buffer][A hi, A lo, B hi, B lo]
+    __shared__ __attribute__((aligned(16))) uint16_t sm0[4][G2_T * G2_BK];   // [A hi, A lo, B hi, B lo]
+    __shared__ __attribute__((aligned(16))) uint16_t sm1[4][G2_T * G2_BK];
     const int wi = work_index(nwork);
     if (wi >= nwork) return;
     const int tid = threadIdx.x;
@@ -139,20 +142,33 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
     if (kb >= n) return;                                   // part beyond a ragged last tile
     G += (int64_t)work[3 * wi + 2] * gstride;
     const int wr = wave >> 1, wc = wave & 1;
-    // global -> register staging: thread owns 16-byte chunk (tid & 3) of rows tid/4 and tid/4 + 128
-    const int cq = tid & 3, c8 = cq * 8;
-    const int r_a = tid >> 2;
     const int W32 = W << 5;    // elements per 32-sample block of the tile
-    int goff[2][2];            // [A/B][p] element offset of the chunk in a block (row * 32 + c8), -1 outside
-    int soff[2];               // LDS offset of the chunk for p = 0, 1
+    // direct loads: this wavefront fills row blocks wave and wave + 8 (16 rows each) of each slab;
+    // lane l writes row rb*16 + l/4, position l%4, i.e. global chunk (l%4) ^ swz(row)
+    const int lr = lane >> 2;
+    const int lc = (lane & 3) ^ (((lr >> 1) ^ (lr >> 2)) & 3);   // swz of the row (depends on lr only)
+    int gsrc[2][2];            // [A/B][block j] element offset of this lane's chunk within a 32-sample block
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const int ra = row0 + r_a + 128 * p, rb = col0 + r_a + 128 * p;
-        goff[0][p] = ra < W ? (ra << 5) + c8 : -1;
-        goff[1][p] = rb < W ? (rb << 5) + c8 : -1;
-        soff[p] = g2_lds(r_a + 128 * p, cq);
+    for (int j = 0; j < 2; ++j) {
+        const int r = (wave + 8 * j) * 16 + lr;
+        const int ra = row0 + r < W ? row0 + r : W - 1;   // rows past the matrix: any valid row (their
+        const int rb = col0 + r < W ? col0 + r : W - 1;   // products land outside G and are dropped)
+        gsrc[0][j] = (ra << 5) + (lc << 3);
+        gsrc[1][j] = (rb << 5) + (lc << 3);
     }
-    // operand read offsets: rows of this lane, chunk 2 * (ks / 16) + lk
+#define G2_LOAD_STAGE(SM, K0)                                                                  \
+    {                                                                                          \
+        const int kb_ = ((K0) >> 5) * W32;                                                     \
+        _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                       \
+        _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                        \
+            const int d_ = (wave + 8 * j) * 16 * 32;                                           \
+            __builtin_amdgcn_global_load_lds((const void*)(Xh + kb_ + gsrc[ab][j]),            \
+                                             (void*)&SM[2 * ab][d_], 16, 0, 0);                \
+            __builtin_amdgcn_global_load_lds((const void*)(Xl + kb_ + gsrc[ab][j]),            \
+                                             (void*)&SM[2 * ab + 1][d_], 16, 0, 0);            \
+        }                                                                                      \
+    }
+    // operand read offsets: rows of this lane, chunk 2 * h + lk for half h of the stage
     int aoff[2][2], boff[2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -161,49 +177,17 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
 #pragma unroll
         for (int nj = 0; nj < 4; ++nj) boff[h][nj] = g2_lds(wc * 128 + nj * 32 + li, 2 * h + lk);
     }
-    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    u16x8 stage[2][2][2];      // [A/B][hi/lo][p]
-#define G2_LOAD_STAGE(K0)                                                                     \
-    {                                                                                         \
-        const int k0_ = (K0);                                                                 \
-        const bool full_ = k0_ + G2_BK <= n;                                                  \
-        const int kb_ = (k0_ >> 5) * W32;                                                     \
-        _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                      \
-        _Pragma("unroll") for (int p = 0; p < 2; ++p) {                                       \
-            const int o = goff[ab][p];                                                        \
-            if (o < 0) {                                                                      \
-                stage[ab][0][p] = z8;                                                         \
-                stage[ab][1][p] = z8;                                                         \
-            } else if (full_) {                                                               \
-                stage[ab][0][p] = *(const u16x8*)(Xh + kb_ + o);                              \
-                stage[ab][1][p] = *(const u16x8*)(Xl + kb_ + o);                              \
-            } else {                                                                          \
-                _Pragma("unroll") for (int e = 0; e < 8; ++e) {                               \
-                    const bool in = k0_ + c8 + e < n;                                         \
-                    stage[ab][0][p][e] = in ? Xh[kb_ + o + e] : (uint16_t)0;                  \
-                    stage[ab][1][p][e] = in ? Xl[kb_ + o + e] : (uint16_t)0;                  \
-                }                                                                             \
-            }                                                                                 \
-        }                                                                                     \
-    }
-#define G2_STORE_STAGE(BUF)                                                                   \
-    {                                                                                         \
-        _Pragma("unroll") for (int ab = 0; ab < 2; ++ab)                                      \
-        _Pragma("unroll") for (int hl = 0; hl < 2; ++hl)                                      \
-        _Pragma("unroll") for (int p = 0; p < 2; ++p)                                         \
-            *(u16x8*)&sm[BUF][2 * ab + hl][soff[p]] = stage[ab][hl][p];                       \
-    }
-// multiply half h (samples 16h .. 16h + 15) of the stage in buffer BUF
-#define G2_MULTIPLY(BUF, h)                                                                   \
+// multiply half h (samples 16h .. 16h + 15) of the stage in LDS buffer SM
+#define G2_MULTIPLY(SM, h)                                                                    \
     {                                                                                         \
         bf16x8 ah[2], al[2];                                                                  \
         _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                    \
-            ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][0][aoff[h][mi]]);     \
-            al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][1][aoff[h][mi]]);     \
+            ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[0][aoff[h][mi]]);          \
+            al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[1][aoff[h][mi]]);          \
         }                                                                                     \
         _Pragma("unroll") for (int nj = 0; nj < 4; ++nj) {                                    \
-            const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][2][boff[h][nj]]); \
-            const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&sm[BUF][3][boff[h][nj]]); \
+            const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[2][boff[h][nj]]); \
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[3][boff[h][nj]]); \
             _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                \
                 acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0); \
                 acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0); \
@@ -218,41 +202,47 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
         for (int nj = 0; nj < 4; ++nj)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
-    G2_LOAD_STAGE(kb)
-    G2_STORE_STAGE(0)
-    if (kb + G2_BK < n) G2_LOAD_STAGE(kb + G2_BK)
-    __syncthreads();
-    // stage k0 is in buffer it & 1 (loop unrolled by two so the buffer index is constant)
+    G2_LOAD_STAGE(sm0, kb)
     for (int k0 = kb; k0 < n; k0 += 2 * G2_BK) {
-        G2_MULTIPLY(0, 0)
-        if (k0 + G2_BK < n) {
-            G2_STORE_STAGE(1)
-            if (k0 + 2 * G2_BK < n) G2_LOAD_STAGE(k0 + 2 * G2_BK)
-        }
-        G2_MULTIPLY(0, 1)
+        // stage k0 is in sm0, stage k0 + 32 goes to sm1 (read two stages ago, free after the barrier)
+        __builtin_amdgcn_s_waitcnt(0x3f70);               // vmcnt(0): this wavefront's loads of stage k0
         __syncthreads();
+        if (k0 + G2_BK < n) G2_LOAD_STAGE(sm1, k0 + G2_BK)
+        G2_MULTIPLY(sm0, 0)
+        G2_MULTIPLY(sm0, 1)
         if (k0 + G2_BK >= n) break;
-        G2_MULTIPLY(1, 0)
-        if (k0 + 2 * G2_BK < n) {
-            G2_STORE_STAGE(0)
-            if (k0 + 3 * G2_BK < n) G2_LOAD_STAGE(k0 + 3 * G2_BK)
-        }
-        G2_MULTIPLY(1, 1)
+        __builtin_amdgcn_s_waitcnt(0x3f70);
         __syncthreads();
+        if (k0 + 2 * G2_BK < n) G2_LOAD_STAGE(sm0, k0 + 2 * G2_BK)
+        G2_MULTIPLY(sm1, 0)
+        G2_MULTIPLY(sm1, 1)
     }
 #undef G2_LOAD_STAGE
-#undef G2_STORE_STAGE
 #undef G2_MULTIPLY
+    // epilogue: G += acc.  A tile inside the matrix reads its 16 values of an MFMA tile in one batch
+    // (one wait instead of 16); tiles at the matrix edge go element by element.
+    const bool inside = row0 + G2_T <= W && col0 + G2_T <= W;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 4; ++nj)
+        for (int nj = 0; nj < 4; ++nj) {
+            const int ib = row0 + wr * 64 + 32 * mi + 4 * lk;
+            const int j = col0 + wc * 128 + 32 * nj + li;
+            if (inside) {
+                double* g = G + (int64_t)ib * W + j;
+                double v[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = row0 + wr * 64 + 32 * mi + 8 * (r >> 2) + 4 * lk + (r & 3);
-                const int j = col0 + wc * 128 + 32 * nj + li;
-                if (i < W && j < W) G[(int64_t)i * W + j] += (double)acc[mi][nj][r];
+                for (int r = 0; r < 16; ++r) v[r] = g[(int64_t)(8 * (r >> 2) + (r & 3)) * W];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) g[(int64_t)(8 * (r >> 2) + (r & 3)) * W] = v[r] + (double)acc[mi][nj][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = ib + 8 * (r >> 2) + (r & 3);
+                    if (i < W && j < W) G[(int64_t)i * W + j] += (double)acc[mi][nj][r];
+                }
             }
+        }
 }
 
 // R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; float rows of stride ld)

@@ -240,6 +240,19 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
     for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
 }
 
+// Zero the samples [n, n rounded up to 32) of every row of a blocked split-bfloat16
+// tile: the Gram kernel reads whole 32-sample blocks.
+__global__ void k_zero_tail(uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl, int64_t W, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tail = ((n + 31) & ~(int64_t)31) - n;
+    if (i >= W * tail) return;
+    const int64_t f = i / tail, t = n + i % tail;
+    const size_t e = (size_t)(t >> 5) * (size_t)(W << 5) + (size_t)(f << 5) + (size_t)(t & 31);
+    Xh[e] = 0;
+    Xl[e] = 0;
+}
+
 // Vertex table of the float32 feature kernel: vtab[8 j + q] = B_q(t_j) (cubic
 // Bernstein weights), vtab[8 j + 4] = t_j, vtab[8 j + 5] = 1 - t_j, t_j = j / S.
 __global__ void k_vertex_table(int S, float* __restrict__ vtab)
@@ -690,6 +703,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
             if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab))) return rc;
+            if (n & 31)
+                hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
                 return rc;
             if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
