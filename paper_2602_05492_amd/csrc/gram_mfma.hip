@@ -177,23 +177,44 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
 #pragma unroll
         for (int nj = 0; nj < 4; ++nj) boff[h][nj] = g2_lds(wc * 128 + nj * 32 + li, 2 * h + lk);
     }
-// multiply half h (samples 16h .. 16h + 15) of the stage in LDS buffer SM
-#define G2_MULTIPLY(SM, h)                                                                    \
+// multiply the stage in LDS buffer SM: 8 steps (half h = step / 4, column tile nj = step % 4);
+// the B operands of the next step (and the A operands of the second half) are read from LDS
+// while the current step's MFMAs run
+#define G2_A(SM, h, ah, al)                                                                   \
+    _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                        \
+        ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[0][aoff[h][mi]]);              \
+        al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[1][aoff[h][mi]]);              \
+    }
+#define G2_B(SM, h, nj, bh, bl)                                                               \
+    bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[2][boff[h][nj]]);                      \
+    bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[3][boff[h][nj]]);
+#define G2_STEP(ah, al, bh, bl, nj)                                                           \
+    _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                        \
+        acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0); \
+        acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0); \
+        acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh, acc[mi][nj], 0, 0, 0); \
+    }
+// order inside a step: its LDS reads (for the next step) first, then its 6 MFMAs; no
+// instruction crosses a step boundary
+#define G2_ORDER(nreads)                                                                      \
+    __builtin_amdgcn_sched_group_barrier(0x100, nreads, 0);                                   \
+    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);                                        \
+    __builtin_amdgcn_sched_barrier(0);
+#define G2_MULTIPLY(SM)                                                                       \
     {                                                                                         \
-        bf16x8 ah[2], al[2];                                                                  \
-        _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                    \
-            ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[0][aoff[h][mi]]);          \
-            al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[1][aoff[h][mi]]);          \
-        }                                                                                     \
-        _Pragma("unroll") for (int nj = 0; nj < 4; ++nj) {                                    \
-            const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[2][boff[h][nj]]); \
-            const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[3][boff[h][nj]]); \
-            _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                \
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0); \
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl, acc[mi][nj], 0, 0, 0); \
-                acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh, acc[mi][nj], 0, 0, 0); \
-            }                                                                                 \
-        }                                                                                     \
+        bf16x8 a0h[2], a0l[2], a1h[2], a1l[2], b0h, b0l, b1h, b1l;                            \
+        G2_A(SM, 0, a0h, a0l)                                                                 \
+        G2_B(SM, 0, 0, b0h, b0l)                                                              \
+        __builtin_amdgcn_sched_barrier(0);                                                    \
+        G2_B(SM, 0, 1, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 0)  G2_ORDER(2)                 \
+        G2_B(SM, 0, 2, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 1)  G2_ORDER(2)                 \
+        G2_B(SM, 0, 3, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 2)  G2_ORDER(2)                 \
+        G2_A(SM, 1, a1h, a1l)                                                                 \
+        G2_B(SM, 1, 0, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 3)  G2_ORDER(6)                 \
+        G2_B(SM, 1, 1, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 0)  G2_ORDER(2)                 \
+        G2_B(SM, 1, 2, b0h, b0l)  G2_STEP(a1h, a1l, b1h, b1l, 1)  G2_ORDER(2)                 \
+        G2_B(SM, 1, 3, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 2)  G2_ORDER(2)                 \
+                                  G2_STEP(a1h, a1l, b1h, b1l, 3)                              \
     }
     floatx16 acc[2][4];
 #pragma unroll
@@ -208,16 +229,18 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
         __builtin_amdgcn_s_waitcnt(0x3f70);               // vmcnt(0): this wavefront's loads of stage k0
         __syncthreads();
         if (k0 + G2_BK < n) G2_LOAD_STAGE(sm1, k0 + G2_BK)
-        G2_MULTIPLY(sm0, 0)
-        G2_MULTIPLY(sm0, 1)
+        G2_MULTIPLY(sm0)
         if (k0 + G2_BK >= n) break;
         __builtin_amdgcn_s_waitcnt(0x3f70);
         __syncthreads();
         if (k0 + 2 * G2_BK < n) G2_LOAD_STAGE(sm0, k0 + 2 * G2_BK)
-        G2_MULTIPLY(sm1, 0)
-        G2_MULTIPLY(sm1, 1)
+        G2_MULTIPLY(sm1)
     }
 #undef G2_LOAD_STAGE
+#undef G2_A
+#undef G2_B
+#undef G2_STEP
+#undef G2_ORDER
 #undef G2_MULTIPLY
     // epilogue: G += acc.  A tile inside the matrix reads its 16 values of an MFMA tile in one batch
     // (one wait instead of 16); tiles at the matrix edge go element by element.
