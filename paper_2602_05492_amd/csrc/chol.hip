@@ -40,68 +40,69 @@ __global__ void k_damp(const double* __restrict__ H, int64_t P, double lam, cons
     A[i * P + j] = v;
 }
 
-// Factor the diagonal block kb in place (lower triangle).
-__global__ void k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag)
+__device__ inline double readlane_f64(double v, int lane)
 {
-    __shared__ double L[NB][NB + 1];
-    const int64_t o = (int64_t)kb * NB;
-    const int nb = (int)(P - o < NB ? P - o : NB);
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        L[i][j] = A[(o + i) * P + o + j];
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (threadIdx.x == 0) {
-            const double d = L[j][j];
-            if (!(d > 0.0) || !isfinite(d)) {
-                flag[0] = 1;
-                L[j][j] = 1.0;
-            } else {
-                L[j][j] = sqrt(d);
-            }
-        }
-        __syncthreads();
-        const double djj = L[j][j];
-        for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) L[i][j] /= djj;
-        __syncthreads();
-        const int rem = nb - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            const int i = j + 1 + e / rem, k = j + 1 + e % rem;
-            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) A[(o + i) * P + o + j] = L[i][j];
-    }
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
 }
 
-// Panel rows below diagonal block kb: row <- row L_kk^{-T} (one thread per row, 64 columns).
+// Factor the diagonal block kb in place (lower triangle).  One wavefront, lane i
+// holds row i in registers; column j's pivot and entries come from the owning
+// lanes by readlane (the loops are unrolled, so every lane index is a constant).
+// Rows / columns past the matrix are an identity block.
+__global__ void __launch_bounds__(64) k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag)
+{
+    const int64_t o = (int64_t)kb * NB;
+    const int nb = (int)(P - o < NB ? P - o : NB);
+    const int i = threadIdx.x;
+    double a[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        a[k] = (i < nb && k < nb) ? (k <= i ? A[(o + i) * P + o + k] : 0.0) : (i == k ? 1.0 : 0.0);
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const double d = readlane_f64(a[j], j);
+        const bool ok = d > 0.0 && isfinite(d);
+        bad |= !ok;
+        const double sj = ok ? sqrt(d) : 1.0;
+        a[j] = i == j ? sj : a[j] / sj;
+        // entries above the diagonal of a row are never read back, so all lanes update
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
+    }
+    if (bad && i == 0) flag[0] = 1;
+    if (i < nb)
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (k <= i && k < nb) A[(o + i) * P + o + k] = a[k];
+}
+
+// Panel rows below diagonal block kb: row <- row L_kk^{-T}.  A block of 64 threads
+// stages 64 rows and L_kk in LDS with coalesced loads; thread r then substitutes row r.
 __global__ void __launch_bounds__(64) k_trsm_panel(double* __restrict__ A, int64_t P, int kb)
 {
     __shared__ double L[NB][NB + 1];
+    __shared__ double R[NB][NB + 1];
     const int64_t o = (int64_t)kb * NB;
-    for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        L[i][j] = j <= i ? A[(o + i) * P + o + j] : 0.0;
+    const int64_t r0 = o + NB + (int64_t)blockIdx.x * NB;
+    const int nr = (int)(P - r0 < NB ? P - r0 : NB);
+    const int t = threadIdx.x;
+    for (int i = 0; i < NB; ++i) {
+        L[i][t] = t <= i ? A[(o + i) * P + o + t] : 0.0;
+        R[i][t] = i < nr ? A[(r0 + i) * P + o + t] : 0.0;
     }
     __syncthreads();
-    const int64_t r = o + NB + (int64_t)blockIdx.x * NB + threadIdx.x;
-    if (r >= P) return;
-    double a[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) a[j] = A[r * P + o + j];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        double s = a[j];
-#pragma unroll
-        for (int l = 0; l < j; ++l) s -= a[l] * L[j][l];
-        a[j] = s / L[j][j];
+    if (t < nr) {
+        for (int j = 0; j < NB; ++j) {
+            double sum = R[t][j];
+            for (int l = 0; l < j; ++l) sum -= R[t][l] * L[j][l];
+            R[t][j] = sum / L[j][j];
+        }
     }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) A[r * P + o + j] = a[j];
+    __syncthreads();
+    for (int i = 0; i < nr; ++i) A[(r0 + i) * P + o + t] = R[i][t];
 }
 
 // Triangular solve of diagonal block kb on b (in place): L y = b (trans 0) or L^T y = b (trans 1).
@@ -144,7 +145,7 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     const int nblk = (int)((P + NB - 1) / NB);
     ProfScope ps_(ctx, PT_CHOLESKY, s);
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb, dflag);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb, dflag);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
         if (rem > 0) {
             hipLaunchKernelGGL(k_trsm_panel, dim3(blocks_for(rem, NB)), dim3(NB), 0, s, A, P, kb);
