@@ -32,6 +32,7 @@ PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12,
 # --pmc-probe run (two sample tiles of the LM workload plus a 256 MiB copy for calibration)
 PMC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_lm_workload_pmc.json")
 CSRC = os.path.join(ROOT, "paper_2602_05492_amd", "csrc")
+GRAM_TILE = 32768          # samples per split-BF16 Gram launch (the library's default tile)
 GRAM_SOURCES = ["gram_mfma.hip"]
 SWEEP_SOURCES = ["sweep_mixed.hip", "sweep_common.hpp", "seg_math.hpp"]
 
@@ -83,14 +84,15 @@ def sweep_flops_per_pair():
 
 
 def pmc_probe() -> int:
-    """Small run for byte counters: J^T J on two 16,384-sample tiles of the LM workload, then a
-    plain 256 MiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    """Small run for byte counters: mixed forward sweep and J^T J on two 32,768-sample tiles (the
+    bench's tile) of the LM workload, then a plain 256 MiB device copy whose counters calibrate
+    FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
     wl = W.make_config(5)
     ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
-    n = 2 * 16384
+    n = 2 * GRAM_TILE
     x = torch.from_numpy(wl.samples(0)[:n]).cuda()
     r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
     ctx.eval(torch.from_numpy(wl.theta0).cuda(), x, wl.cbar_true, "mixed")
@@ -259,7 +261,7 @@ def main() -> int:
     tot_ms, launches = timed[dom]
     achieved = work[dom] / (tot_ms * 1e-3) / 1e12
     bound, peak = peak_of[dom]
-    traffic = gram_traffic(16384) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma") else None
+    traffic = gram_traffic(GRAM_TILE) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma") else None
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (peak / 1e12), "traffic": traffic, "launches": launches,
                 "avg_launch_ms": tot_ms / launches}

@@ -624,7 +624,10 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // sample tile: large for the float64 Gram; for the MFMA Grams small enough that the tile of
     // feature rows (W x T, 4 bytes per entry) stays resident in the last-level cache while every
     // output tile re-reads it
-    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows : (gram == BEM_GRAM_FP32_MFMA ? 8192 : 16384);
+    // sample tile: 32,768 for the split-BF16 Gram (1 GB of blocked bf16 pairs at the LM workload; 3
+    // parts of 10,944 samples per launch)
+    int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows
+                                        : (gram == BEM_GRAM_FP32_MFMA ? 8192 : (gram == BEM_GRAM_FP64 ? 16384 : 32768));
     const size_t elem = gram == BEM_GRAM_FP64 ? 8 : 4;
     while (T > 1024 && (size_t)W * T * elem > ((size_t)3 << 30)) T /= 2;
     if (T > N) T = N > 0 ? N : 1;
