@@ -65,8 +65,11 @@ typedef enum {
  *        within 2*near_factor*L of the sample, which contains every sample
  *        closer than near_factor*L to the segment), which are evaluated in
  *        float64 from the float64 inputs; u and cotangents are float32; every
- *        reduction over samples is finished in float64.  The boundary system,
- *        its solves and the LM solve are float64 in both modes. */
+ *        reduction over samples is finished in float64.  The float64 sums of
+ *        near pairs in bem_eval and bem_vjp are accumulated with atomics, so
+ *        MIXED results can differ in their last bits from call to call; FP64
+ *        results are reproducible.  The boundary system, its solves and the LM
+ *        solve are float64 in both modes. */
 typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
 
 /* Arithmetic of the Gram contraction that forms J^T J and J^T r.
@@ -74,7 +77,8 @@ typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
  * FP32_MFMA    : float32 J tiles, float32 MFMA, float32 accumulation within
  *                a sample tile, float64 across tiles.
  * BF16X3_MFMA  : J split as hi + lo bfloat16, hi*hi + hi*lo + lo*hi on bf16
- *                MFMA with float32 accumulation within a tile, float64 across. */
+ *                MFMA with float32 accumulation within a third of a sample
+ *                tile, float64 across thirds and tiles (fixed order). */
 typedef enum { BEM_GRAM_FP64 = 0, BEM_GRAM_FP32_MFMA = 1, BEM_GRAM_BF16X3_MFMA = 2 } bem_gram;
 
 typedef struct {
@@ -154,7 +158,8 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
 /* One Levenberg-Marquardt step (Eq. optimstep, Sec. 4.3) on the samples x
  * with targets T [N,3] float64:
  *   cbar update (state->mean_rule), u = u(theta), r = u - T, loss L0 = (1/2N) sum r^2,
- *   g = (1/N) sum J^T r by the adjoint (bem_vjp), H = (1/N) sum J^T J (bem_jtj),
+ *   g = (1/N) sum J^T r by the adjoint (bem_vjp), H = (1/N) sum J^T J (bem_jtj's
+ *   Gram; J^T r itself is not formed again),
  *   delta = (lambda diag(H) + H)^{-1} g by float64 Cholesky,
  *   theta' = theta - delta, L1 = loss at theta' on the same samples with cbar fixed;
  *   accept iff L1 < L0: theta <- theta', lambda /= 10; else lambda *= 10.
