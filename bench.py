@@ -139,7 +139,14 @@ def lm_curve(steps: int, gram: str, prec: str) -> int:
 
 
 def cpu_baseline(wl, x_host, budget_note: str) -> dict:
-    """Time the FP64 oracle on bounded pieces of one LM step and extrapolate to the full step."""
+    """Time the FP64 oracle on bounded pieces of one LM step and extrapolate to the full step
+    (BLAS held to one thread, so the figure is one host core's)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(wl, x_host, budget_note)
+
+
+def _cpu_baseline(wl, x_host, budget_note: str) -> dict:
     import numpy as np
     import oracle as O
     S, eps = wl.S, wl.eps
