@@ -14,6 +14,8 @@ the HIP library and takes every step in the paper's order, in float64:
   Jacobian: differential BIE, same matrix  (Eq. diffbie, Sec. 3.2 discretisation)
   normal equations, LM step, damping       (Eq. optimstep, Eq. losshessian,
                                             Eq. lossjacobian, Sec. 4.3)
+  compatibility condition: constrained     (Sec. 3.1.2 compatibility, Sec. 4.3
+  step and re-projection of w_c             enforcement)
 
 Segment integrals are the antiderivatives of the two kernels evaluated at the
 segment ends (exactly the integral the paper approximates by quadrature); the
@@ -413,6 +415,7 @@ class LMState:
     loss_before: float = np.nan
     loss_after: float = np.nan
     cbar: np.ndarray = None
+    compat: bool = False        # enforce the compatibility condition (Sec. 4.3)
 
     def __post_init__(self):
         if self.cbar_sum is None:
@@ -439,6 +442,67 @@ def damped_step(JtJ: np.ndarray, Jtr: np.ndarray, lam: float) -> np.ndarray:
     return cho_solve(cho_factor(Hd, lower=True), Jtr)
 
 
+# =============================================================================
+# Compatibility condition (Sec. 3.1.2: zero net flux of the normal-derivative
+# jump over the handles) and its enforcement in the LM step (Sec. 4.3)
+# =============================================================================
+def compat_vectors(theta, S: int) -> np.ndarray:
+    """Columns a_c (c = RGB) of A [P, 3] with a_c . theta = int over the handles of w_c.
+
+    On a straight segment the jump w_c is linear between its end values, so its
+    integral is L (w_c(a) + w_c(b)) / 2; with w_c(t) = (1 - t) wc0 + t wc1 at the
+    vertex parameters t_k this sums, per handle, to alpha_h wc0 + beta_h wc1 with
+      alpha_h = sum_k L_hk (2 - t_k - t_{k+1}) / 2,   beta_h = sum_k L_hk (t_k + t_{k+1}) / 2.
+    Segments not longer than DEGENERATE_LENGTH carry no jump (as in the handle term)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    H = theta.shape[0]
+    p = handle_vertices(theta, S)
+    L = np.sqrt(((p[:, 1:] - p[:, :-1]) ** 2).sum(-1))                   # [H, S]
+    L = np.where(L > DEGENERATE_LENGTH, L, 0.0)
+    t = vertex_params(S)
+    alpha = (L * (2.0 - t[:-1] - t[1:]) / 2.0).sum(1)
+    beta = (L * (t[:-1] + t[1:]) / 2.0).sum(1)
+    A = np.zeros((H, 20, 3))
+    for c in range(3):
+        A[:, 14 + c, c] = alpha
+        A[:, 17 + c, c] = beta
+    return A.reshape(H * 20, 3)
+
+
+def constrained_step(JtJ: np.ndarray, Jtr: np.ndarray, lam: float, A: np.ndarray) -> np.ndarray:
+    """The damped step of damped_step restricted to A^T delta = 0 (the projection of the
+    approximate Hessian and of the gradient onto the feasible directions for fixed end points):
+    the minimiser of delta^T Hd delta / 2 - delta^T Jtr over that subspace, from the KKT system
+      [Hd A; A^T 0] [delta; nu] = [Jtr; 0]  ->  delta = Hd^{-1} (Jtr - A nu),
+      (A^T Hd^{-1} A) nu = A^T Hd^{-1} Jtr."""
+    from scipy.linalg import cho_factor, cho_solve
+    d = np.diag(JtJ).copy()
+    d = np.maximum(d, 1e-12 * max(d.max(), 1e-300))
+    cf = cho_factor(JtJ + lam * np.diag(d), lower=True)
+    keep = np.abs(A).sum(0) > 0                     # a channel without handles has no constraint
+    A = A[:, keep]
+    d0 = cho_solve(cf, Jtr)
+    if A.shape[1] == 0:
+        return d0
+    X = cho_solve(cf, A)
+    nu = np.linalg.solve(A.T @ X, A.T @ d0)
+    return d0 - X @ nu
+
+
+def reproject(theta, S: int) -> np.ndarray:
+    """Orthogonal projection of the wc parameters onto a_c(theta) . theta = 0, with a_c taken at
+    theta's own end points (the re-projection after each update, Sec. 4.3)."""
+    theta = np.asarray(theta, dtype=np.float64).copy()
+    A = compat_vectors(theta, S)
+    flat = theta.reshape(-1)
+    for c in range(3):
+        a = A[:, c]
+        aa = float(a @ a)
+        if aa > 0:
+            flat -= a * (float(a @ flat) / aa)
+    return flat.reshape(theta.shape)
+
+
 def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256):
     """One damped Gauss-Newton step with accept/reject on the same samples.  Returns (theta', state)."""
     theta = np.asarray(theta, dtype=np.float64)
@@ -454,8 +518,12 @@ def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256
     u = u0 + cbar[None, :]
     L0 = loss(u, T)
     JtJ, Jtr = normal_equations(theta, x, u - T, S, eps, per_side)
-    delta = damped_step(JtJ, Jtr, state.lam)
-    theta_new = theta - delta.reshape(theta.shape)
+    if state.compat:
+        delta = constrained_step(JtJ, Jtr, state.lam, compat_vectors(theta, S))
+        theta_new = reproject(theta - delta.reshape(theta.shape), S)
+    else:
+        delta = damped_step(JtJ, Jtr, state.lam)
+        theta_new = theta - delta.reshape(theta.shape)
     L1 = loss(evaluate(theta_new, x, cbar, S, eps, per_side), T)
     state.loss_before, state.loss_after = L0, L1
     if L1 < L0:
