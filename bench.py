@@ -189,6 +189,8 @@ def main() -> int:
     ap.add_argument("--gram", default="bf16x3_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
     ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--compat", type=int, default=0,
+                    help="enforce the compatibility condition in every LM step (constrained step + re-projection)")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
     ap.add_argument("--lm-curve", type=int, default=0,
                     help="instead of timing: run this many LM steps (fresh samples each) and print loss, lambda and "
@@ -225,7 +227,7 @@ def main() -> int:
         T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(i)).cuda()
         batches.append((x, T))
     theta = torch.from_numpy(wl.theta0).cuda()
-    st = B.new_lm_state(wl.lam0, 0)
+    st = B.new_lm_state(wl.lam0, 0, compat=args.compat)
     for i in range(args.warmup):
         ctx.lm_step(theta, batches[i][0], batches[i][1], st, args.gram, args.prec)
         print(f"warmup {i}: loss {st.loss_before:.6e} -> {st.loss_after:.6e} accepted {st.accepted}",
@@ -325,7 +327,7 @@ def main() -> int:
         "config": {"workload": "LM normal equations: 256 cubic handles x 32 segments (P = 5,120), "
                                "2,097,152 uniform samples per step, sigma 0.2, eps 1e-2, 1,024 outer elements",
                    "handles": H, "segs_per_handle": S, "samples": N, "params": wl.P, "outer_elements": M,
-                   "prec": args.prec, "gram": args.gram, "parallelism": "single GPU"},
+                   "prec": args.prec, "gram": args.gram, "compat": args.compat, "parallelism": "single GPU"},
         "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
         "fp64_gpu_ms_per_step": fp64_ms, "speedup_vs_fp64_gpu": speedup,
         "step_direction_rel_err_vs_fp64": step_err,

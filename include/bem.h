@@ -104,6 +104,8 @@ typedef struct {
     double loss_before;       /* out: (1/2N) sum |u - T|^2 at theta                 */
     double loss_after;        /* out: same at the trial parameters                  */
     int32_t chol_retries;     /* out: extra damping rounds after a failed Cholesky  */
+    int32_t compat;           /* in: 1 enforces the compatibility condition          */
+    double compat_violation;  /* out: max_c |a_c . theta'| / sum |a_c theta'| (compat) */
 } bem_lm_state;
 
 /* Build the outer boundary (unit square, counter-clockwise, elems_per_side
@@ -163,6 +165,14 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  *   delta = (lambda diag(H) + H)^{-1} g by float64 Cholesky,
  *   theta' = theta - delta, L1 = loss at theta' on the same samples with cbar fixed;
  *   accept iff L1 < L0: theta <- theta', lambda /= 10; else lambda *= 10.
+ * With state->compat = 1 the compatibility condition of Sec. 3.1.2 (zero net
+ * flux of the normal-derivative jump, int over the handles of w_c = 0 per
+ * channel, linear in the wc parameters for fixed end points: a_c . theta = 0)
+ * is enforced as in Sec. 4.3: delta is the damped step restricted to
+ * a_c . delta = 0 (a_c at the current end points; KKT system through its 3x3
+ * Schur complement, 3 more Cholesky solves), and after the update the wc
+ * parameters are projected orthogonally onto a_c . theta' = 0 with a_c at the
+ * new end points; state->compat_violation reports what remains (rounding).
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,20] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.

@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
 class LMState(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("cbar", ctypes.c_double * 3), ("cbar_sum", ctypes.c_double * 3),
                 ("cbar_count", ctypes.c_int64), ("mean_rule", ctypes.c_int32), ("accepted", ctypes.c_int32),
-                ("loss_before", ctypes.c_double), ("loss_after", ctypes.c_double), ("chol_retries", ctypes.c_int32)]
+                ("loss_before", ctypes.c_double), ("loss_after", ctypes.c_double), ("chol_retries", ctypes.c_int32),
+                ("compat", ctypes.c_int32), ("compat_violation", ctypes.c_double)]
 
 
 _lib = None
@@ -240,10 +241,11 @@ class Context:
         return state
 
 
-def new_lm_state(lam: float = 1e-3, mean_rule: int = 0) -> LMState:
+def new_lm_state(lam: float = 1e-3, mean_rule: int = 0, compat: int = 0) -> LMState:
     s = LMState()
     s.lam = lam
     s.mean_rule = mean_rule
+    s.compat = compat
     return s
 
 

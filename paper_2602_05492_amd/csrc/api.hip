@@ -254,6 +254,7 @@ int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N, 
     if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA)
         return set_error(ctx, BEM_EINVAL, "bad gram mode %d", (int)gram);
     if (state->mean_rule != 0 && state->mean_rule != 1) return set_error(ctx, BEM_EINVAL, "bad mean_rule");
+    if (state->compat != 0 && state->compat != 1) return set_error(ctx, BEM_EINVAL, "bad compat flag");
     if (!(state->lambda > 0.0) || !std::isfinite(state->lambda)) return set_error(ctx, BEM_EINVAL, "lambda must be > 0");
     state->lambda = std::fmin(std::fmax(state->lambda, 1e-12), 1e12);
     rc = run_lm_step(ctx, theta, H, x, N, target, state, (int)gram, prec == BEM_PREC_MIXED, stream);

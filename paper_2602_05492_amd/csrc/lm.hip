@@ -54,6 +54,128 @@ __global__ void __launch_bounds__(256) k_rowsum(const UT* __restrict__ u, const 
         for (int c = 0; c < 3; ++c) partial[3 * blockIdx.x + c] = red[c][0];
 }
 
+// ---- compatibility condition (Sec. 3.1.2) and its enforcement (Sec. 4.3) -------------------
+// A [3][P]: a_c . theta = int over the handles of w_c for fixed end points.  A segment's jump is
+// linear between its end values, so per handle alpha_h = sum_k L_k (2 - t_k - t_{k+1}) / 2 at
+// wc0_{h,c} and beta_h = sum_k L_k (t_k + t_{k+1}) / 2 at wc1_{h,c}; thread per handle, from the
+// float64 segment table (degenerate segments have L2 = 0 there).  A must be zero beforehand.
+__global__ void k_compat_vectors(const double* __restrict__ seg64, int H, int S, int64_t P, double* __restrict__ A)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= H) return;
+    double alpha = 0.0, beta = 0.0;
+    for (int k = 0; k < S; ++k) {
+        const double L = sqrt(seg64[((size_t)h * S + k) * kSegStride + 6]);
+        const double ta = (double)k / (double)S, tb = (double)(k + 1) / (double)S;
+        alpha += L * (2.0 - ta - tb) / 2.0;
+        beta += L * (ta + tb) / 2.0;
+    }
+    for (int c = 0; c < 3; ++c) {
+        A[(size_t)c * P + (size_t)h * 20 + 14 + c] = alpha;
+        A[(size_t)c * P + (size_t)h * 20 + 17 + c] = beta;
+    }
+}
+
+__device__ inline void block_sum(double* v, int n, double (*red)[256])
+{
+    for (int i = 0; i < n; ++i) red[i][threadIdx.x] = v[i];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int i = 0; i < n; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
+        __syncthreads();
+    }
+    for (int i = 0; i < n; ++i) v[i] = red[i][0];
+    __syncthreads();
+}
+
+// Constrained damped step (one block): delta0 = Hd^{-1} g and X_c = Hd^{-1} a_c are given; solve
+// (A^T X) nu = A^T delta0 over the channels with a nonzero a_c (Gaussian elimination with partial
+// pivoting) and set delta = delta0 - X nu, so that A^T delta = 0.
+__global__ void __launch_bounds__(256) k_compat_solve(const double* __restrict__ A, const double* __restrict__ X,
+                                                      int64_t P, double* __restrict__ delta)
+{
+    __shared__ double red[12][256];
+    __shared__ double nu[3];
+    double v[12];
+    for (int i = 0; i < 12; ++i) v[i] = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+        for (int i = 0; i < 3; ++i) {
+            const double a = A[(size_t)i * P + p];
+            for (int j = 0; j < 3; ++j) v[3 * i + j] += a * X[(size_t)j * P + p];
+            v[9 + i] += a * delta[p];
+        }
+    }
+    block_sum(v, 12, red);
+    if (threadIdx.x == 0) {
+        int idx[3], n = 0;
+        for (int c = 0; c < 3; ++c)
+            if (v[4 * c] > 0.0) idx[n++] = c;             // a_c = 0: no constraint on that channel
+        double M[3][4];
+        for (int r = 0; r < n; ++r) {
+            for (int q = 0; q < n; ++q) M[r][q] = v[3 * idx[r] + idx[q]];
+            M[r][n] = v[9 + idx[r]];
+        }
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r)
+                if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+            for (int q = 0; q <= n; ++q) { const double tmp = M[col][q]; M[col][q] = M[piv][q]; M[piv][q] = tmp; }
+            for (int r = col + 1; r < n; ++r) {
+                const double f = M[r][col] / M[col][col];
+                for (int q = col; q <= n; ++q) M[r][q] -= f * M[col][q];
+            }
+        }
+        double sol[3] = {0.0, 0.0, 0.0};
+        for (int r = n - 1; r >= 0; --r) {
+            double s = M[r][n];
+            for (int q = r + 1; q < n; ++q) s -= M[r][q] * sol[q];
+            sol[r] = s / M[r][r];
+        }
+        for (int c = 0; c < 3; ++c) nu[c] = 0.0;
+        for (int r = 0; r < n; ++r) nu[idx[r]] = sol[r];
+    }
+    __syncthreads();
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x)
+        delta[p] -= X[p] * nu[0] + X[(size_t)P + p] * nu[1] + X[2 * (size_t)P + p] * nu[2];
+}
+
+// Re-projection of the wc parameters of theta onto a_c . theta = 0 with a_c taken at theta's own
+// end points (one block; the three a_c have disjoint supports); out[0] = the largest remaining
+// |a_c . theta| relative to sum_p |a_c[p] theta[p]|.
+__global__ void __launch_bounds__(256) k_reproject(const double* __restrict__ A, int64_t P, double* __restrict__ theta,
+                                                   double* __restrict__ out)
+{
+    __shared__ double red[6][256];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x)
+        for (int c = 0; c < 3; ++c) {
+            const double a = A[(size_t)c * P + p];
+            v[c] += a * theta[p];
+            v[3 + c] += a * a;
+        }
+    block_sum(v, 6, red);
+    double f[3];
+    for (int c = 0; c < 3; ++c) f[c] = v[3 + c] > 0.0 ? v[c] / v[3 + c] : 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x)
+        theta[p] -= A[p] * f[0] + A[(size_t)P + p] * f[1] + A[2 * (size_t)P + p] * f[2];
+    __syncthreads();
+    for (int c = 0; c < 6; ++c) v[c] = 0.0;
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x)
+        for (int c = 0; c < 3; ++c) {
+            const double a = A[(size_t)c * P + p];
+            v[c] += a * theta[p];
+            v[3 + c] += fabs(a * theta[p]);
+        }
+    block_sum(v, 6, red);
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int c = 0; c < 3; ++c)
+            if (v[3 + c] > 0.0) m = fmax(m, fabs(v[c]) / v[3 + c]);
+        out[0] = m;
+    }
+}
+
 __global__ void k_finish_sum(const double* __restrict__ partial, int nb, double* __restrict__ out)
 {
     if (threadIdx.x < 3) {
@@ -119,9 +241,10 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     const int64_t P = 20 * (int64_t)H;
     const size_t ue = mixed ? sizeof(float) : sizeof(double);
     const int64_t n3 = 3 * (N > 0 ? N : 1);
-    // lm workspace layout (ctx->lmw): u | r | g | JtJ | (spare P) | A | delta | theta' | partials | flag
+    // lm workspace layout (ctx->lmw): u | r | g | JtJ | (spare P) | A | delta | theta' | partials | flag |
+    // compatibility vectors [3][P] | their solves [3][P] | violation
     const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)20 * H +
-                                                 3 * (size_t)kRedBlocks + 8) * sizeof(double) + 64;
+                                                 3 * (size_t)kRedBlocks + 8 + 6 * (size_t)P + 8) * sizeof(double) + 64;
     if ((rc = ensure(ctx, ctx->lmw, bytes, s))) return rc;
     char* base = (char*)ctx->lmw.ptr;
     void* u = base;
@@ -133,6 +256,10 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     double* th1 = delta + P;
     double* dpart = th1 + (size_t)20 * H;
     int* dflag = (int*)(dpart + 3 * kRedBlocks + 4);
+    double* cA = dpart + 3 * kRedBlocks + 8;
+    double* cX = cA + 3 * (size_t)P;
+    double* cviol = cX + 3 * (size_t)P;
+    st->compat_violation = 0.0;
     const bem_prec prec = mixed ? BEM_PREC_MIXED : BEM_PREC_FP64;
     st->accepted = 0;
     st->chol_retries = 0;
@@ -186,10 +313,35 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     if (hipMemcpyAsync(delta, g, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "copy gradient");
     if ((rc = chol_solve(ctx, A, P, delta, s))) return rc;
+    const int S = ctx->opts.segs_per_handle;
+    if (st->compat) {
+        // the step restricted to A^T delta = 0 (A at the current end points, whose segment table
+        // the normal equations left in place): X = Hd^{-1} A, then the 3x3 Schur complement
+        if ((rc = fill_f64(ctx, cA, 3 * P, 0.0, s))) return rc;
+        hipLaunchKernelGGL(k_compat_vectors, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->seg64.ptr, H,
+                           S, P, cA);
+        if (hipMemcpyAsync(cX, cA, 3 * (size_t)P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "copy constraint vectors");
+        for (int c = 0; c < 3; ++c)
+            if ((rc = chol_solve(ctx, A, P, cX + (size_t)c * P, s))) return rc;
+        hipLaunchKernelGGL(k_compat_solve, dim3(1), dim3(256), 0, s, (const double*)cA, (const double*)cX, P, delta);
+    }
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
     hipLaunchKernelGGL(k_finite, dim3(blocks_for(P, 256)), dim3(256), 0, s, delta, P, dflag);
     hipLaunchKernelGGL(k_axpy_to, dim3(blocks_for(P, 256)), dim3(256), 0, s, theta, delta, P, th1);
     if ((rc = check_launch(ctx, "update"))) return rc;
+    if (st->compat) {
+        // re-projection of w_c at the new end points
+        if ((rc = launch_expand(ctx, th1, H, s))) return rc;
+        if ((rc = fill_f64(ctx, cA, 3 * P, 0.0, s))) return rc;
+        hipLaunchKernelGGL(k_compat_vectors, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->seg64.ptr, H,
+                           S, P, cA);
+        hipLaunchKernelGGL(k_reproject, dim3(1), dim3(256), 0, s, (const double*)cA, P, th1, cviol);
+        hipLaunchKernelGGL(k_finite, dim3(blocks_for(P, 256)), dim3(256), 0, s, th1, P, dflag);
+        if ((rc = check_launch(ctx, "compatibility"))) return rc;
+        if (hipMemcpyAsync(&st->compat_violation, cviol, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "violation readback");
+    }
     // trial loss on the same samples and mean colour
     if ((rc = bem_eval(ctx, th1, H, x, N, st->cbar, u, prec, s))) return rc;
     if ((rc = row_sums(ctx, u, mixed, T, N, 0, nullptr, sums, dpart, s))) return rc;
