@@ -105,31 +105,42 @@ __global__ void __launch_bounds__(64) k_trsm_panel(double* __restrict__ A, int64
     for (int i = 0; i < nr; ++i) A[(r0 + i) * P + o + t] = R[i][t];
 }
 
-// Triangular solve of diagonal block kb on b (in place): L y = b (trans 0) or L^T y = b (trans 1).
-__global__ void k_trsv_diag(const double* __restrict__ A, int64_t P, int kb, double* __restrict__ b, int trans)
+// Triangular solve of diagonal block kb on the nrhs columns of B [P][nrhs] (in place):
+// L y = b (trans 0) or L^T y = b (trans 1).  One wavefront; thread t owns row t.
+constexpr int kMaxRhs = 4;
+__global__ void __launch_bounds__(64) k_trsv_diag(const double* __restrict__ A, int64_t P, int kb,
+                                                  double* __restrict__ B, int nrhs, int trans)
 {
-    __shared__ double x[NB];
+    __shared__ double x[NB][kMaxRhs];
     const int64_t o = (int64_t)kb * NB;
     const int nb = (int)(P - o < NB ? P - o : NB);
     const int t = threadIdx.x;
-    if (t < nb) x[t] = b[o + t];
+    if (t < nb)
+        for (int c = 0; c < nrhs; ++c) x[t][c] = B[(o + t) * nrhs + c];
     __syncthreads();
     if (!trans) {
         for (int j = 0; j < nb; ++j) {
-            if (t == 0) x[j] /= A[(o + j) * P + o + j];
+            if (t < nrhs) x[j][t] /= A[(o + j) * P + o + j];
             __syncthreads();
-            if (t > j && t < nb) x[t] -= A[(o + t) * P + o + j] * x[j];
+            if (t > j && t < nb) {
+                const double l = A[(o + t) * P + o + j];
+                for (int c = 0; c < nrhs; ++c) x[t][c] -= l * x[j][c];
+            }
             __syncthreads();
         }
     } else {
         for (int j = nb - 1; j >= 0; --j) {
-            if (t == 0) x[j] /= A[(o + j) * P + o + j];
+            if (t < nrhs) x[j][t] /= A[(o + j) * P + o + j];
             __syncthreads();
-            if (t < j) x[t] -= A[(o + j) * P + o + t] * x[j];
+            if (t < j) {
+                const double l = A[(o + j) * P + o + t];
+                for (int c = 0; c < nrhs; ++c) x[t][c] -= l * x[j][c];
+            }
             __syncthreads();
         }
     }
-    if (t < nb) b[o + t] = x[t];
+    if (t < nb)
+        for (int c = 0; c < nrhs; ++c) B[(o + t) * nrhs + c] = x[t][c];
 }
 
 }  // namespace
@@ -164,24 +175,28 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     return hflag ? BEM_ENOTPD : BEM_OK;
 }
 
-// b <- (L L^T)^{-1} b with the factor in A.
-int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* b, hipStream_t s)
+// B <- (L L^T)^{-1} B with the factor in A; B [P][nrhs] row-major, nrhs <= 4.
+int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* B, int nrhs, hipStream_t s)
 {
     int rc;
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(ctx, BEM_EINVAL, "chol_solve: 1..4 right-hand sides");
+    ProfScope ps_(ctx, PT_CHOLESKY, s);
     const int nblk = (int)((P + NB - 1) / NB);
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, b, 0);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, B, nrhs, 0);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
         if (rem > 0 &&
-            (rc = gemm_f64(ctx, (int)rem, 1, NB, -1.0, A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB, P, false,
-                           b + (int64_t)kb * NB, 1, false, 1.0, b + (int64_t)(kb + 1) * NB, 1, s, nullptr, 0)))
+            (rc = gemm_f64(ctx, (int)rem, nrhs, NB, -1.0, A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB, P, false,
+                           B + (int64_t)kb * NB * nrhs, nrhs, false, 1.0, B + (int64_t)(kb + 1) * NB * nrhs, nrhs, s,
+                           nullptr, 0)))
             return rc;
     }
     for (int kb = nblk - 1; kb >= 0; --kb) {
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, b, 1);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, B, nrhs, 1);
         const int64_t o = (int64_t)kb * NB;
         const int nb = (int)(P - o < NB ? P - o : NB);
-        if (o > 0 && (rc = gemm_f64(ctx, (int)o, 1, nb, -1.0, A + o * P, P, true, b + o, 1, false, 1.0, b, 1, s, nullptr, 0)))
+        if (o > 0 && (rc = gemm_f64(ctx, (int)o, nrhs, nb, -1.0, A + o * P, P, true, B + o * nrhs, nrhs, false, 1.0, B,
+                                    nrhs, s, nullptr, 0)))
             return rc;
     }
     return check_launch(ctx, "cholesky solve");

@@ -150,7 +150,7 @@ constexpr int kXrPartials = 32;   // sample-block groups of the split-BF16 X r (
 // chol.hip
 int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,
                 hipStream_t s);
-int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* b, hipStream_t s);
+int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* B, int nrhs, hipStream_t s);
 // lm.hip
 int fill_i32(bem_ctx* ctx, int* p, int64_t n, int v, hipStream_t s);
 int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,

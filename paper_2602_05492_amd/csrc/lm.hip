@@ -89,10 +89,19 @@ __device__ inline void block_sum(double* v, int n, double (*red)[256])
     __syncthreads();
 }
 
-// Constrained damped step (one block): delta0 = Hd^{-1} g and X_c = Hd^{-1} a_c are given; solve
-// (A^T X) nu = A^T delta0 over the channels with a nonzero a_c (Gaussian elimination with partial
-// pivoting) and set delta = delta0 - X nu, so that A^T delta = 0.
-__global__ void __launch_bounds__(256) k_compat_solve(const double* __restrict__ A, const double* __restrict__ X,
+// Right-hand sides of the constrained step: R [P][4] = [g | a_0 | a_1 | a_2].
+__global__ void k_pack_rhs(const double* __restrict__ g, const double* __restrict__ A, int64_t P, double* __restrict__ R)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    R[4 * p] = g[p];
+    for (int c = 0; c < 3; ++c) R[4 * p + 1 + c] = A[(size_t)c * P + p];
+}
+
+// Constrained damped step (one block): R [P][4] holds delta0 = Hd^{-1} g and X_c = Hd^{-1} a_c;
+// solve (A^T X) nu = A^T delta0 over the channels with a nonzero a_c (Gaussian elimination with
+// partial pivoting) and write delta = delta0 - X nu, so that A^T delta = 0.
+__global__ void __launch_bounds__(256) k_compat_solve(const double* __restrict__ A, const double* __restrict__ R,
                                                       int64_t P, double* __restrict__ delta)
 {
     __shared__ double red[12][256];
@@ -102,8 +111,8 @@ __global__ void __launch_bounds__(256) k_compat_solve(const double* __restrict__
     for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
         for (int i = 0; i < 3; ++i) {
             const double a = A[(size_t)i * P + p];
-            for (int j = 0; j < 3; ++j) v[3 * i + j] += a * X[(size_t)j * P + p];
-            v[9 + i] += a * delta[p];
+            for (int j = 0; j < 3; ++j) v[3 * i + j] += a * R[4 * p + 1 + j];
+            v[9 + i] += a * R[4 * p];
         }
     }
     block_sum(v, 12, red);
@@ -137,7 +146,7 @@ __global__ void __launch_bounds__(256) k_compat_solve(const double* __restrict__
     }
     __syncthreads();
     for (int64_t p = threadIdx.x; p < P; p += blockDim.x)
-        delta[p] -= X[p] * nu[0] + X[(size_t)P + p] * nu[1] + X[2 * (size_t)P + p] * nu[2];
+        delta[p] = R[4 * p] - (R[4 * p + 1] * nu[0] + R[4 * p + 2] * nu[1] + R[4 * p + 3] * nu[2]);
 }
 
 // Re-projection of the wc parameters of theta onto a_c . theta = 0 with a_c taken at theta's own
@@ -242,9 +251,9 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     const size_t ue = mixed ? sizeof(float) : sizeof(double);
     const int64_t n3 = 3 * (N > 0 ? N : 1);
     // lm workspace layout (ctx->lmw): u | r | g | JtJ | (spare P) | A | delta | theta' | partials | flag |
-    // compatibility vectors [3][P] | their solves [3][P] | violation
+    // compatibility vectors [3][P] | right-hand sides [P][4] | violation
     const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)20 * H +
-                                                 3 * (size_t)kRedBlocks + 8 + 6 * (size_t)P + 8) * sizeof(double) + 64;
+                                                 3 * (size_t)kRedBlocks + 8 + 7 * (size_t)P + 8) * sizeof(double) + 64;
     if ((rc = ensure(ctx, ctx->lmw, bytes, s))) return rc;
     char* base = (char*)ctx->lmw.ptr;
     void* u = base;
@@ -257,8 +266,8 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     double* dpart = th1 + (size_t)20 * H;
     int* dflag = (int*)(dpart + 3 * kRedBlocks + 4);
     double* cA = dpart + 3 * kRedBlocks + 8;
-    double* cX = cA + 3 * (size_t)P;
-    double* cviol = cX + 3 * (size_t)P;
+    double* cX = cA + 3 * (size_t)P;          // [P][4]: gradient and the three a_c, solved in place
+    double* cviol = cX + 4 * (size_t)P;
     st->compat_violation = 0.0;
     const bem_prec prec = mixed ? BEM_PREC_MIXED : BEM_PREC_FP64;
     st->accepted = 0;
@@ -310,20 +319,21 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         st->chol_retries++;
     }
     st->lambda = lam;
-    if (hipMemcpyAsync(delta, g, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return set_error(ctx, BEM_EHIP, "copy gradient");
-    if ((rc = chol_solve(ctx, A, P, delta, s))) return rc;
     const int S = ctx->opts.segs_per_handle;
-    if (st->compat) {
+    if (!st->compat) {
+        if (hipMemcpyAsync(delta, g, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "copy gradient");
+        if ((rc = chol_solve(ctx, A, P, delta, 1, s))) return rc;
+    } else {
         // the step restricted to A^T delta = 0 (A at the current end points, whose segment table
-        // the normal equations left in place): X = Hd^{-1} A, then the 3x3 Schur complement
+        // the normal equations left in place): one solve of Hd [delta0 | X] = [g | A], then the
+        // 3x3 Schur complement
         if ((rc = fill_f64(ctx, cA, 3 * P, 0.0, s))) return rc;
         hipLaunchKernelGGL(k_compat_vectors, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->seg64.ptr, H,
                            S, P, cA);
-        if (hipMemcpyAsync(cX, cA, 3 * (size_t)P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return set_error(ctx, BEM_EHIP, "copy constraint vectors");
-        for (int c = 0; c < 3; ++c)
-            if ((rc = chol_solve(ctx, A, P, cX + (size_t)c * P, s))) return rc;
+        hipLaunchKernelGGL(k_pack_rhs, dim3(blocks_for(P, 256)), dim3(256), 0, s, (const double*)g,
+                           (const double*)cA, P, cX);
+        if ((rc = chol_solve(ctx, A, P, cX, 4, s))) return rc;
         hipLaunchKernelGGL(k_compat_solve, dim3(1), dim3(256), 0, s, (const double*)cA, (const double*)cX, P, delta);
     }
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
