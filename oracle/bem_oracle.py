@@ -489,11 +489,10 @@ def constrained_step(JtJ: np.ndarray, Jtr: np.ndarray, lam: float, A: np.ndarray
     return d0 - X @ nu
 
 
-def reproject(theta, S: int) -> np.ndarray:
-    """Orthogonal projection of the wc parameters onto a_c(theta) . theta = 0, with a_c taken at
-    theta's own end points (the re-projection after each update, Sec. 4.3)."""
+def project_compatible(theta, A: np.ndarray) -> np.ndarray:
+    """theta minus, per channel c, its component along a_c: the orthogonal projection onto
+    a_c . theta = 0 for the given vectors A [P, 3] (their supports are disjoint)."""
     theta = np.asarray(theta, dtype=np.float64).copy()
-    A = compat_vectors(theta, S)
     flat = theta.reshape(-1)
     for c in range(3):
         a = A[:, c]
@@ -503,8 +502,29 @@ def reproject(theta, S: int) -> np.ndarray:
     return flat.reshape(theta.shape)
 
 
-def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256):
+def reproject(theta, S: int) -> np.ndarray:
+    """Orthogonal projection of the wc parameters onto a_c(theta) . theta = 0, with a_c taken at
+    theta's own end points (the re-projection after each update, Sec. 4.3)."""
+    return project_compatible(theta, compat_vectors(theta, S))
+
+
+@dataclass(frozen=True)
+class HandleModel:
+    """The operations of one handle parametrisation that an LM step uses."""
+    evaluate: object
+    normal_equations: object
+    compat_vectors: object
+    reproject: object
+
+
+CUBIC = HandleModel(evaluate=evaluate, normal_equations=normal_equations, compat_vectors=compat_vectors,
+                    reproject=reproject)
+
+
+def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256, model: HandleModel = CUBIC):
     """One damped Gauss-Newton step with accept/reject on the same samples.  Returns (theta', state)."""
+    evaluate, normal_equations = model.evaluate, model.normal_equations
+    compat_vectors, reproject = model.compat_vectors, model.reproject
     theta = np.asarray(theta, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
     state.cbar_sum = state.cbar_sum + T.sum(axis=0)

@@ -44,6 +44,12 @@ class ConfigSpec:
     near_frac: float    # fraction of samples placed within 1e-3 of a handle segment
     lm_iters: int
     name: str
+    model: str = "cubic"              # "cubic": 20 parameters per handle; "straight": 10 (Sec. 4.1)
+    target_max: float | None = None   # targets clamped to at most this value (Sec. 4.3)
+
+    @property
+    def params_per_handle(self) -> int:
+        return 20 if self.model == "cubic" else 10
 
 
 SPECS = {
@@ -52,7 +58,14 @@ SPECS = {
     3: ConfigSpec(3, 128, 32, 1_048_576, 0.0, True, 0.1, 0, "mixed forward: 128 handles x 32 segments, 1,048,576 samples, 10% near a segment"),
     4: ConfigSpec(4, 256, 32, 4_194_304, 0.3, True, 0.0, 0, "differentiation: 256 handles x 32 segments, 4,194,304 samples"),
     5: ConfigSpec(5, 256, 32, 2_097_152, 0.2, True, 0.0, 50, "LM normal equations: 256 handles x 32 segments, 2,097,152 samples, P=5,120"),
+    # the paper's own setting: 500 straight handles placed by a Sobol sequence at 1/20 of the
+    # width (Sec. 4.2), 100,000 uniform samples per step, targets clamped at 1 (Sec. 4.3)
+    6: ConfigSpec(6, 500, 1, 100_000, 0.1, True, 0.0, 100,
+                  "paper-native: 500 straight handles (Sobol placement, length 1/20), 100,000 samples, P=5,000",
+                  model="straight", target_max=1.0),
 }
+PAPER_CONFIG = 6
+SOBOL_LENGTH = 1.0 / 20.0         # initial handle length: 1/20 of the image width (Sec. 4.2)
 
 
 def rng_for(config: int, stream: int, step: int = 0) -> np.random.Generator:
@@ -155,6 +168,30 @@ def draw_colours(rng: np.random.Generator, H: int) -> np.ndarray:
     return np.concatenate([wd[:, 0], wd[:, 1], wc[:, 0], wc[:, 1]], axis=1)
 
 
+def sobol_handles(n: int, seed: int, length: float = SOBOL_LENGTH) -> np.ndarray:
+    """End points [n, 4] = (A, B) of straight handles placed as in Sec. 4.2.
+
+    A comes from a scrambled Sobol sequence in the unit square (scipy's generator, direction
+    numbers of Joe and Kuo); B lies at distance `length` from A in the direction of a third
+    Sobol coordinate; B is then snapped into the domain (the unit square, the one subdomain
+    here) by clamping, which shortens handles that would leave it.
+    """
+    from scipy.stats import qmc
+    m = max(1, int(np.ceil(np.log2(max(n, 1)))))
+    u = qmc.Sobol(d=3, scramble=True, seed=np.random.default_rng(np.random.SeedSequence(entropy=seed))).random_base2(m)[:n]
+    a = u[:, :2]
+    ang = 2.0 * np.pi * u[:, 2]
+    b = np.clip(a + length * np.stack([np.cos(ang), np.sin(ang)], axis=1), 0.0, 1.0)
+    return np.concatenate([a, b], axis=1)
+
+
+def draw_straight_colours(rng: np.random.Generator, H: int) -> np.ndarray:
+    """Constant jumps [H, 6] = (wd RGB, wc RGB) from left/right colours uniform in [0,1], with
+    the same map as draw_colours (wd = cL - cR, wc = cL + cR - 1)."""
+    c = rng.uniform(0.0, 1.0, size=(H, 2, 3))
+    return np.concatenate([c[:, 0] - c[:, 1], c[:, 0] + c[:, 1] - 1.0], axis=1)
+
+
 def pack_theta(ctrl: np.ndarray, colours: np.ndarray) -> np.ndarray:
     H = ctrl.shape[0]
     return np.ascontiguousarray(np.concatenate([ctrl.reshape(H, 8), colours], axis=1), dtype=np.float64)
@@ -214,7 +251,14 @@ class Workload:
 
     @property
     def P(self) -> int:
-        return 20 * self.spec.H
+        return self.spec.params_per_handle * self.spec.H
+
+    def target(self, u_true: np.ndarray, step: int = 0, idx=None) -> np.ndarray:
+        """Noisy target from the noise-free reconstruction at the step's samples (rows idx of
+        them if given): u_true + sigma * noise, clamped at target_max when the workload sets it."""
+        nz = self.noise(step)
+        T = u_true + self.spec.sigma * (nz if idx is None else nz[idx])
+        return np.minimum(T, self.spec.target_max) if self.spec.target_max is not None else T
 
     def samples(self, step: int = 0, n: int | None = None) -> np.ndarray:
         n = self.spec.N if n is None else n
@@ -246,6 +290,16 @@ def pixel_grid(res: int = 512) -> np.ndarray:
 @lru_cache(maxsize=None)
 def make_config(config: int) -> Workload:
     spec = SPECS[config]
+    if spec.model == "straight":
+        # ground truth: Sobol-placed handles with random constant jumps; start: another Sobol
+        # placement (the initialisation of Sec. 4.2) with small random jumps
+        ends = sobol_handles(spec.H, seed=100 * config + GEOM)
+        theta_true = np.ascontiguousarray(
+            np.concatenate([ends, draw_straight_colours(rng_for(config, COLOUR), spec.H)], axis=1))
+        ends0 = sobol_handles(spec.H, seed=100 * config + PERTURB)
+        jumps0 = 0.05 * rng_for(config, PERTURB).standard_normal((spec.H, 6))
+        theta0 = np.ascontiguousarray(np.concatenate([ends0, jumps0], axis=1))
+        return Workload(spec=spec, theta_true=theta_true, theta0=theta0)
     ctrl = draw_geometry(config)
     theta_true = pack_theta(ctrl, draw_colours(rng_for(config, COLOUR), spec.H))
     rng = rng_for(config, PERTURB)
