@@ -15,11 +15,18 @@
  * (Eq. optimstep, Eq. losshessian, Eq. lossjacobian, Sec. 4.3).
  *
  * Conventions shared by every entry point
- *  - Handles: H cubic Bezier curves, each cut at t = k/S into S straight
- *    segments (K = H*S).  theta is [H,20] float64 row-major, per handle
+ *  - Handles (bem_opts.handle_model), each cut at t = k/S into S straight
+ *    segments (K = H*S); theta is [H,Q] float64 row-major, P = Q*H parameters,
+ *    and every Jacobian/gradient uses theta's column order.
+ *    BEM_HANDLE_CUBIC (Q = 20): cubic Bezier curves, per handle
  *      [P0x P0y P1x P1y P2x P2y P3x P3y | wd0 RGB | wd1 RGB | wc0 RGB | wc1 RGB]
  *    where wd/wc at end 0 (t=0) and end 1 (t=1) are interpolated linearly in t.
- *    P = 20*H parameters; every Jacobian/gradient uses this column order.
+ *    BEM_HANDLE_STRAIGHT (Q = 10): the paper's own handles (Sec. 3.2 line
+ *    segments; Sec. 4.1 two end points, jumps constant over the handle),
+ *      [Ax Ay Bx By | wd RGB | wc RGB],
+ *    the segment A -> B with vertices A + (k/S)(B - A).  S = 1 is exact: the
+ *    closed-form integrals of a straight piece with constant density do not
+ *    change under subdivision.
  *  - Orientation: a segment a->b has right normal n = (tau_y, -tau_x); wd is
  *    the colour on the left minus the colour on the right, wc the jump of the
  *    derivative along n.  The outer boundary is counter-clockwise, so n is
@@ -81,6 +88,9 @@ typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
  *                tile, float64 across thirds and tiles (fixed order). */
 typedef enum { BEM_GRAM_FP64 = 0, BEM_GRAM_FP32_MFMA = 1, BEM_GRAM_BF16X3_MFMA = 2 } bem_gram;
 
+/* Handle parametrisation (see the conventions above). */
+typedef enum { BEM_HANDLE_CUBIC = 0, BEM_HANDLE_STRAIGHT = 1 } bem_handle_model;
+
 typedef struct {
     int32_t elems_per_side;   /* outer elements per side of the unit square (256: length 1/256, Sec. 3.1.3) */
     int32_t segs_per_handle;  /* S >= 1 */
@@ -88,6 +98,7 @@ typedef struct {
     double near_factor;       /* MIXED near-pair threshold in segment lengths (1.0); > 0 */
     int32_t tile_rows;        /* sample rows per J tile in bem_jtj (0: automatic) */
     int32_t device;           /* HIP device ordinal the context lives on */
+    int32_t handle_model;     /* bem_handle_model: Q = 20 (cubic) or 10 (straight) parameters per handle */
 } bem_opts;
 
 /* Host-side state of the LM iteration (Sec. 4.3).  lambda is the damping
@@ -113,8 +124,9 @@ typedef struct {
  * Galerkin matrix A of Eq. bie_galerkin: A_ii = |G_i|/2, A_ij = 3x3-point
  * Gauss integral of dG/dn_y over G_i x G_j, the coincident term zero
  * (Sec. 3.1.3).  *out receives a new context (host).  opts is host memory,
- * copied.  Errors: EINVAL (null pointer, elems_per_side < 2 or > 4096,
- * S < 1 or > 1024, eps < 0 or not finite, near_factor <= 0), ENOMEM, EHIP. */
+ * copied.  Errors: EINVAL (null pointer, elems_per_side < 2 or > 1024,
+ * S < 1 or > 1024, eps < 0 or not finite, near_factor <= 0, bad
+ * handle_model), ENOMEM, EHIP. */
 int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out);
 
 /* One-time float64 factorisation (Sec. 3.1.3, factor once and reuse, Sec. 4.2):
@@ -130,7 +142,7 @@ int bem_factor(bem_ctx* ctx, hipStream_t stream);
  * alpha = 1 plus the mean colour, Sec. 3.1.3), where f is the handle term of
  * Eq. handleterm, U = A+ F the solved outer-boundary values with
  * F_i = int_{G_i} f by 3-point Gauss, and beta_j(x) = -int_{G_j} dG/dn_y.
- * theta [H,20] f64, x [N,2] f64, cbar[3] (host), u [N,3] row-major, float64
+ * theta [H,Q] f64, x [N,2] f64, cbar[3] (host), u [N,3] row-major, float64
  * for FP64 and float32 for MIXED.  H = 0 or N = 0 are allowed.
  * Errors: ESTATE (not factored), EINVAL, ENOMEM, EHIP. */
 int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
@@ -140,7 +152,7 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
  * the reverse-mode form of the differential BIE (Eq. diffbie): segment
  * adjoints over all samples, psi = sum_x gbar(x) beta(x), mu = A+^T psi, and
  * the segment adjoints at the boundary Gauss points with cotangent mu.
- * gbar [N,3] row-major (float64 for FP64, float32 for MIXED), grad [H,20]
+ * gbar [N,3] row-major (float64 for FP64, float32 for MIXED), grad [H,Q]
  * float64, overwritten.  The mean colour does not depend on theta.
  * Errors: as bem_eval. */
 int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
@@ -174,7 +186,7 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * parameters are projected orthogonally onto a_c . theta' = 0 with a_c at the
  * new end points; state->compat_violation reports what remains (rounding).
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
- * most 10 times) before ENOTPD.  theta [H,20] (device) is updated in place;
+ * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.
  * Errors: as bem_eval, ENOTPD, ENUMERIC (non-finite loss or step). */
 int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N,

@@ -358,7 +358,7 @@ def boundary_rhs_jacobian(theta: np.ndarray, S: int, eps: float, bnd: Boundary) 
 def boundary_derivative_values(theta, S, eps, bnd: Boundary) -> np.ndarray:
     """Z_c = A^+ dF_c/dtheta: the discretised differential BIE solved per column, [M, 3, P]."""
     dF = boundary_rhs_jacobian(theta, S, eps, bnd)
-    return np.einsum("ij,jcp->icp", bnd.Apinv, dF)
+    return (bnd.Apinv @ dF.reshape(bnd.M, -1)).reshape(dF.shape)
 
 
 def jacobian(theta, x, S: int, eps: float, per_side: int = 256) -> np.ndarray:

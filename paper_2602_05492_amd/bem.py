@@ -20,6 +20,8 @@ HEADER = os.path.join(HERE, "..", "include", "bem.h")
 
 PREC = {"fp64": 0, "mixed": 1}
 GRAM = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2}
+HANDLE_MODELS = {"cubic": 0, "straight": 1}
+PARAMS_PER_HANDLE = {"cubic": 20, "straight": 10}
 STATUS = {0: "BEM_OK", -1: "BEM_EINVAL", -2: "BEM_ENOMEM", -3: "BEM_ESTATE", -4: "BEM_ENOTPD",
           -5: "BEM_EHIP", -6: "BEM_ENUMERIC"}
 
@@ -32,7 +34,8 @@ class BemError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("elems_per_side", ctypes.c_int32), ("segs_per_handle", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("near_factor", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("near_factor", ctypes.c_double), ("tile_rows", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("handle_model", ctypes.c_int32)]
 
 
 class LMState(ctypes.Structure):
@@ -116,6 +119,7 @@ class Options:
     near_factor: float = 1.0
     tile_rows: int = 0
     device: int = 0
+    handle_model: str = "cubic"     # "cubic" (20 parameters per handle) or "straight" (10)
 
 
 class Context:
@@ -124,8 +128,11 @@ class Context:
     def __init__(self, opts: Options | None = None, **kw):
         self.opts = opts or Options(**kw)
         L = lib()
+        if self.opts.handle_model not in HANDLE_MODELS:
+            raise ValueError(f"handle_model must be one of {sorted(HANDLE_MODELS)}")
         o = Opts(self.opts.elems_per_side, self.opts.segs_per_handle, self.opts.eps, self.opts.near_factor,
-                 self.opts.tile_rows, self.opts.device)
+                 self.opts.tile_rows, self.opts.device, HANDLE_MODELS[self.opts.handle_model])
+        self.Q = PARAMS_PER_HANDLE[self.opts.handle_model]
         h = ctypes.c_void_p()
         with torch.cuda.device(self.opts.device):
             st = _stream()
@@ -155,8 +162,8 @@ class Context:
 
     def _theta_x(self, theta, x):
         _check_dev("theta", theta, torch.float64)
-        if theta.dim() != 2 or theta.shape[1] != 20:
-            raise ValueError("theta must be [H, 20]")
+        if theta.dim() != 2 or theta.shape[1] != self.Q:
+            raise ValueError(f"theta must be [H, {self.Q}] for {self.opts.handle_model} handles")
         if x is not None:
             _check_dev("x", x, torch.float64)
             if x.dim() != 2 or x.shape[1] != 2:
@@ -212,7 +219,9 @@ class Context:
         dt = torch.float64 if prec == "fp64" else torch.float32
         _check_dev("gbar", gbar, dt, (N, 3))
         if out is None:
-            out = torch.empty((H, 20), dtype=torch.float64, device=self.device)
+            out = torch.empty((H, self.Q), dtype=torch.float64, device=self.device)
+        else:
+            _check_dev("out", out, torch.float64, (H, self.Q))
         self._check(lib().bem_vjp(self._h, _ptr(theta), H, _ptr(x), N, _ptr(gbar), _ptr(out), PREC[prec], _stream()))
         return out
 
@@ -220,7 +229,7 @@ class Context:
         H, N = self._theta_x(theta, x)
         dt = torch.float64 if prec == "fp64" else torch.float32
         _check_dev("resid", resid, dt, (N, 3))
-        P_ = 20 * H
+        P_ = self.Q * H
         JtJ = torch.empty((P_, P_), dtype=torch.float64, device=self.device)
         Jtr = torch.empty((P_,), dtype=torch.float64, device=self.device)
         self._check(lib().bem_jtj(self._h, _ptr(theta), H, _ptr(x), N, _ptr(resid), _ptr(JtJ), _ptr(Jtr),
@@ -229,7 +238,7 @@ class Context:
 
     def jacobian(self, theta, x) -> torch.Tensor:
         H, N = self._theta_x(theta, x)
-        J = torch.empty((N, 3, 20 * H), dtype=torch.float64, device=self.device)
+        J = torch.empty((N, 3, self.Q * H), dtype=torch.float64, device=self.device)
         self._check(lib().bem_jacobian(self._h, _ptr(theta), H, _ptr(x), N, _ptr(J), _stream()))
         return J
 

@@ -168,6 +168,8 @@ int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
     if (!(o.near_factor > 0.0) || !std::isfinite(o.near_factor))
         return set_error(nullptr, BEM_EINVAL, "near_factor must be finite and > 0");
     if (o.tile_rows < 0) return set_error(nullptr, BEM_EINVAL, "tile_rows must be >= 0");
+    if (o.handle_model != BEM_HANDLE_CUBIC && o.handle_model != BEM_HANDLE_STRAIGHT)
+        return set_error(nullptr, BEM_EINVAL, "handle_model = %d is neither cubic (0) nor straight (1)", o.handle_model);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         hipGetLastError();
@@ -181,6 +183,11 @@ int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
     ctx->device = o.device;
     ctx->per_side = o.elems_per_side;
     ctx->M = 4 * o.elems_per_side;
+    ctx->model = o.handle_model;
+    const bool straight = o.handle_model == BEM_HANDLE_STRAIGHT;
+    ctx->npar = straight ? 10 : 20;
+    ctx->ngeo = straight ? 4 : 8;
+    ctx->ncol = straight ? 2 : 4;
     int rc = ensure(ctx, ctx->A, (size_t)ctx->M * ctx->M * sizeof(double), stream);
     if (!rc) rc = launch_assemble(ctx, stream);
     if (rc) {

@@ -79,6 +79,9 @@ struct bem_ctx {
     int per_side = 0;
     int state = 0;           // 0 empty, 1 built, 2 factored
     int device = 0;
+    // handle parametrisation: parameters per handle, and per handle in a feature row of the
+    // normal equations the geometry columns of one channel and the channel-shared colour columns
+    int model = 0, npar = 20, ngeo = 8, ncol = 4;
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;

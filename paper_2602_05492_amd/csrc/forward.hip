@@ -14,21 +14,23 @@ namespace {
 constexpr double kGaussNode = 0.77459666924148337703585307995647992;   // sqrt(3/5)
 constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
 
-// One thread per segment: vertices at t = j/S and j+1/S of the cubic Bezier,
-// jumps linear in t between the handle's two ends.
-__global__ void k_expand(const double* __restrict__ theta, int H, int S, double* __restrict__ seg64,
+// One thread per segment: vertices at t = j/S and j+1/S of the handle (cubic Bezier, or the
+// segment A -> B of a straight handle, model 1); cubic jumps linear in t between the handle's
+// two ends, straight jumps constant.
+__global__ void k_expand(const double* __restrict__ theta, int H, int S, int model, double* __restrict__ seg64,
                          float* __restrict__ seg32)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= H * S) return;
     const int h = k / S, j = k % S;
-    const double* th = theta + (size_t)h * 20;
+    const bool straight = model == 1;
+    const double* th = theta + (size_t)h * (straight ? 10 : 20);
     const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
     double wa[4], wb[4];
-    bernstein3(ta, wa);
-    bernstein3(tb, wb);
+    vertex_weights(model, ta, wa);
+    vertex_weights(model, tb, wb);
     double ax = 0, ay = 0, bx = 0, by = 0;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < (straight ? 2 : 4); ++c) {
         ax += wa[c] * th[2 * c]; ay += wa[c] * th[2 * c + 1];
         bx += wb[c] * th[2 * c]; by += wb[c] * th[2 * c + 1];
     }
@@ -42,10 +44,15 @@ __global__ void k_expand(const double* __restrict__ theta, int H, int S, double*
     rec[0] = ax; rec[1] = ay; rec[2] = bx; rec[3] = by; rec[4] = vx; rec[5] = vy;
     rec[6] = L2; rec[7] = kd; rec[8] = ks;
     for (int c = 0; c < 3; ++c) {
-        rec[kWdA + c] = (1.0 - ta) * th[8 + c] + ta * th[11 + c];
-        rec[kWdB + c] = (1.0 - tb) * th[8 + c] + tb * th[11 + c];
-        rec[kWcA + c] = (1.0 - ta) * th[14 + c] + ta * th[17 + c];
-        rec[kWcB + c] = (1.0 - tb) * th[14 + c] + tb * th[17 + c];
+        if (straight) {
+            rec[kWdA + c] = rec[kWdB + c] = th[4 + c];
+            rec[kWcA + c] = rec[kWcB + c] = th[7 + c];
+        } else {
+            rec[kWdA + c] = (1.0 - ta) * th[8 + c] + ta * th[11 + c];
+            rec[kWdB + c] = (1.0 - tb) * th[8 + c] + tb * th[11 + c];
+            rec[kWcA + c] = (1.0 - ta) * th[14 + c] + ta * th[17 + c];
+            rec[kWcB + c] = (1.0 - tb) * th[14 + c] + tb * th[17 + c];
+        }
     }
     rec[kIL2] = live ? 1.0 / L2 : 0.0;
     rec[22] = rec[23] = 0.0;
@@ -174,8 +181,8 @@ int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s)
     if ((rc = ensure(ctx, ctx->seg64, n * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->seg32, n * sizeof(float), s))) return rc;
     if (K == 0) return BEM_OK;
-    hipLaunchKernelGGL(k_expand, dim3(blocks_for(K, 256)), dim3(256), 0, s, theta, H, S, (double*)ctx->seg64.ptr,
-                       (float*)ctx->seg32.ptr);
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(K, 256)), dim3(256), 0, s, theta, H, S, ctx->model,
+                       (double*)ctx->seg64.ptr, (float*)ctx->seg32.ptr);
     return check_launch(ctx, "expand");
 }
 

@@ -4,11 +4,13 @@
 //   J_c(x) = df_c/dtheta(x) + sum_i beta_i(x) Z_c[i, :],   Z = A+ dF/dtheta.
 //
 // Per sample x and channel c the augmented row a_c(x) = [g_c(x) | e(x) | beta(x)]
-// holds the 8H geometry derivatives of f_c (control points), the 4H
-// channel-independent colour coefficients and the M outer-element weights, so
-// that J_c(x) = a_c(x) S_c with S_c = [E_c ; Z_c'] (E_c a column selection).
+// holds the G*H geometry derivatives of f_c, the C*H channel-independent colour
+// coefficients and the M outer-element weights, so that J_c(x) = a_c(x) S_c with
+// S_c = [E_c ; Z_c'] (E_c a column selection).  Cubic handles: G = 8 (control
+// points), C = 4 (wd and wc at both ends); straight handles: G = 4 (end points),
+// C = 2 (the constant wd and wc).
 // Sample tiles of feature rows Xt = [g_1 | g_2 | g_3 | e | beta] (feature-major,
-// W = 28H + M rows) are formed by the feature kernels and contracted into the
+// W = (3G + C)H + M rows) are formed by the feature kernels and contracted into the
 // Gram G = sum_x Xt Xt^T (only the blocks the three channels need), and into
 // R = sum_x Xt r.  Afterwards, per channel,
 //   J^T J += E_c^T A_c E_c + sym(E_c^T B_c Z_c') + Z_c'^T D Z_c'
@@ -62,19 +64,43 @@ template <> struct Store<uint16_t> {
     }
 };
 
+// Feature rows of one (point, handle): the chained gradients geo[c][q] on the four weights of
+// vertex_weights and the coefficients col[m] of wd0, wd1, wc0, wc1 (jumps at t = 0 and t = 1).
+// Cubic handles (model 0): rows c*8H + 8h + q and 24H + 4h + m.  Straight handles (model 1):
+// the end-point gradients are geo[c][0..3], rows c*4H + 4h + q, and the constant jumps take
+// the sum of their two end coefficients, rows 12H + 2h + {0: wd, 1: wc}.
+template <class OutT, class A>
+__device__ inline void store_handle_rows(int model, OutT* Xt, uint16_t* Xlo, int H, int h, int64_t t, int64_t ld,
+                                         const A (&geo)[3][8], const A (&col)[4])
+{
+    if (model == 1) {
+        for (int c = 0; c < 3; ++c)
+            for (int q = 0; q < 4; ++q)
+                Store<OutT>::put(Xt, Xlo, (int64_t)c * 4 * H + 4 * h + q, t, ld, (double)geo[c][q]);
+        Store<OutT>::put(Xt, Xlo, (int64_t)12 * H + 2 * h, t, ld, (double)col[0] + (double)col[1]);
+        Store<OutT>::put(Xt, Xlo, (int64_t)12 * H + 2 * h + 1, t, ld, (double)col[2] + (double)col[3]);
+        return;
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int q = 0; q < 8; ++q)
+            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
+}
+
 // Handle features of one point and one handle (thread per (point, handle)):
 //   rows c*8H + 8h + 2j + d : d f_c / d P_{h,j,d}      (c = 0..2, j = 0..3, d = x, y)
 //   rows 24H + 4h + m       : coefficient of wd0, wd1, wc0, wc1 of handle h (any channel)
 // The vertex gradient of the polyline is chained to control points with the
-// Bernstein weights of the vertex parameter t_k = k/S.
+// Bernstein weights of the vertex parameter t_k = k/S (straight handles: to the end
+// points with 1 - t_k, t_k; rows as store_handle_rows).
 //
 // Float64 (Mixed = false), or mixed with near pairs inline in float64: the latter
 // runs only for the samples flagged in `only` (their near-pair list overflowed).
 template <bool Mixed, class OutT>
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, int64_t npts,
                                                   const double* __restrict__ seg64, const float* __restrict__ seg32,
-                                                  int H, int S, double eps2, float eps2f, float near2,
-                                                  const uint8_t* __restrict__ only,
+                                                  int H, int S, int model, double eps2, float eps2f,
+                                                  float near2, const uint8_t* __restrict__ only,
                                                   OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
 {
     using A = typename std::conditional<Mixed, float, double>::type;
@@ -135,7 +161,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
             col[3] += m.sa * (A)ta + m.sb * (A)tb;
         }
         double B[4];
-        bernstein3((double)j / (double)S, B);
+        vertex_weights(model, (double)j / (double)S, B);
         for (int c = 0; c < 3; ++c) {
             const A gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
             for (int q = 0; q < 4; ++q) {
@@ -146,13 +172,10 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
             pv[c][1] = vb[c][1];
         }
     }
-    for (int c = 0; c < 3; ++c)
-        for (int q = 0; q < 8; ++q)
-            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
-    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
+    store_handle_rows(model, Xt, Xlo, H, h, t, ld, geo, col);
 }
 
-constexpr int kFeatVals = 28;   // chained contributions of one pair to the 28 handle rows
+constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] and col[4]
 
 // Mixed handle features: float32 pairs, near pairs skipped (same predicate as the
 // classification), then the float64 contributions of this sample's listed near pairs
@@ -162,7 +185,8 @@ constexpr int kFeatVals = 28;   // chained contributions of one pair to the 28 h
 // rewritten afterwards by k_features<true>.
 template <class OutT>
 __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
-                                                      const float* __restrict__ seg32, int H, int S, float eps2f,
+                                                      const float* __restrict__ seg32, int H, int S, int model,
+                                                      float eps2f,
                                                       float near2, const NearPair* __restrict__ list,
                                                       const int* __restrict__ wave_count,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
@@ -234,10 +258,7 @@ __global__ void __launch_bounds__(256) k_features_far(const double* __restrict__
             for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
         }
     }
-    for (int c = 0; c < 3; ++c)
-        for (int q = 0; q < 8; ++q)
-            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
-    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
+    store_handle_rows(model, Xt, Xlo, H, h, t, ld, geo, col);
 }
 
 // Zero the samples [n, n rounded up to 32) of every row of a blocked split-bfloat16
@@ -253,15 +274,15 @@ __global__ void k_zero_tail(uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl
     Xl[e] = 0;
 }
 
-// Vertex table of the float32 feature kernel: vtab[8 j + q] = B_q(t_j) (cubic
-// Bernstein weights), vtab[8 j + 4] = t_j, vtab[8 j + 5] = 1 - t_j, t_j = j / S.
-__global__ void k_vertex_table(int S, float* __restrict__ vtab)
+// Vertex table of the float32 feature kernel: vtab[8 j + q] = the vertex weights at t_j
+// (vertex_weights), vtab[8 j + 4] = t_j, vtab[8 j + 5] = 1 - t_j, t_j = j / S.
+__global__ void k_vertex_table(int S, int model, float* __restrict__ vtab)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j > S) return;
     const double t = (double)j / (double)S;
     double B[4];
-    bernstein3(t, B);
+    vertex_weights(model, t, B);
     for (int q = 0; q < 4; ++q) vtab[8 * j + q] = (float)B[q];
     vtab[8 * j + 4] = (float)t;
     vtab[8 * j + 5] = (float)(1.0 - t);
@@ -269,13 +290,15 @@ __global__ void k_vertex_table(int S, float* __restrict__ vtab)
 }
 
 // Float64 contributions of the listed near (sample, segment) pairs of one tile
-// (wavefronts w0 .. w0 + nw - 1) to the 28 handle rows: thread per list slot,
-// corr[slot][28], geometry rows already chained to control points.
+// (wavefronts w0 .. w0 + nw - 1) to one handle's features: thread per list slot,
+// corr[slot][28] = geo[3][8] and col[4] as in store_handle_rows (geometry already
+// chained with the vertex weights).
 __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list,
                                                        const int* __restrict__ wave_count,
                                                        const uint8_t* __restrict__ flag, int64_t w0, int64_t nw,
                                                        const double* __restrict__ x, const double* __restrict__ seg64,
-                                                       int K, int S, double eps2, float* __restrict__ corr)
+                                                       int K, int S, int model, double eps2,
+                                                       float* __restrict__ corr)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nw * kWaveSlots) return;
@@ -290,8 +313,8 @@ __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restric
     const int j = p.seg % S;
     const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
     double Ba[4], Bb[4];
-    bernstein3(ta, Ba);
-    bernstein3(tb, Bb);
+    vertex_weights(model, ta, Ba);
+    vertex_weights(model, tb, Bb);
     float* o = corr + (size_t)t * kFeatVals;
     const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
     const Moments<double> m = pair_moments(g, st);
@@ -371,83 +394,101 @@ __global__ void k_to_f64(const T* __restrict__ in, int64_t n, double* __restrict
     if (i < n) out[i] = (double)in[i];
 }
 
-// Channel-c augmented Gram in compact order [g_c (8H) | e (4H) | beta (M)],
+// Feature layout of the normal equations: G geometry rows per handle and channel, C
+// channel-shared colour rows per handle, H handles (the rows of Xt are
+// [g_0 (GH) | g_1 | g_2 | e (CH) | beta (M)]).
+struct Layout {
+    int G, C, H;
+    __host__ __device__ int64_t geo() const { return (int64_t)G * H; }
+    __host__ __device__ int64_t handle_rows() const { return (int64_t)(3 * G + C) * H; }
+    __host__ __device__ int compact() const { return (G + C) * H; }
+    __host__ __device__ int params() const { return G + 3 * C; }
+    // row of Xt of compact index a of channel c ([g_c | e | beta])
+    __host__ __device__ int64_t row(int a, int c) const
+    {
+        return a < geo() ? (int64_t)c * geo() + a : 2 * geo() + a;
+    }
+};
+
+// Channel-c augmented Gram in compact order [g_c (GH) | e (CH) | beta (M)],
 // symmetric fill from the upper triangle of G.
-__global__ void k_gather_gram(const double* __restrict__ G, int64_t W, int H, int c, int Wc, double* __restrict__ Gc)
+__global__ void k_gather_gram(const double* __restrict__ G, int64_t W, Layout L, int c, int Wc, double* __restrict__ Gc)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const int a = blockIdx.y;
     if (b >= Wc) return;
-    const int64_t ia = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)16 * H + a;
-    const int64_t ib = b < 8 * H ? (int64_t)c * 8 * H + b : (int64_t)16 * H + b;
+    const int64_t ia = L.row(a, c);
+    const int64_t ib = L.row(b, c);
     // the upper triangle holds every needed entry (diagonal tiles are computed whole); reading
     // it on both sides makes the gathered block exactly symmetric
     Gc[(size_t)a * Wc + b] = ia <= ib ? G[(size_t)ia * W + ib] : G[(size_t)ib * W + ia];
 }
 
-// Zc[i][a] = Z[i][col(a)], col(a) = a < 8H ? c*8H + a : 24H + (a - 8H)
-__global__ void k_gather_z(const double* __restrict__ Z, int H, int M, int c, double* __restrict__ Zc)
+// Zc[i][a] = Z[i][row(a)] for the handle part of the compact order (a < (G + C)H)
+__global__ void k_gather_z(const double* __restrict__ Z, Layout L, int M, int c, double* __restrict__ Zc)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
-    const int n = 12 * H;
+    const int n = L.compact();
     if (a >= n) return;
-    const int64_t src = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)24 * H + (a - 8 * H);
-    Zc[(size_t)i * n + a] = Z[(size_t)i * 28 * H + src];
+    Zc[(size_t)i * n + a] = Z[(size_t)i * L.handle_rows() + L.row(a, c)];
 }
 
-__device__ inline int64_t param_col(int a, int H, int c)
+// theta column of compact index a of channel c: geometry (G per handle, shared by the
+// channels) first, then the colour parameters, 3 per colour coefficient (RGB)
+__device__ inline int64_t param_col(int a, Layout L, int c)
 {
-    if (a < 8 * H) return (int64_t)20 * (a / 8) + (a % 8);
-    const int b = a - 8 * H;
-    return (int64_t)20 * (b / 4) + 8 + 3 * (b % 4) + c;
+    if (a < L.geo()) return (int64_t)L.params() * (a / L.G) + (a % L.G);
+    const int b = a - (int)L.geo();
+    return (int64_t)L.params() * (b / L.C) + L.G + 3 * (b % L.C) + c;
 }
 
 // JtJ[col(a)][col(b)] += s * (Gc[a][b] + T1[a][b] + T1[b][a] + T2[a][b]), T2 symmetrised so
 // that J^T J is exactly symmetric
 __global__ void k_scatter_h(const double* __restrict__ Gc, int Wc, const double* __restrict__ T1,
-                            const double* __restrict__ T2, int H, int c, double s, double* __restrict__ JtJ, int64_t P)
+                            const double* __restrict__ T2, Layout L, int c, double s, double* __restrict__ JtJ, int64_t P)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const int a = blockIdx.y;
-    const int n = 12 * H;
+    const int n = L.compact();
     if (b >= n) return;
     const double v = Gc[(size_t)a * Wc + b] + T1[(size_t)a * n + b] + T1[(size_t)b * n + a] +
                      0.5 * (T2[(size_t)a * n + b] + T2[(size_t)b * n + a]);
-    JtJ[param_col(a, H, c) * P + param_col(b, H, c)] += s * v;
+    JtJ[param_col(a, L, c) * P + param_col(b, L, c)] += s * v;
 }
 
-// Jtr[col(a)] += s * (R[idx(a)][c] + sum_i Zc[i][a] R[28H + i][c])
-__global__ void k_scatter_g(const double* __restrict__ R, const double* __restrict__ Zc, int H, int M, int c, double s,
-                            double* __restrict__ Jtr)
+// Jtr[col(a)] += s * (R[row(a)][c] + sum_i Zc[i][a] R[beta row i][c])
+__global__ void k_scatter_g(const double* __restrict__ R, const double* __restrict__ Zc, Layout L, int M, int c,
+                            double s, double* __restrict__ Jtr)
 {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = 12 * H;
+    const int n = L.compact();
     if (a >= n) return;
-    const int64_t idx = a < 8 * H ? (int64_t)c * 8 * H + a : (int64_t)16 * H + a;
-    double v = R[(size_t)idx * 3 + c];
-    for (int i = 0; i < M; ++i) v += Zc[(size_t)i * n + a] * R[((size_t)28 * H + i) * 3 + c];
-    Jtr[param_col(a, H, c)] += s * v;
+    double v = R[(size_t)L.row(a, c) * 3 + c];
+    for (int i = 0; i < M; ++i) v += Zc[(size_t)i * n + a] * R[((size_t)L.handle_rows() + i) * 3 + c];
+    Jtr[param_col(a, L, c)] += s * v;
 }
 
 // J[n][c][p] assembly for the explicit Jacobian: features + beta . Z
-__global__ void k_assemble_jacobian(const double* __restrict__ Xt, int64_t ld, const double* __restrict__ BZ, int H,
+__global__ void k_assemble_jacobian(const double* __restrict__ Xt, int64_t ld, const double* __restrict__ BZ, Layout L,
                                     int64_t npts, double* __restrict__ J)
 {
     const int64_t t = blockIdx.y;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int P = 20 * H;
+    const int Q = L.params();
+    const int P = Q * L.H;
+    const int64_t nf = L.handle_rows();
     if (p >= P || t >= npts) return;
-    const int h = p / 20, q = p % 20;
+    const int h = p / Q, q = p % Q;
     for (int c = 0; c < 3; ++c) {
         double v;
-        if (q < 8) {
-            const int64_t f = (int64_t)c * 8 * H + 8 * h + q;
-            v = Xt[(size_t)f * ld + t] + BZ[(size_t)t * 28 * H + f];
+        if (q < L.G) {
+            const int64_t f = (int64_t)c * L.geo() + (int64_t)L.G * h + q;
+            v = Xt[(size_t)f * ld + t] + BZ[(size_t)t * nf + f];
         } else {
-            const int m = (q - 8) / 3, cc = (q - 8) % 3;
-            const int64_t f = (int64_t)24 * H + 4 * h + m;
-            v = cc == c ? Xt[(size_t)f * ld + t] + BZ[(size_t)t * 28 * H + f] : 0.0;
+            const int m = (q - L.G) / 3, cc = (q - L.G) % 3;
+            const int64_t f = 3 * L.geo() + (int64_t)L.C * h + m;
+            v = cc == c ? Xt[(size_t)f * ld + t] + BZ[(size_t)t * nf + f] : 0.0;
         }
         J[((size_t)t * 3 + c) * P + p] = v;
     }
@@ -464,9 +505,11 @@ int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
     return check_launch(ctx, "fill");
 }
 
+static Layout layout_of(const bem_ctx* ctx, int H) { return Layout{ctx->ngeo, ctx->ncol, H}; }
+
 // Feature rows of npts points into Xt (ld: row stride of float64 / float32 tiles,
-// row count of the blocked bfloat16 tile); rows 0..28H-1 handle
-// features, rows 28H.. beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
+// row count of the blocked bfloat16 tile); rows 0..(3G + C)H - 1 handle
+// features, the next M rows beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
 // Mixed precision needs the near-pair list of the whole sample set (nl), the tile's
 // first global sample index t0 (a multiple of 64), the global samples xg and a
 // correction buffer of ceil(npts / 64) * kWaveSlots * 28 floats.
@@ -477,9 +520,11 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
+    const int model = ctx->model;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     const double nf = 2.0 * ctx->opts.near_factor;
     const float near2 = (float)(nf * nf);
+    const int64_t beta_row0 = layout_of(ctx, H).handle_rows();
     const dim3 grid(blocks_for(npts, 256), H);
     if (mixed && (!nl || !xg || !corr || !vtab || (t0 & 63)))
         return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
@@ -489,20 +534,20 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             {
                 ProfScope ps_(ctx, PT_NEAR, s);
                 hipLaunchKernelGGL(k_features_near, dim3(blocks_for(nw * kWaveSlots, 256)), dim3(256), 0, s, nl->list,
-                                   nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, eps2,
-                                   corr);
+                                   nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, model,
+                                   eps2, corr);
             }
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
-                               H, S, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo, ld);
+                               H, S, model, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo, ld);
             hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, nl->flag + t0, Xt, Xlo,
-                               ld);
+                               (const float*)ctx->seg32.ptr, H, S, model, eps2, (float)eps2, near2, nl->flag + t0, Xt,
+                               Xlo, ld);
         } else {
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, eps2, (float)eps2, near2, (const uint8_t*)nullptr,
-                               Xt, Xlo, ld);
+                               (const float*)ctx->seg32.ptr, H, S, model, eps2, (float)eps2, near2,
+                               (const uint8_t*)nullptr, Xt, Xlo, ld);
         }
     }
     if (with_beta) {
@@ -511,24 +556,24 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             {
                 ProfScope ps_(ctx, PT_BETA_ROWS, s);
                 hipLaunchKernelGGL((k_beta_rows<true, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, beta_row0);
             }
         else
             {
                 ProfScope ps_(ctx, PT_BETA_ROWS, s);
                 hipLaunchKernelGGL((k_beta_rows<false, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, (int64_t)28 * H);
+                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, beta_row0);
             }
     }
     return check_launch(ctx, "features");
 }
 
-// Z = A+ dF/dtheta in compact feature columns [M][28H] -> ctx->tmp4 (also leaves Gauss features in tmp3)
+// Z = A+ dF/dtheta in feature columns [M][(3G + C)H] -> ctx->tmp4 (also leaves Gauss features in tmp3)
 int boundary_derivatives(bem_ctx* ctx, int H, hipStream_t s, double** Zout)
 {
     int rc;
     const int M = ctx->M;
-    const int nf = 28 * H;
+    const int nf = (int)layout_of(ctx, H).handle_rows();
     const size_t gxs = (size_t)3 * M * 2;
     if ((rc = ensure(ctx, ctx->tmp3, (gxs + (size_t)nf * 3 * M) * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->tmp4, (size_t)2 * M * nf * sizeof(double), s))) return rc;
@@ -547,16 +592,17 @@ int boundary_derivatives(bem_ctx* ctx, int H, hipStream_t s, double** Zout)
     return BEM_OK;
 }
 
-static std::vector<int> gram_tiles(int H, int W, int ts)
+static std::vector<int> gram_tiles(const Layout& L, int W, int ts)
 {
     // upper-triangle ts x ts tiles, skipping pairs of tiles that lie inside two
     // different channels' geometry blocks (those products never enter J^T J)
     const int nt = (W + ts - 1) / ts;
+    const int64_t g = L.geo();
     auto region = [&](int t) {
         const int64_t lo = (int64_t)t * ts, hi = lo + ts - 1;
-        if (lo >= 24LL * H) return -1;                           // colour coefficients / beta: shared
-        if (hi >= 24LL * H) return -2;                           // straddles geometry and shared rows
-        const int64_t c0 = lo / (8LL * H), c1 = hi / (8LL * H);
+        if (lo >= 3 * g) return -1;                              // colour coefficients / beta: shared
+        if (hi >= 3 * g) return -2;                              // straddles geometry and shared rows
+        const int64_t c0 = lo / g, c1 = hi / g;
         return c0 == c1 ? (int)c0 : -2;
     };
     std::vector<int> t;
@@ -612,10 +658,11 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
 {
     int rc;
     const int M = ctx->M;
-    const int64_t P = 20 * (int64_t)H;
-    const int64_t W = 28 * (int64_t)H + M;
-    const int Wc = 12 * H + M;
-    const int n12 = 12 * H;
+    const Layout L = layout_of(ctx, H);
+    const int64_t P = (int64_t)L.params() * H;
+    const int64_t W = L.handle_rows() + M;
+    const int n12 = L.compact();          // handle part of one channel's compact order
+    const int Wc = n12 + M;
     if (H == 0) return BEM_OK;
     if ((rc = prepare_forward_tables(ctx, theta, H, s))) return rc;
     double* Z = nullptr;
@@ -659,8 +706,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)resid, 3 * N, r64);
     }
     const int ts = gram == BEM_GRAM_FP64 ? 64 : (gram == BEM_GRAM_FP32_MFMA ? 128 : 256);
-    const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(H, (int)W, ts)
-                                                         : gram_work(gram_tiles(H, (int)W, ts), parts);
+    const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(L, (int)W, ts)
+                                                         : gram_work(gram_tiles(L, (int)W, ts), parts);
     const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
     // tmp5: tile list, the vertex table, then the near-pair corrections of one sample tile
     const int S = ctx->opts.segs_per_handle;
@@ -670,7 +717,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + vtab_bytes + corr_floats * sizeof(float) + 256, s))) return rc;
     float* vtab = (float*)((char*)ctx->tmp5.ptr + tiles_bytes);
     float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes) : nullptr;
-    hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, vtab);
+    hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
     NearList nl{};
     if (mixed && N > 0) {
         if (pre) nl = *pre;
@@ -732,20 +779,20 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     double* T2 = T1 + (size_t)n12 * n12;
     double* W1 = T2 + (size_t)n12 * n12;
     for (int c = 0; c < 3; ++c) {
-        hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, H, c, Wc, Gc);
-        hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, H, M, c, Zc);
+        hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, L, c, Wc, Gc);
+        hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, L, M, c, Zc);
         if ((rc = check_launch(ctx, "gather"))) return rc;
-        // T1 = B_c Zc   (B_c = Gc[0:12H, 12H:Wc])
+        // T1 = B_c Zc   (B_c = Gc[0:n12, n12:Wc])
         if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, T1, n12, s, nullptr, 0))) return rc;
-        // W1 = D Zc    (D = Gc[12H:, 12H:])
+        // W1 = D Zc    (D = Gc[n12:, n12:])
         if ((rc = gemm_f64(ctx, M, n12, M, 1.0, Gc + (size_t)n12 * Wc + n12, Wc, false, Zc, n12, false, 0.0, W1, n12, s,
                            nullptr, 0)))
             return rc;
         // T2 = Zc^T W1
         if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Zc, n12, true, W1, n12, false, 0.0, T2, n12, s, nullptr, 0))) return rc;
-        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, T1, T2, H, c, sc, JtJ, P);
+        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, T1, T2, L, c, sc, JtJ, P);
         if (want_r)
-            hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, H, M, c, sc, Jtr);
+            hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, L, M, c, sc, Jtr);
         if ((rc = check_launch(ctx, "scatter"))) return rc;
     }
     return BEM_OK;
@@ -755,21 +802,24 @@ int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int6
 {
     int rc;
     const int M = ctx->M;
-    const int64_t W = 28 * (int64_t)H + M;
+    const Layout L = layout_of(ctx, H);
+    const int nf = (int)L.handle_rows();
+    const int64_t W = nf + M;
     if (H == 0 || N == 0) return BEM_OK;
     if ((rc = prepare_forward_tables(ctx, theta, H, s))) return rc;
     double* Z = nullptr;
     if ((rc = boundary_derivatives(ctx, H, s, &Z))) return rc;
     const int64_t ld = N;
-    if ((rc = ensure(ctx, ctx->tmp0, ((size_t)W * N + (size_t)N * 28 * H) * sizeof(double), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp0, ((size_t)W * N + (size_t)N * nf) * sizeof(double), s))) return rc;
     double* Xt = (double*)ctx->tmp0.ptr;
     double* BZ = Xt + (size_t)W * N;
     if ((rc = launch_features<double>(ctx, x, N, H, false, true, Xt, nullptr, ld, s))) return rc;
     // BZ[t][f] = sum_i beta_i(t) Z[i][f]  (beta rows of Xt transposed)
-    if ((rc = gemm_f64(ctx, (int)N, 28 * H, M, 1.0, Xt + (size_t)28 * H * ld, ld, true, Z, 28 * H, false, 0.0, BZ, 28 * H,
-                       s, nullptr, 0)))
+    if ((rc = gemm_f64(ctx, (int)N, nf, M, 1.0, Xt + (size_t)nf * ld, ld, true, Z, nf, false, 0.0, BZ, nf, s, nullptr,
+                       0)))
         return rc;
-    hipLaunchKernelGGL(k_assemble_jacobian, dim3(blocks_for(20 * H, 256), N), dim3(256), 0, s, Xt, ld, BZ, H, N, J);
+    hipLaunchKernelGGL(k_assemble_jacobian, dim3(blocks_for((int64_t)L.params() * H, 256), N), dim3(256), 0, s, Xt, ld,
+                       BZ, L, N, J);
     return check_launch(ctx, "jacobian");
 }
 

@@ -56,10 +56,13 @@ __global__ void __launch_bounds__(256) k_rowsum(const UT* __restrict__ u, const 
 
 // ---- compatibility condition (Sec. 3.1.2) and its enforcement (Sec. 4.3) -------------------
 // A [3][P]: a_c . theta = int over the handles of w_c for fixed end points.  A segment's jump is
-// linear between its end values, so per handle alpha_h = sum_k L_k (2 - t_k - t_{k+1}) / 2 at
-// wc0_{h,c} and beta_h = sum_k L_k (t_k + t_{k+1}) / 2 at wc1_{h,c}; thread per handle, from the
-// float64 segment table (degenerate segments have L2 = 0 there).  A must be zero beforehand.
-__global__ void k_compat_vectors(const double* __restrict__ seg64, int H, int S, int64_t P, double* __restrict__ A)
+// linear between its end values, so per cubic handle alpha_h = sum_k L_k (2 - t_k - t_{k+1}) / 2
+// at wc0_{h,c} and beta_h = sum_k L_k (t_k + t_{k+1}) / 2 at wc1_{h,c}; a straight handle's
+// constant wc_{h,c} has the coefficient alpha_h + beta_h = sum_k L_k (model 1).  Thread per
+// handle, from the float64 segment table (degenerate segments have L2 = 0 there).  A must be
+// zero beforehand.
+__global__ void k_compat_vectors(const double* __restrict__ seg64, int H, int S, int model, int64_t P,
+                                 double* __restrict__ A)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= H) return;
@@ -71,8 +74,12 @@ __global__ void k_compat_vectors(const double* __restrict__ seg64, int H, int S,
         beta += L * (ta + tb) / 2.0;
     }
     for (int c = 0; c < 3; ++c) {
-        A[(size_t)c * P + (size_t)h * 20 + 14 + c] = alpha;
-        A[(size_t)c * P + (size_t)h * 20 + 17 + c] = beta;
+        if (model == 1) {
+            A[(size_t)c * P + (size_t)h * 10 + 7 + c] = alpha + beta;
+        } else {
+            A[(size_t)c * P + (size_t)h * 20 + 14 + c] = alpha;
+            A[(size_t)c * P + (size_t)h * 20 + 17 + c] = beta;
+        }
     }
 }
 
@@ -247,12 +254,12 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
                 int gram, bool mixed, hipStream_t s)
 {
     int rc;
-    const int64_t P = 20 * (int64_t)H;
+    const int64_t P = (int64_t)ctx->npar * H;
     const size_t ue = mixed ? sizeof(float) : sizeof(double);
     const int64_t n3 = 3 * (N > 0 ? N : 1);
     // lm workspace layout (ctx->lmw): u | r | g | JtJ | (spare P) | A | delta | theta' | partials | flag |
     // compatibility vectors [3][P] | right-hand sides [P][4] | violation
-    const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)20 * H +
+    const size_t bytes = 2 * (size_t)n3 * ue + ((size_t)P + 2 * (size_t)P * P + 2 * (size_t)P + (size_t)P +
                                                  3 * (size_t)kRedBlocks + 8 + 7 * (size_t)P + 8) * sizeof(double) + 64;
     if ((rc = ensure(ctx, ctx->lmw, bytes, s))) return rc;
     char* base = (char*)ctx->lmw.ptr;
@@ -263,7 +270,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     double* A = JtJ + (size_t)P * P + P;
     double* delta = A + (size_t)P * P;
     double* th1 = delta + P;
-    double* dpart = th1 + (size_t)20 * H;
+    double* dpart = th1 + (size_t)P;
     int* dflag = (int*)(dpart + 3 * kRedBlocks + 4);
     double* cA = dpart + 3 * kRedBlocks + 8;
     double* cX = cA + 3 * (size_t)P;          // [P][4]: gradient and the three a_c, solved in place
@@ -330,7 +337,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         // 3x3 Schur complement
         if ((rc = fill_f64(ctx, cA, 3 * P, 0.0, s))) return rc;
         hipLaunchKernelGGL(k_compat_vectors, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->seg64.ptr, H,
-                           S, P, cA);
+                           S, ctx->model, P, cA);
         hipLaunchKernelGGL(k_pack_rhs, dim3(blocks_for(P, 256)), dim3(256), 0, s, (const double*)g,
                            (const double*)cA, P, cX);
         if ((rc = chol_solve(ctx, A, P, cX, 4, s))) return rc;
@@ -345,7 +352,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         if ((rc = launch_expand(ctx, th1, H, s))) return rc;
         if ((rc = fill_f64(ctx, cA, 3 * P, 0.0, s))) return rc;
         hipLaunchKernelGGL(k_compat_vectors, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->seg64.ptr, H,
-                           S, P, cA);
+                           S, ctx->model, P, cA);
         hipLaunchKernelGGL(k_reproject, dim3(1), dim3(256), 0, s, (const double*)cA, P, th1, cviol);
         hipLaunchKernelGGL(k_finite, dim3(blocks_for(P, 256)), dim3(256), 0, s, th1, P, dflag);
         if ((rc = check_launch(ctx, "compatibility"))) return rc;

@@ -257,4 +257,19 @@ BEM_HD inline void bernstein3(T t, T w[4])
     w[3] = t * t * t;
 }
 
+// Weights of the polyline vertex at t on the handle's geometry parameters: the four cubic
+// Bernstein weights of the control points, or (1 - t, t, 0, 0) on the end points of a
+// straight handle (model 1).
+template <class T>
+BEM_HD inline void vertex_weights(int model, T t, T w[4])
+{
+    if (model == 1) {
+        w[0] = T(1) - t;
+        w[1] = t;
+        w[2] = w[3] = T(0);
+    } else {
+        bernstein3(t, w);
+    }
+}
+
 }  // namespace bem

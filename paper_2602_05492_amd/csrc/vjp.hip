@@ -310,22 +310,32 @@ __global__ void k_gauss_cotangent(const double* __restrict__ mu, int M, int m, d
     for (int c = 0; c < 3; ++c) gc[3 * t + c] = mu[3 * i + c] * w;
 }
 
-// Segment sums -> theta gradient: one thread per handle.
-__global__ void k_chain_theta(const double* __restrict__ sg, int H, int S, double* __restrict__ grad)
+// Segment sums -> theta gradient: one thread per handle.  Cubic handles chain the vertex
+// gradients to the control points with Bernstein weights and the end jumps with (1 - t, t);
+// straight handles (model 1) chain them to the end points with (1 - t, t) and sum the jumps.
+__global__ void k_chain_theta(const double* __restrict__ sg, int H, int S, int model, double* __restrict__ grad)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= H) return;
     double out[20];
     for (int p = 0; p < 20; ++p) out[p] = 0.0;
+    const bool straight = model == 1;
     for (int j = 0; j < S; ++j) {
         const double* v = sg + ((size_t)h * S + j) * kV;
         const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
         double Ba[4], Bb[4];
-        bernstein3(ta, Ba);
-        bernstein3(tb, Bb);
+        vertex_weights(model, ta, Ba);
+        vertex_weights(model, tb, Bb);
         for (int c = 0; c < 4; ++c) {
             out[2 * c] += Ba[c] * v[0] + Bb[c] * v[2];
             out[2 * c + 1] += Ba[c] * v[1] + Bb[c] * v[3];
+        }
+        if (straight) {
+            for (int c = 0; c < 3; ++c) {
+                out[4 + c] += v[4 + c] + v[7 + c];       // wd
+                out[7 + c] += v[10 + c] + v[13 + c];     // wc
+            }
+            continue;
         }
         for (int c = 0; c < 3; ++c) {
             out[8 + c] += (1.0 - ta) * v[4 + c] + (1.0 - tb) * v[7 + c];     // wd at end 0
@@ -334,7 +344,8 @@ __global__ void k_chain_theta(const double* __restrict__ sg, int H, int S, doubl
             out[17 + c] += ta * v[10 + c] + tb * v[13 + c];                  // wc at end 1
         }
     }
-    for (int p = 0; p < 20; ++p) grad[(size_t)h * 20 + p] = out[p];
+    const int q = straight ? 10 : 20;
+    for (int p = 0; p < q; ++p) grad[(size_t)h * q + p] = out[p];
 }
 
 int chunks_for(int64_t N, int groups, int64_t& chunk)
@@ -445,7 +456,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, 0,
                            (int64_t)K * kV, (double*)ctx->red.ptr);
     }
-    hipLaunchKernelGGL(k_chain_theta, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->red.ptr, H, S, grad);
+    hipLaunchKernelGGL(k_chain_theta, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->red.ptr, H, S,
+                       ctx->model, grad);
     return check_launch(ctx, "vjp");
 }
 

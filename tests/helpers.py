@@ -10,10 +10,11 @@ def log(*a):
 
 
 @functools.lru_cache(maxsize=None)
-def ctx_for(S: int, eps: float = 1e-2, per_side: int = 256, near_factor: float = 1.0, tile_rows: int = 0):
+def ctx_for(S: int, eps: float = 1e-2, per_side: int = 256, near_factor: float = 1.0, tile_rows: int = 0,
+            handle_model: str = "cubic"):
     from paper_2602_05492_amd import bem as B
     return B.Context(segs_per_handle=S, eps=eps, elems_per_side=per_side, near_factor=near_factor,
-                     tile_rows=tile_rows)
+                     tile_rows=tile_rows, handle_model=handle_model)
 
 
 def dev(a, dtype=None):

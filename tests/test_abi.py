@@ -25,14 +25,15 @@ def test_binding_covers_every_declared_symbol():
 
 
 def _opts(**kw):
-    o = dict(elems_per_side=256, segs_per_handle=32, eps=1e-2, near_factor=1.0, tile_rows=0, device=0)
+    o = dict(elems_per_side=256, segs_per_handle=32, eps=1e-2, near_factor=1.0, tile_rows=0, device=0,
+             handle_model=0)
     o.update(kw)
     return B.Opts(**o)
 
 
 @pytest.mark.parametrize("bad", [dict(elems_per_side=1), dict(elems_per_side=5000), dict(segs_per_handle=0),
                                  dict(eps=-1.0), dict(eps=float("nan")), dict(near_factor=0.0),
-                                 dict(tile_rows=-3)])
+                                 dict(tile_rows=-3), dict(handle_model=2), dict(handle_model=-1)])
 def test_build_rejects_bad_options(bad):
     L = B.lib()
     h = ctypes.c_void_p()
@@ -40,6 +41,15 @@ def test_build_rejects_bad_options(bad):
     assert rc == -1
     assert h.value is None
     assert L.bem_last_error(None)
+
+
+def test_opts_struct_matches_header():
+    """bem_opts: the binding's field order and sizes are the header's."""
+    src = open(B.HEADER).read()
+    body = src[src.index("typedef struct {\n    int32_t elems_per_side"):]
+    body = body[:body.index("} bem_opts;")]
+    fields = [ln.split(";")[0].split()[-1] for ln in body.splitlines()[1:] if ";" in ln]
+    assert fields == [f[0] for f in B.Opts._fields_]
 
 
 def test_null_arguments():
