@@ -4,9 +4,12 @@
 One step = one full LM iteration on a fresh batch of samples: mean colour,
 forward sweep, residual and loss, gradient by the adjoint, J tiles and Gram
 contraction for J^T J, float64 Cholesky solve, trial forward and
-accept/reject (the whole hot path).  Workload: 256 cubic handles x 32
-segments (P = 5,120 parameters), 2,097,152 uniform samples per step with
-Gaussian target noise sigma = 0.2, eps = 1e-2, 256 outer elements per side.
+accept/reject (the whole hot path).  Default workload (--workload lm): 256
+cubic handles x 32 segments (P = 5,120 parameters), 2,097,152 uniform samples
+per step with Gaussian target noise sigma = 0.2, eps = 1e-2, 256 outer
+elements per side.  --workload paper: the paper's own setting, 500 straight
+handles (10 parameters each, one piece, Sobol placement at 1/20 width),
+100,000 uniform samples per step, sigma = 0.1, targets clamped at 1.
 Batches are generated and placed in HBM before the timed region.
 
 Prints one JSON line.  `roofline` is for the kernel family with the largest
@@ -57,9 +60,34 @@ F_BOUNDARY_PAIR = 40.0     # forward / adjoint: one sample x one outer element
 F_GRAD_PAIR = 300.0        # adjoint or J-tile: one sample x one handle segment
 
 
-def gram_entries(H: int, M: int) -> int:
+WORKLOADS = {"lm": 5, "paper": 6}
+WORKLOAD_TEXT = {
+    "lm": "LM normal equations: 256 cubic handles x 32 segments (P = 5,120), 2,097,152 uniform samples per step, "
+          "sigma 0.2, eps 1e-2, 1,024 outer elements",
+    "paper": "paper-native: 500 straight handles x 1 segment (P = 5,000; Sobol placement, length 1/20), 100,000 "
+             "uniform samples per step, sigma 0.1, targets clamped at 1, eps 1e-2, 1,024 outer elements",
+}
+# feature rows per handle of the normal equations: geometry per channel, channel-shared colour
+FEATURE_ROWS = {"cubic": (8, 4), "straight": (4, 2)}
+
+
+def make_context(wl):
+    from paper_2602_05492_amd import bem as B
+    return B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side, handle_model=wl.spec.model)
+
+
+def make_target(ctx, wl, tht, x, step):
+    """Noise-free reconstruction of the ground truth plus the workload's noise (clamped where the
+    workload clamps), on the GPU."""
+    import torch
+    T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(step)).cuda()
+    return T.clamp_(max=wl.spec.target_max) if wl.spec.target_max is not None else T
+
+
+def gram_entries(H: int, M: int, model: str = "cubic") -> int:
     """Distinct Gram entries J^T J needs per sample (symmetric blocks counted once)."""
-    g, s = 8 * H, 4 * H + M
+    fg, fc = FEATURE_ROWS[model]
+    g, s = fg * H, fc * H + M
     return 3 * (g * (g + 1) // 2) + 3 * g * s + s * (s + 1) // 2
 
 
@@ -105,20 +133,20 @@ def pmc_probe() -> int:
     return 0
 
 
-def lm_curve(steps: int, gram: str, prec: str) -> int:
-    """LM iterations of the LM workload with fresh samples per step; one JSON line per step."""
+def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int) -> int:
+    """LM iterations of a workload with fresh samples per step; one JSON line per step."""
     import numpy as np
     import torch
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
-    wl = W.make_config(5)
-    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
+    wl = W.make_config(WORKLOADS[workload])
+    ctx = make_context(wl)
     tht = torch.from_numpy(wl.theta_true).cuda()
     c = (np.arange(512) + 0.5) / 512
     grid = torch.from_numpy(np.stack(np.meshgrid(c, c, indexing="xy"), -1).reshape(-1, 2).copy()).cuda()
     truth = ctx.eval(tht, grid, wl.cbar_true, "fp64")
     theta = torch.from_numpy(wl.theta0).cuda()
-    st = B.new_lm_state(wl.lam0, 0)
+    st = B.new_lm_state(wl.lam0, 0, compat=compat)
 
     def rmse(cbar):
         u = ctx.eval(theta, grid, tuple(cbar), "fp64")
@@ -126,7 +154,7 @@ def lm_curve(steps: int, gram: str, prec: str) -> int:
 
     for i in range(steps):
         x = torch.from_numpy(wl.samples(i)).cuda()
-        T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(i)).cuda()
+        T = make_target(ctx, wl, tht, x, i)
         if i == 0:   # the start, with the mean colour the first step will use
             print(json.dumps({"step": 0, "rmse": rmse(T.mean(0).tolist())}), flush=True)
         t = time.perf_counter()
@@ -150,7 +178,8 @@ def _cpu_baseline(wl, x_host, budget_note: str) -> dict:
     import numpy as np
     import oracle as O
     S, eps = wl.S, wl.eps
-    th = wl.theta0
+    # straight handles are evaluated by the oracle as the equivalent cubic handles
+    th = wl.theta0 if wl.spec.model == "cubic" else O.straight.embed(wl.theta0)
     bnd = O.boundary(wl.elems_per_side)                 # one-time factor, not part of a step
     gp = bnd.gp.reshape(-1, 2)
     n_eval, n_jac, n_gp = 256, 64, 192
@@ -176,7 +205,7 @@ def _cpu_baseline(wl, x_host, budget_note: str) -> dict:
     step = 2 * (N * t_eval + t_rhs) + t_z + N * t_jac
     return {"value": 1.0 / step, "unit": "LM steps/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle (numpy FP64, one process) timed on {n_eval} samples (forward), {n_jac} samples "
-                       f"(Jacobian rows + Gram) and {n_gp} of {len(gp)} boundary Gauss points of the LM workload, "
+                       f"(Jacobian rows + Gram) and {n_gp} of {len(gp)} boundary Gauss points of the workload, "
                        f"extrapolated linearly to one step of {N:,} samples: {step:.3e} s/step. {budget_note}")}
 
 
@@ -191,6 +220,9 @@ def main() -> int:
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--compat", type=int, default=0,
                     help="enforce the compatibility condition in every LM step (constrained step + re-projection)")
+    ap.add_argument("--workload", default="lm", choices=sorted(WORKLOADS),
+                    help="lm: 256 cubic handles x 32 segments, 2,097,152 samples; paper: 500 straight handles, "
+                         "100,000 samples")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
     ap.add_argument("--lm-curve", type=int, default=0,
                     help="instead of timing: run this many LM steps (fresh samples each) and print loss, lambda and "
@@ -199,7 +231,7 @@ def main() -> int:
     if args.pmc_probe:
         return pmc_probe()
     if args.lm_curve:
-        return lm_curve(args.lm_curve, args.gram, args.prec)
+        return lm_curve(args.lm_curve, args.gram, args.prec, args.workload, args.compat)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built "
@@ -211,8 +243,8 @@ def main() -> int:
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
 
-    wl = W.make_config(5)
-    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
+    wl = W.make_config(WORKLOADS[args.workload])
+    ctx = make_context(wl)
     H, S, N, M = wl.H, wl.S, wl.N, ctx.M
     K = H * S
     nb = args.warmup + args.steps
@@ -224,8 +256,7 @@ def main() -> int:
         if x0_host is None:
             x0_host = xh
         x = torch.from_numpy(xh).cuda()
-        T = ctx.eval(tht, x, wl.cbar_true, "fp64") + wl.spec.sigma * torch.from_numpy(wl.noise(i)).cuda()
-        batches.append((x, T))
+        batches.append((x, make_target(ctx, wl, tht, x, i)))
     theta = torch.from_numpy(wl.theta0).cuda()
     st = B.new_lm_state(wl.lam0, 0, compat=args.compat)
     for i in range(args.warmup):
@@ -256,8 +287,8 @@ def main() -> int:
         "vjp_segments": steps * F_GRAD_PAIR * (N + 3 * M) * K,
         "vjp_elements": steps * F_BOUNDARY_PAIR * N * M,
         "features": steps * F_GRAD_PAIR * (N + 3 * M) * K,
-        "gram_mfma": steps * 2.0 * N * gram_entries(H, M),
-        "gram_f64": steps * 2.0 * N * gram_entries(H, M),
+        "gram_mfma": steps * 2.0 * N * gram_entries(H, M, wl.spec.model),
+        "gram_f64": steps * 2.0 * N * gram_entries(H, M, wl.spec.model),
     }
     peak_of = {"sweep_mixed": ("alu", PEAKS["fp32_vector"]), "sweep_f64": ("alu", PEAKS["fp64_vector"]),
                "vjp_segments": ("alu", PEAKS["fp32_vector"] if args.prec == "mixed" else PEAKS["fp64_vector"]),
@@ -270,7 +301,9 @@ def main() -> int:
     tot_ms, launches = timed[dom]
     achieved = work[dom] / (tot_ms * 1e-3) / 1e12
     bound, peak = peak_of[dom]
-    traffic = gram_traffic(GRAM_TILE) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma") else None
+    # the committed byte counters were taken on the LM workload's Gram
+    traffic = (gram_traffic(GRAM_TILE) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma" and args.workload == "lm")
+               else None)
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (peak / 1e12), "traffic": traffic, "launches": launches,
                 "avg_launch_ms": tot_ms / launches}
@@ -281,7 +314,7 @@ def main() -> int:
 
     # forward sweep against the float32 vector peak (packed FP32 counts twice; without it the
     # vector ceiling is half of that)
-    fpp = sweep_flops_per_pair() if args.prec == "mixed" else None
+    fpp = sweep_flops_per_pair() if (args.prec == "mixed" and args.workload == "lm") else None
     sweep_valu = None
     if fpp and pairs_fwd:
         tf = fpp * pairs_fwd / 1e12
@@ -294,7 +327,7 @@ def main() -> int:
     step_err = None
     if args.fp64_ref and args.prec == "mixed":
         th64 = torch.from_numpy(wl.theta0).cuda()
-        st64 = B.new_lm_state(wl.lam0, 0)
+        st64 = B.new_lm_state(wl.lam0, 0, compat=args.compat)
         torch.cuda.synchronize()
         t = time.perf_counter()
         ctx.lm_step(th64, batches[0][0], batches[0][1], st64, "fp64", "fp64")
@@ -308,7 +341,7 @@ def main() -> int:
         d64 = (th64 - torch.from_numpy(wl.theta0).cuda()).flatten()
         for gm in ["bf16x3_mfma", "fp32_mfma"]:
             thg = torch.from_numpy(wl.theta0).cuda()
-            stg = B.new_lm_state(wl.lam0, 0)
+            stg = B.new_lm_state(wl.lam0, 0, compat=args.compat)
             ctx.lm_step(thg, batches[0][0], batches[0][1], stg, gm, "mixed")
             dg = (thg - torch.from_numpy(wl.theta0).cuda()).flatten()
             step_err[gm] = (float(torch.linalg.vector_norm(dg - d64) / torch.linalg.vector_norm(d64))
@@ -324,8 +357,7 @@ def main() -> int:
         "metric": METRIC, "value": value, "unit": "LM steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.prec == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": "LM normal equations: 256 cubic handles x 32 segments (P = 5,120), "
-                               "2,097,152 uniform samples per step, sigma 0.2, eps 1e-2, 1,024 outer elements",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "handle_model": wl.spec.model,
                    "handles": H, "segs_per_handle": S, "samples": N, "params": wl.P, "outer_elements": M,
                    "prec": args.prec, "gram": args.gram, "compat": args.compat, "parallelism": "single GPU"},
         "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
