@@ -6,3 +6,4 @@ its Python binding) never calls it; it shares no code with the GPU path.
 """
 from .bem_oracle import *  # noqa: F401,F403
 from . import straight  # noqa: F401,E402
+from . import regularizers  # noqa: F401,E402

@@ -41,6 +41,7 @@ from functools import lru_cache
 import numpy as np
 
 from . import dual as du
+from . import regularizers as rg
 
 TWO_PI = 2.0 * np.pi
 FOUR_PI = 4.0 * np.pi
@@ -416,6 +417,7 @@ class LMState:
     loss_after: float = np.nan
     cbar: np.ndarray = None
     compat: bool = False        # enforce the compatibility condition (Sec. 4.3)
+    chol_retries: int = 0       # damping raises after a failed Cholesky in the last step
 
     def __post_init__(self):
         if self.cbar_sum is None:
@@ -521,8 +523,11 @@ CUBIC = HandleModel(evaluate=evaluate, normal_equations=normal_equations, compat
                     reproject=reproject)
 
 
-def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256, model: HandleModel = CUBIC):
-    """One damped Gauss-Newton step with accept/reject on the same samples.  Returns (theta', state)."""
+def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256, model: HandleModel = CUBIC,
+            reg: rg.Reg | None = None):
+    """One damped Gauss-Newton step with accept/reject on the same samples.  Returns (theta', state).
+    With regularisation terms (Sec. 4.4) their Hessian and gradient are added to the normal
+    equations and their value to the loss on both sides of the accept test."""
     evaluate, normal_equations = model.evaluate, model.normal_equations
     compat_vectors, reproject = model.compat_vectors, model.reproject
     theta = np.asarray(theta, dtype=np.float64)
@@ -538,13 +543,30 @@ def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256
     u = u0 + cbar[None, :]
     L0 = loss(u, T)
     JtJ, Jtr = normal_equations(theta, x, u - T, S, eps, per_side)
+    pairs = None
+    if reg is not None and reg.active():
+        R0, gR, HR, pairs = rg.terms(theta, reg)
+        JtJ, Jtr, L0 = JtJ + HR, Jtr + gR, L0 + R0
+    from scipy.linalg import LinAlgError
+    state.chol_retries = 0
+    while True:                     # a failed Cholesky raises the damping (at most 10 times)
+        try:
+            if state.compat:
+                delta = constrained_step(JtJ, Jtr, state.lam, compat_vectors(theta, S))
+            else:
+                delta = damped_step(JtJ, Jtr, state.lam)
+            break
+        except LinAlgError:
+            if state.chol_retries >= 10:
+                raise
+            state.lam = min(state.lam * 10.0, LAMBDA_MAX)
+            state.chol_retries += 1
+    theta_new = theta - delta.reshape(theta.shape)
     if state.compat:
-        delta = constrained_step(JtJ, Jtr, state.lam, compat_vectors(theta, S))
-        theta_new = reproject(theta - delta.reshape(theta.shape), S)
-    else:
-        delta = damped_step(JtJ, Jtr, state.lam)
-        theta_new = theta - delta.reshape(theta.shape)
+        theta_new = reproject(theta_new, S)
     L1 = loss(evaluate(theta_new, x, cbar, S, eps, per_side), T)
+    if pairs is not None:
+        L1 += rg.value(theta_new, reg, pairs)
     state.loss_before, state.loss_after = L0, L1
     if L1 < L0:
         state.accepted = True

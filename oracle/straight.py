@@ -94,5 +94,5 @@ STRAIGHT = O.HandleModel(evaluate=evaluate, normal_equations=normal_equations, c
                          reproject=reproject)
 
 
-def lm_step(theta, x, T, state: O.LMState, S: int, eps: float, per_side: int = 256):
-    return O.lm_step(theta, x, T, state, S, eps, per_side, model=STRAIGHT)
+def lm_step(theta, x, T, state: O.LMState, S: int, eps: float, per_side: int = 256, reg=None):
+    return O.lm_step(theta, x, T, state, S, eps, per_side, model=STRAIGHT, reg=reg)
