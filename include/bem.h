@@ -117,7 +117,43 @@ typedef struct {
     int32_t chol_retries;     /* out: extra damping rounds after a failed Cholesky  */
     int32_t compat;           /* in: 1 enforces the compatibility condition          */
     double compat_violation;  /* out: max_c |a_c . theta'| / sum |a_c theta'| (compat) */
+    double reg_value;         /* out: regularisation terms at theta (in loss_before)  */
+    int32_t snap_pairs;       /* out: end point pairs snapped in this step            */
 } bem_lm_state;
+
+/* Regularisation terms of the LM step (Sec. 4.4).  Each enters the step with its
+ * analytic gradient and Hessian, added to the normal equations (g and H of
+ * lm_step), and with its value added to the loss on both sides of the accept
+ * test.  A weight of 0 switches a term off; all are off until
+ * bem_set_regularization.  End points E0, E1 of a handle: straight A, B; cubic
+ * P0, P3.  Jump vectors w: straight wd, wc; cubic wd0, wd1, wc0, wc1 (RGB).
+ *   length    length_weight (l - length_max)^2 for each handle with
+ *             l = |E1 - E0| > length_max;
+ *   snapping  snap_weight |e - e'|^2 for each pair of end points e, e' of two
+ *             different handles, closer than snap_dist, each of which has the
+ *             other as its lowest snapping score
+ *               snap_mix |e - e'| / snap_dist + (1 - snap_mix)(1 - |tau . tau'|)
+ *             (tau: unit direction E1 - E0 of each handle, 0 for a zero-length
+ *             handle; ties go to the lower end point index 2h + j).  The pairs
+ *             are chosen at the step's theta and kept for its trial point;
+ *   sparsity  lambda t tanh(sqrt(w . w + eps^2) / t) per jump vector, lambda =
+ *             sparse_wd for wd and sparse_wc for wc.
+ * The length and snapping Hessians are exact (positive semi-definite); the
+ * sparsity term's curvature along w is negative (the term saturates) and is
+ * left out, so that the approximate Hessian stays positive definite for the
+ * Cholesky solve (Sec. 4.3): it contributes f'(s)/s (I - w w^T / s^2),
+ * s = sqrt(w . w + eps^2). */
+typedef struct {
+    double length_weight;     /* >= 0 */
+    double length_max;        /* >= 0 */
+    double snap_weight;       /* >= 0 */
+    double snap_dist;         /* > 0 when snap_weight > 0 */
+    double snap_mix;          /* in [0, 1] */
+    double sparse_wd;         /* >= 0 */
+    double sparse_wc;         /* >= 0 */
+    double sparse_t;          /* > 0 when a sparsity weight is > 0 */
+    double sparse_eps;        /* >= 0 */
+} bem_reg;
 
 /* Build the outer boundary (unit square, counter-clockwise, elems_per_side
  * equal elements per side, M = 4*elems_per_side) and assemble the float64
@@ -185,6 +221,9 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * Schur complement, 3 more Cholesky solves), and after the update the wc
  * parameters are projected orthogonally onto a_c . theta' = 0 with a_c at the
  * new end points; state->compat_violation reports what remains (rounding).
+ * With regularisation terms set (bem_set_regularization) their gradient and
+ * Hessian are added to g and H, and their value to L0 and L1 (snapping pairs
+ * chosen at theta); state->reg_value and state->snap_pairs report them.
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.
@@ -192,6 +231,29 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
 int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N,
             const double* target, bem_lm_state* state, bem_gram gram, bem_prec prec,
             hipStream_t stream);
+
+/* Set the regularisation terms lm_step adds (host struct, copied; NULL switches
+ * every term off).  Errors: EINVAL (null context, a negative or non-finite
+ * weight, snap_dist <= 0 or snap_mix outside [0, 1] with snapping on,
+ * sparse_t <= 0 or sparse_eps < 0 with sparsity on). */
+int bem_set_regularization(bem_ctx* ctx, const bem_reg* reg);
+
+/* The regularisation terms set on the context at theta [H,Q] (device): *value
+ * (host) = their sum, grad [P] and hess [P,P] (device, row-major, overwritten;
+ * both NULL for the value only), *pairs (host, may be NULL) = the number of
+ * snapped end point pairs.  Snapping compares every pair of end points
+ * (O(H^2)) and is limited to H <= 65536.  Synchronises the stream.
+ * Errors: ESTATE, EINVAL (one of grad / hess NULL, H out of range), ENOMEM, EHIP. */
+int bem_regularization(bem_ctx* ctx, const double* theta, int32_t H, double* value, double* grad,
+                       double* hess, int32_t* pairs, hipStream_t stream);
+
+/* Handle pruning (Sec. 4.4, with the sparsity term): removes, in place, every
+ * handle whose wd norm and wc norm (for cubic handles the larger over the two
+ * ends) are both below threshold (a NaN norm counts as below), keeping the
+ * order of the others in theta[0 : *H_out].  Rows past *H_out are unspecified.
+ * Synchronises the stream.  Errors: ESTATE, EINVAL (threshold < 0 or not
+ * finite, null H_out), ENOMEM, EHIP. */
+int bem_prune(bem_ctx* ctx, double* theta, int32_t H, double threshold, int32_t* H_out, hipStream_t stream);
 
 /* Explicit float64 Jacobian J [N,3,P] (row = sample*3 + channel), the
  * quantity the paper differentiates in Sec. 3.2.  For tests and small N.

@@ -109,7 +109,7 @@ def snap_pairs(theta, dist: float, mix: float) -> list:
     E = endpoints(theta)
     n = E.shape[0]
     chord = E[1::2] - E[0::2]
-    ln = np.hypot(chord[:, 0], chord[:, 1])
+    ln = np.sqrt(chord[:, 0] * chord[:, 0] + chord[:, 1] * chord[:, 1])
     tau = np.where(ln[:, None] > 0, chord / np.where(ln > 0, ln, 1.0)[:, None], 0.0)
     best = np.full(n, -1)
     for i in range(n):
@@ -117,7 +117,8 @@ def snap_pairs(theta, dist: float, mix: float) -> list:
         for j in range(n):
             if j // 2 == i // 2:
                 continue
-            d = float(np.sqrt((E[i, 0] - E[j, 0]) ** 2 + (E[i, 1] - E[j, 1]) ** 2))
+            dx, dy = E[i, 0] - E[j, 0], E[i, 1] - E[j, 1]
+            d = float(np.sqrt(dx * dx + dy * dy))
             if not d < dist:
                 continue
             dot = abs(tau[i // 2, 0] * tau[j // 2, 0] + tau[i // 2, 1] * tau[j // 2, 1])

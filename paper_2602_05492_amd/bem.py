@@ -42,7 +42,16 @@ class LMState(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("cbar", ctypes.c_double * 3), ("cbar_sum", ctypes.c_double * 3),
                 ("cbar_count", ctypes.c_int64), ("mean_rule", ctypes.c_int32), ("accepted", ctypes.c_int32),
                 ("loss_before", ctypes.c_double), ("loss_after", ctypes.c_double), ("chol_retries", ctypes.c_int32),
-                ("compat", ctypes.c_int32), ("compat_violation", ctypes.c_double)]
+                ("compat", ctypes.c_int32), ("compat_violation", ctypes.c_double), ("reg_value", ctypes.c_double),
+                ("snap_pairs", ctypes.c_int32)]
+
+
+class Reg(ctypes.Structure):
+    """Regularisation terms of the LM step (bem_reg); a zero weight switches a term off."""
+    _fields_ = [("length_weight", ctypes.c_double), ("length_max", ctypes.c_double),
+                ("snap_weight", ctypes.c_double), ("snap_dist", ctypes.c_double), ("snap_mix", ctypes.c_double),
+                ("sparse_wd", ctypes.c_double), ("sparse_wc", ctypes.c_double), ("sparse_t", ctypes.c_double),
+                ("sparse_eps", ctypes.c_double)]
 
 
 _lib = None
@@ -58,6 +67,9 @@ _SIGS = {
     "bem_jtj": (ctypes.c_int, [P, P, I32, P, I64, P, P, P, ctypes.c_int, ctypes.c_int, P]),
     "lm_step": (ctypes.c_int, [P, P, I32, P, I64, P, ctypes.POINTER(LMState), ctypes.c_int, ctypes.c_int, P]),
     "bem_jacobian": (ctypes.c_int, [P, P, I32, P, I64, P, P]),
+    "bem_set_regularization": (ctypes.c_int, [P, ctypes.POINTER(Reg)]),
+    "bem_regularization": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double), P, P, ctypes.POINTER(I32), P]),
+    "bem_prune": (ctypes.c_int, [P, P, I32, ctypes.c_double, ctypes.POINTER(I32), P]),
     "bem_boundary_solve": (ctypes.c_int, [P, P, I32, P, P, P]),
     "bem_get_matrix": (ctypes.c_int, [P, I32, P, P]),
     "bem_num_elements": (I32, [P]),
@@ -241,6 +253,36 @@ class Context:
         J = torch.empty((N, 3, self.Q * H), dtype=torch.float64, device=self.device)
         self._check(lib().bem_jacobian(self._h, _ptr(theta), H, _ptr(x), N, _ptr(J), _stream()))
         return J
+
+    def set_regularization(self, **terms):
+        """Set the LM step's regularisation terms (bem_reg field names); no arguments: all off."""
+        if not terms:
+            self._check(lib().bem_set_regularization(self._h, None))
+            return
+        r = Reg(**terms)
+        self._check(lib().bem_set_regularization(self._h, ctypes.byref(r)))
+
+    def regularization(self, theta, with_derivatives: bool = True):
+        """(value, grad [P] or None, hess [P, P] or None, snapped pairs) of the terms at theta."""
+        H, _ = self._theta_x(theta, None)
+        P_ = self.Q * H
+        v = ctypes.c_double()
+        n = I32()
+        g = hm = None
+        if with_derivatives:
+            g = torch.empty((P_,), dtype=torch.float64, device=self.device)
+            hm = torch.empty((P_, P_), dtype=torch.float64, device=self.device)
+        self._check(lib().bem_regularization(self._h, _ptr(theta), H, ctypes.byref(v), _ptr(g) if g is not None else None,
+                                             _ptr(hm) if hm is not None else None, ctypes.byref(n), _stream()))
+        return v.value, g, hm, n.value
+
+    def prune(self, theta, threshold: float) -> torch.Tensor:
+        """Remove, in place, the handles whose wd and wc norms are both below threshold; returns the
+        view theta[:H_kept]."""
+        H, _ = self._theta_x(theta, None)
+        k = I32()
+        self._check(lib().bem_prune(self._h, _ptr(theta), H, float(threshold), ctypes.byref(k), _stream()))
+        return theta[: k.value]
 
     def lm_step(self, theta, x, target, state: LMState, gram: str = "fp64", prec: str = "fp64") -> LMState:
         H, N = self._theta_x(theta, x)

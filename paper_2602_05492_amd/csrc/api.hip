@@ -278,6 +278,50 @@ int bem_jacobian(bem_ctx* ctx, const double* theta, int32_t H, const double* x, 
     return run_jacobian(ctx, theta, H, x, N, J, stream);
 }
 
+int bem_set_regularization(bem_ctx* ctx, const bem_reg* reg)
+{
+    if (!ctx) return BEM_EINVAL;
+    ctx->err.clear();
+    if (!reg) {
+        ctx->reg = bem_reg{};
+        return BEM_OK;
+    }
+    char why[160];
+    if (check_reg(*reg, why, sizeof(why))) return set_error(ctx, BEM_EINVAL, "%s", why);
+    ctx->reg = *reg;
+    return BEM_OK;
+}
+
+int bem_regularization(bem_ctx* ctx, const double* theta, int32_t H, double* value, double* grad, double* hess,
+                       int32_t* pairs, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, nullptr, 0);
+    if (rc) return rc;
+    if (!value) return set_error(ctx, BEM_EINVAL, "value is null");
+    if ((grad == nullptr) != (hess == nullptr)) return set_error(ctx, BEM_EINVAL, "give both grad and hess or neither");
+    const int64_t P = (int64_t)ctx->npar * H;
+    if (grad && P > 0) {
+        if ((rc = fill_f64(ctx, grad, P, 0.0, stream))) return rc;
+        if ((rc = fill_f64(ctx, hess, P * P, 0.0, stream))) return rc;
+    }
+    int np = 0;
+    if ((rc = reg_terms(ctx, theta, H, true, grad, hess, value, &np, stream))) return rc;
+    if (pairs) *pairs = np;
+    return BEM_OK;
+}
+
+int bem_prune(bem_ctx* ctx, double* theta, int32_t H, double threshold, int32_t* H_out, hipStream_t stream)
+{
+    int rc = check_common(ctx, theta, H, nullptr, 0);
+    if (rc) return rc;
+    if (!H_out) return set_error(ctx, BEM_EINVAL, "H_out is null");
+    if (!(threshold >= 0.0) || !std::isfinite(threshold)) return set_error(ctx, BEM_EINVAL, "threshold must be >= 0");
+    int kept = 0;
+    if ((rc = run_prune(ctx, theta, H, threshold, &kept, stream))) return rc;
+    *H_out = kept;
+    return BEM_OK;
+}
+
 int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U, hipStream_t stream)
 {
     int rc = check_common(ctx, theta, H, nullptr, 0);
@@ -351,7 +395,7 @@ void bem_destroy(bem_ctx* ctx)
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
-                      &ctx->nearw, &ctx->nearv, &ctx->nearf};
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw};
     for (DevBuf* b : bufs) release(*b);
     prof_resolve(ctx);
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);

@@ -82,13 +82,14 @@ struct bem_ctx {
     // handle parametrisation: parameters per handle, and per handle in a feature row of the
     // normal equations the geometry columns of one channel and the channel-shared colour columns
     int model = 0, npar = 20, ngeo = 8, ncol = 4;
+    bem_reg reg{};           // regularisation terms of lm_step (all off by default)
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw;
 };
 
 namespace bem {
@@ -129,6 +130,12 @@ struct NearList;
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s,
                        NearList* out = nullptr);
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
+// reg.hip
+bool reg_active(const bem_ctx* ctx);
+int check_reg(const bem_reg& r, char* why, size_t n);
+int reg_terms(bem_ctx* ctx, const double* theta, int H, bool choose, double* g, double* Hm, double* value, int* pairs,
+              hipStream_t s);
+int run_prune(bem_ctx* ctx, double* theta, int H, double thr, int* H_out, hipStream_t s);
 // vjp.hip
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
             double* grad, hipStream_t s, const NearList* pre = nullptr);

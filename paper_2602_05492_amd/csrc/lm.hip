@@ -276,6 +276,8 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     double* cX = cA + 3 * (size_t)P;          // [P][4]: gradient and the three a_c, solved in place
     double* cviol = cX + 4 * (size_t)P;
     st->compat_violation = 0.0;
+    st->reg_value = 0.0;
+    st->snap_pairs = 0;
     const bem_prec prec = mixed ? BEM_PREC_MIXED : BEM_PREC_FP64;
     st->accepted = 0;
     st->chol_retries = 0;
@@ -312,6 +314,18 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / (double)N);
     // the step's right-hand side is the adjoint gradient above, so J^T r is not formed
     if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr))) return rc;
+    // regularisation terms (Sec. 4.4): gradient and Hessian into g and J^T J, value into the loss;
+    // the snapping pairs chosen here are kept for the trial point
+    const bool reg = reg_active(ctx);
+    double R0 = 0.0;
+    if (reg) {
+        int np = 0;
+        if ((rc = reg_terms(ctx, theta, H, true, g, JtJ, &R0, &np, s))) return rc;
+        st->reg_value = R0;
+        st->snap_pairs = np;
+        st->loss_before = L0 + R0;
+        st->loss_after = L0 + R0;
+    }
     // damped Cholesky, raising lambda until it factors
     double lam = st->lambda;
     for (int attempt = 0;; ++attempt) {
@@ -365,9 +379,14 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     int hflag = 0;
     if (hipMemcpy(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "flag readback");
-    const double L1 = 0.5 * sums[0] / (double)N;
+    double L1 = 0.5 * sums[0] / (double)N;
+    if (reg) {
+        double R1 = 0.0;
+        if ((rc = reg_terms(ctx, th1, H, false, nullptr, nullptr, &R1, nullptr, s))) return rc;
+        L1 += R1;
+    }
     st->loss_after = L1;
-    if (!hflag && std::isfinite(L1) && L1 < L0) {
+    if (!hflag && std::isfinite(L1) && L1 < st->loss_before) {
         if (hipMemcpyAsync(theta, th1, P * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return set_error(ctx, BEM_EHIP, "accept copy");
