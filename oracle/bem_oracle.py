@@ -263,12 +263,39 @@ class Boundary:
         return len(self.ea)
 
 
-@lru_cache(maxsize=8)
-def boundary(per_side: int = 256) -> Boundary:
-    ea, eb = square_boundary(per_side)
+def boundary_from_elements(ea: np.ndarray, eb: np.ndarray) -> Boundary:
+    """Galerkin system and truncated pseudo-inverse of any set of straight elements a -> b
+    (closed or open, possibly self-intersecting: the subdomain boundaries of Sec. 4.1)."""
+    ea = np.ascontiguousarray(ea, dtype=np.float64)
+    eb = np.ascontiguousarray(eb, dtype=np.float64)
     gp, gw = gauss_points(ea, eb)
     A = assemble_matrix(ea, eb)
     return Boundary(ea, eb, gp, gw, A, truncated_pinv(A))
+
+
+@lru_cache(maxsize=8)
+def boundary(per_side: int = 256) -> Boundary:
+    return boundary_from_elements(*square_boundary(per_side))
+
+
+def polygon_elements(verts, per_edge: int, closed: bool = True):
+    """Elements of a polyline through verts [n, 2] (closed: back to the first vertex), each
+    edge cut into per_edge equal elements, in vertex order."""
+    v = np.asarray(verts, dtype=np.float64)
+    if closed:
+        v = np.concatenate([v, v[:1]])
+    t = np.arange(per_edge + 1) / per_edge
+    ea, eb = [], []
+    for k in range(len(v) - 1):
+        p = v[k][None, :] + t[:, None] * (v[k + 1] - v[k])[None, :]
+        ea.append(p[:-1])
+        eb.append(p[1:])
+    return np.concatenate(ea), np.concatenate(eb)
+
+
+def as_boundary(b) -> Boundary:
+    """A Boundary, or the unit square with b elements per side."""
+    return b if isinstance(b, Boundary) else boundary(b)
 
 
 def element_weights(x: np.ndarray, bnd: Boundary) -> np.ndarray:
@@ -292,7 +319,7 @@ def boundary_values(theta: np.ndarray, S: int, eps: float, bnd: Boundary) -> np.
 
 def evaluate(theta, x, cbar, S: int, eps: float, per_side: int = 256) -> np.ndarray:
     """u(x) = cbar + sum_j beta_j(x) U_j + f(x) (Eq. bie, alpha = 1, plus the domain mean colour)."""
-    bnd = boundary(per_side)
+    bnd = as_boundary(per_side)
     U = boundary_values(theta, S, eps, bnd)
     x = np.asarray(x, dtype=np.float64)
     return np.asarray(cbar, dtype=np.float64)[None, :] + element_weights(x, bnd) @ U + handle_term(x, theta, S, eps)
@@ -364,7 +391,7 @@ def boundary_derivative_values(theta, S, eps, bnd: Boundary) -> np.ndarray:
 
 def jacobian(theta, x, S: int, eps: float, per_side: int = 256) -> np.ndarray:
     """du_c/dtheta at x = df_c/dtheta + sum_j beta_j(x) Z_{j,c}, [n, 3, P]."""
-    bnd = boundary(per_side)
+    bnd = as_boundary(per_side)
     Z = boundary_derivative_values(theta, S, eps, bnd)
     x = np.asarray(x, dtype=np.float64)
     return handle_term_jacobian(x, theta, S, eps) + np.einsum("nj,jcp->ncp", element_weights(x, bnd), Z)
@@ -372,7 +399,7 @@ def jacobian(theta, x, S: int, eps: float, per_side: int = 256) -> np.ndarray:
 
 def vjp(theta, x, gbar, S: int, eps: float, per_side: int = 256, chunk: int = 2048) -> np.ndarray:
     """sum_x sum_c gbar_c(x) du_c/dtheta(x), [H, 20]."""
-    bnd = boundary(per_side)
+    bnd = as_boundary(per_side)
     Z = boundary_derivative_values(theta, S, eps, bnd)
     x = np.asarray(x, dtype=np.float64)
     g = np.zeros(theta.size)
@@ -387,7 +414,7 @@ def vjp(theta, x, gbar, S: int, eps: float, per_side: int = 256, chunk: int = 20
 
 def normal_equations(theta, x, resid, S: int, eps: float, per_side: int = 256, chunk: int = 2048):
     """(1/N) sum_x J^T J and (1/N) sum_x J^T r with uniform density p = 1 (Eq. losshessian, Eq. lossjacobian)."""
-    bnd = boundary(per_side)
+    bnd = as_boundary(per_side)
     Z = boundary_derivative_values(theta, S, eps, bnd)
     x = np.asarray(x, dtype=np.float64)
     N = len(x)

@@ -1,0 +1,118 @@
+"""Pins of the oracle on subdomain boundaries other than the unit square (Sec. 4.1: each
+subdomain has its own outer boundary, possibly non-convex, open or self-intersecting, and its
+own factored system), checked against properties that do not use the oracle's own formulas:
+
+* the square built from its four corners equals the square of the default boundary;
+* double-layer identity on a non-convex (L-shaped) polygon: the element weights sum to 1
+  inside and to 0 outside;
+* the Galerkin matrix of a closed polygon annihilates constants up to quadrature error;
+* the zero-Neumann condition of the solved field at the L-shape's edges, shrinking under
+  refinement;
+* invariance of the whole evaluation (and its Jacobian) under a rigid motion of boundary,
+  handles and samples;
+* an open boundary has no constant null space and its truncated solve drops exactly the
+  smallest singular value.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2602_05492_amd import workload as W
+
+L_SHAPE = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 0.5], [0.5, 0.5], [0.5, 1.0], [0.0, 1.0]])
+
+
+def _inside_L(x):
+    return (x[:, 0] > 0) & (x[:, 1] > 0) & (x[:, 0] < 1) & (x[:, 1] < 1) & ~((x[:, 0] > 0.5) & (x[:, 1] > 0.5))
+
+
+def test_square_from_corners_is_the_default_square():
+    ea, eb = O.polygon_elements([[0, 0], [1, 0], [1, 1], [0, 1]], 16)
+    sa, sb = O.square_boundary(16)
+    assert np.array_equal(ea, sa) and np.array_equal(eb, sb)
+    b = O.boundary_from_elements(ea, eb)
+    assert np.array_equal(b.A, O.boundary(16).A)
+
+
+def test_double_layer_identity_on_L_shape():
+    bnd = O.boundary_from_elements(*O.polygon_elements(L_SHAPE, 8))
+    x = W.random_points(31, 400, -0.2, 1.2)
+    w = O.element_weights(x, bnd).sum(1)
+    inside = _inside_L(x)
+    assert np.allclose(w[inside], 1.0, atol=1e-12)
+    assert np.allclose(w[~inside], 0.0, atol=1e-12)
+
+
+def test_matrix_annihilates_constants_on_L_shape():
+    for n in (8, 32):
+        b = O.boundary_from_elements(*O.polygon_elements(L_SHAPE, n))
+        r = b.A @ np.ones(b.M)
+        lens = np.hypot(*(b.eb - b.ea).T)
+        # row i of A 1 is |G_i| (1/2 + double layer of unit density) = 0 up to quadrature error,
+        # which is largest next to the corners
+        assert np.abs(r).max() < 0.02 * lens.max()
+        assert np.median(np.abs(r) / lens) < 1e-3
+
+
+def _L_handles():
+    th = W.random_handles(32, 3, spread=0.08, centre_lo=0.2, centre_hi=0.35)
+    return th
+
+
+def test_neumann_condition_on_L_shape():
+    """du/dn at the L-shape's re-entrant edges, by one-sided differences one and two element
+    lengths inside (away from the corners), shrinks as the boundary is refined."""
+    th = _L_handles()
+    S, eps = 8, 1e-2
+    errs = []
+    for n in (8, 16, 32):
+        bnd = O.boundary_from_elements(*O.polygon_elements(L_SHAPE, n))
+        h = 0.5 / n
+        s = np.linspace(0.65, 0.85, 5)
+        p = np.concatenate([np.stack([np.full_like(s, 0.5), s], 1), np.stack([s, np.full_like(s, 0.5)], 1)])
+        nrm = np.concatenate([np.tile([1.0, 0.0], (5, 1)), np.tile([0.0, 1.0], (5, 1))])     # outward
+        u1 = O.evaluate(th, p - h * nrm, np.zeros(3), S, eps, bnd)
+        u2 = O.evaluate(th, p - 2 * h * nrm, np.zeros(3), S, eps, bnd)
+        errs.append(np.abs((u1 - u2) / h).max())
+    assert errs[2] < errs[1] < errs[0], errs
+
+
+def _rotate(p, c, s, t):
+    return np.stack([c * p[..., 0] - s * p[..., 1], s * p[..., 0] + c * p[..., 1]], -1) + t
+
+
+def test_rigid_motion_invariance():
+    th = _L_handles()
+    S, eps = 4, 1e-2
+    ea, eb = O.polygon_elements(L_SHAPE, 6)
+    x = W.random_points(33, 50, 0.05, 0.45)
+    ang, t = 0.7, np.array([0.3, -0.2])
+    c, s = np.cos(ang), np.sin(ang)
+    th2 = th.copy()
+    th2[:, :8] = _rotate(th[:, :8].reshape(-1, 4, 2), c, s, t).reshape(-1, 8)
+    b1 = O.boundary_from_elements(ea, eb)
+    b2 = O.boundary_from_elements(_rotate(ea, c, s, t), _rotate(eb, c, s, t))
+    u1 = O.evaluate(th, x, np.zeros(3), S, eps, b1)
+    u2 = O.evaluate(th2, _rotate(x, c, s, t), np.zeros(3), S, eps, b2)
+    assert np.allclose(u1, u2, atol=1e-11)
+    # colour columns of the Jacobian do not rotate
+    J1 = O.jacobian(th, x[:5], S, eps, b1)
+    J2 = O.jacobian(th2, _rotate(x[:5], c, s, t), S, eps, b2)
+    cols = [20 * h + q for h in range(3) for q in range(8, 20)]
+    assert np.allclose(J1[:, :, cols], J2[:, :, cols], atol=1e-10)
+
+
+def test_open_boundary_is_solvable():
+    """An open boundary has no constant null space: its smallest singular value is not small,
+    and the truncated solve drops exactly that one (|A - A A+ A|_2 = sigma_min); the closed
+    L-shape's smallest singular value is at quadrature-error level."""
+    ea, eb = O.polygon_elements(L_SHAPE[:5], 8, closed=False)
+    b = O.boundary_from_elements(ea, eb)
+    assert b.M == 32
+    s = np.linalg.svd(b.A, compute_uv=False)
+    assert s[-1] > 1e-3 * s[0]
+    assert np.linalg.norm(b.A - b.A @ b.Apinv @ b.A, 2) == pytest.approx(s[-1], rel=1e-8)
+    sc = np.linalg.svd(O.boundary_from_elements(*O.polygon_elements(L_SHAPE, 8)).A, compute_uv=False)
+    assert sc[-1] < 1e-2 * s[-1]
+    u = O.evaluate(_L_handles(), W.random_points(34, 20, 0.05, 0.45), np.zeros(3), 4, 1e-2, b)
+    assert np.isfinite(u).all()
