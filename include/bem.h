@@ -33,7 +33,8 @@
  *    outward there.
  *  - The handle kernels are regularised r^2 -> r^2 + eps^2 (Sec. 3.1.3); the
  *    outer-boundary kernels are exact.
- *  - Samples x are [N,2] float64 strictly inside the open unit square.
+ *  - Samples x are [N,2] float64 strictly inside the subdomain: the open unit
+ *    square for bem_build, the region the elements bound for bem_build_elements.
  *  - All array pointers are DEVICE pointers owned by the caller unless marked
  *    (host).  The library owns only the context and its internal workspaces,
  *    which it grows with hipMalloc on first use of a size and frees in
@@ -165,6 +166,20 @@ typedef struct {
  * handle_model), ENOMEM, EHIP. */
 int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out);
 
+/* The same for an outer boundary made of any M straight elements (Sec. 4.1: each
+ * subdomain has its own boundary, which may be non-convex, open or
+ * self-intersecting).  elems (host, copied) is [M,4] float64 row-major, element i
+ * running from (elems[4i], elems[4i+1]) to (elems[4i+2], elems[4i+3]); a closed
+ * boundary runs counter-clockwise, so that the right normal points out of the
+ * subdomain.  The Galerkin matrix, its truncated-SVD solve (which drops the
+ * smallest singular value whether or not the boundary is closed) and every later
+ * call are those of bem_build with these elements; opts.elems_per_side is
+ * ignored.  Elements must not overlap one another.  Samples of the later calls
+ * are the subdomain's.  Errors: as bem_build, EINVAL (null elems, M not in
+ * [2, 4096], a zero-length or non-finite element). */
+int bem_build_elements(const bem_opts* opts, const double* elems, int32_t M, hipStream_t stream,
+                       bem_ctx** out);
+
 /* One-time float64 factorisation (Sec. 3.1.3, factor once and reuse, Sec. 4.2):
  * the smallest singular triplet (sigma_n, u_n, v_n) of A by inverse iteration
  * with a pivoted LU of A, the deflated matrix B = A + (s - sigma_n) u_n v_n^T
@@ -255,6 +270,19 @@ int bem_regularization(bem_ctx* ctx, const double* theta, int32_t H, double* val
  * finite, null H_out), ENOMEM, EHIP. */
 int bem_prune(bem_ctx* ctx, double* theta, int32_t H, double threshold, int32_t* H_out, hipStream_t stream);
 
+/* Samples grouped by subdomain (Sec. 4.1: each sample belongs to the subdomain its
+ * camera ray hits first; Sec. 4.3: each subdomain's normal equations use its own
+ * samples and are solved separately): a stable partition of x [N,2] and T [N,3]
+ * (float64, device; T may be NULL) by labels [N] (int32, device) into x_out and
+ * T_out (device, [N,2] / [N,3] rows reserved), so that the samples with label d
+ * occupy rows offsets[d] .. offsets[d+1]-1 in their original order; labels
+ * outside [0, D) are dropped (offsets[D] = rows kept).  offsets is host [D+1].
+ * The workspace is ctx's (any context of the device).  Synchronises the stream.
+ * Errors: EINVAL (null pointers, D not in [1, 1024], N < 0), ENOMEM, EHIP. */
+int bem_partition_samples(bem_ctx* ctx, const int32_t* labels, int64_t N, int32_t D, const double* x,
+                          const double* T, double* x_out, double* T_out, int64_t* offsets,
+                          hipStream_t stream);
+
 /* Explicit float64 Jacobian J [N,3,P] (row = sample*3 + channel), the
  * quantity the paper differentiates in Sec. 3.2.  For tests and small N.
  * Errors: as bem_eval. */
@@ -294,7 +322,7 @@ const char* bem_profile_name(int32_t tag);
 void bem_destroy(bem_ctx* ctx);
 
 /* Description of the last non-OK status of this context (NULL: of the last
- * failed bem_build on this thread).  Valid until the next call on the context. */
+ * failed bem_build or bem_build_elements on this thread).  Valid until the next call on the context. */
 const char* bem_last_error(const bem_ctx* ctx);
 
 #ifdef __cplusplus

@@ -61,6 +61,7 @@ I64 = ctypes.c_int64
 
 _SIGS = {
     "bem_build": (ctypes.c_int, [ctypes.POINTER(Opts), P, ctypes.POINTER(P)]),
+    "bem_build_elements": (ctypes.c_int, [ctypes.POINTER(Opts), P, I32, P, ctypes.POINTER(P)]),
     "bem_factor": (ctypes.c_int, [P, P]),
     "bem_eval": (ctypes.c_int, [P, P, I32, P, I64, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int, P]),
     "bem_vjp": (ctypes.c_int, [P, P, I32, P, I64, P, P, ctypes.c_int, P]),
@@ -70,6 +71,7 @@ _SIGS = {
     "bem_set_regularization": (ctypes.c_int, [P, ctypes.POINTER(Reg)]),
     "bem_regularization": (ctypes.c_int, [P, P, I32, ctypes.POINTER(ctypes.c_double), P, P, ctypes.POINTER(I32), P]),
     "bem_prune": (ctypes.c_int, [P, P, I32, ctypes.c_double, ctypes.POINTER(I32), P]),
+    "bem_partition_samples": (ctypes.c_int, [P, P, I64, I32, P, P, P, P, ctypes.POINTER(I64), P]),
     "bem_boundary_solve": (ctypes.c_int, [P, P, I32, P, P, P]),
     "bem_get_matrix": (ctypes.c_int, [P, I32, P, P]),
     "bem_num_elements": (I32, [P]),
@@ -135,9 +137,11 @@ class Options:
 
 
 class Context:
-    """A built and factored outer-boundary system plus the library's workspaces."""
+    """A built and factored outer-boundary system plus the library's workspaces.  With
+    elements ([M, 4] float64 array-like of element end points a, b) the outer boundary is
+    that set of straight elements (a subdomain's boundary) instead of the unit square."""
 
-    def __init__(self, opts: Options | None = None, **kw):
+    def __init__(self, opts: Options | None = None, elements=None, **kw):
         self.opts = opts or Options(**kw)
         L = lib()
         if self.opts.handle_model not in HANDLE_MODELS:
@@ -148,7 +152,15 @@ class Context:
         h = ctypes.c_void_p()
         with torch.cuda.device(self.opts.device):
             st = _stream()
-            rc = L.bem_build(ctypes.byref(o), st, ctypes.byref(h))
+            if elements is None:
+                rc = L.bem_build(ctypes.byref(o), st, ctypes.byref(h))
+            else:
+                import numpy as np
+                el = np.ascontiguousarray(elements, dtype=np.float64)
+                if el.ndim != 2 or el.shape[1] != 4:
+                    raise ValueError("elements must be [M, 4]")
+                rc = L.bem_build_elements(ctypes.byref(o), ctypes.c_void_p(el.ctypes.data), el.shape[0], st,
+                                          ctypes.byref(h))
             if rc != 0:
                 raise BemError(rc, L.bem_last_error(None).decode())
             self._h = h
@@ -284,12 +296,39 @@ class Context:
         self._check(lib().bem_prune(self._h, _ptr(theta), H, float(threshold), ctypes.byref(k), _stream()))
         return theta[: k.value]
 
+    def partition(self, labels, x, target=None, D: int = 1):
+        """Stable partition of the samples (and targets) by subdomain label in [0, D) on the GPU:
+        (x sorted, target sorted or None, offsets list of D + 1 row indices)."""
+        _check_dev("labels", labels, torch.int32)
+        _check_dev("x", x, torch.float64)
+        N = x.shape[0]
+        if labels.shape != (N,) or x.shape != (N, 2):
+            raise ValueError("labels must be [N] and x [N, 2]")
+        if target is not None:
+            _check_dev("target", target, torch.float64, (N, 3))
+        xo = torch.empty_like(x)
+        To = torch.empty_like(target) if target is not None else None
+        off = (I64 * (D + 1))()
+        self._check(lib().bem_partition_samples(self._h, _ptr(labels), N, D, _ptr(x), _ptr(target), _ptr(xo),
+                                                _ptr(To), off, _stream()))
+        return xo, To, [int(v) for v in off]
+
     def lm_step(self, theta, x, target, state: LMState, gram: str = "fp64", prec: str = "fp64") -> LMState:
         H, N = self._theta_x(theta, x)
         _check_dev("target", target, torch.float64, (N, 3))
         self._check(lib().lm_step(self._h, _ptr(theta), H, _ptr(x), N, _ptr(target), ctypes.byref(state),
                                   GRAM[gram], PREC[prec], _stream()))
         return state
+
+
+def lm_step_subdomains(contexts, thetas, x, target, labels, states, gram: str = "fp64", prec: str = "fp64"):
+    """One LM step in every subdomain (Sec. 4.1, Sec. 4.3): the samples are grouped by label on
+    the GPU, then subdomain d takes its own step (its own handles, mean colour, normal equations,
+    Cholesky and damping) on its own samples.  contexts, thetas and states are per subdomain."""
+    xs, Ts, off = contexts[0].partition(labels, x, target, len(contexts))
+    for d, (ctx, th, st) in enumerate(zip(contexts, thetas, states)):
+        ctx.lm_step(th, xs[off[d]:off[d + 1]], Ts[off[d]:off[d + 1]], st, gram, prec)
+    return states
 
 
 def new_lm_state(lam: float = 1e-3, mean_rule: int = 0, compat: int = 0) -> LMState:

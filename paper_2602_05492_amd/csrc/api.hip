@@ -154,13 +154,15 @@ using namespace bem;
 
 extern "C" {
 
-int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
+// Shared part of bem_build / bem_build_elements: validate the options, create the context and
+// its element table (elems: host [M][4], or null for the unit square), assemble A.
+static int build_context(const bem_opts* opts, const double* elems, int M, hipStream_t stream, bem_ctx** out)
 {
     g_build_error.clear();
     if (!opts || !out) return set_error(nullptr, BEM_EINVAL, "null opts or out");
     *out = nullptr;
     const bem_opts& o = *opts;
-    if (o.elems_per_side < 2 || o.elems_per_side > 1024)
+    if (!elems && (o.elems_per_side < 2 || o.elems_per_side > 1024))
         return set_error(nullptr, BEM_EINVAL, "elems_per_side = %d not in [2, 1024]", o.elems_per_side);
     if (o.segs_per_handle < 1 || o.segs_per_handle > 1024)
         return set_error(nullptr, BEM_EINVAL, "segs_per_handle = %d not in [1, 1024]", o.segs_per_handle);
@@ -170,6 +172,16 @@ int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
     if (o.tile_rows < 0) return set_error(nullptr, BEM_EINVAL, "tile_rows must be >= 0");
     if (o.handle_model != BEM_HANDLE_CUBIC && o.handle_model != BEM_HANDLE_STRAIGHT)
         return set_error(nullptr, BEM_EINVAL, "handle_model = %d is neither cubic (0) nor straight (1)", o.handle_model);
+    if (elems) {
+        if (M < 2 || M > 4096) return set_error(nullptr, BEM_EINVAL, "M = %d elements not in [2, 4096]", M);
+        for (int i = 0; i < M; ++i) {
+            const double* e = elems + 4 * (size_t)i;
+            const double dx = e[2] - e[0], dy = e[3] - e[1];
+            if (!std::isfinite(e[0]) || !std::isfinite(e[1]) || !std::isfinite(e[2]) || !std::isfinite(e[3]) ||
+                !(dx * dx + dy * dy > 0.0))
+                return set_error(nullptr, BEM_EINVAL, "element %d is degenerate or not finite", i);
+        }
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         hipGetLastError();
@@ -181,14 +193,25 @@ int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
     if (!ctx) return set_error(nullptr, BEM_ENOMEM, "context allocation");
     ctx->opts = o;
     ctx->device = o.device;
-    ctx->per_side = o.elems_per_side;
-    ctx->M = 4 * o.elems_per_side;
+    ctx->per_side = elems ? 0 : o.elems_per_side;
+    ctx->M = elems ? M : 4 * o.elems_per_side;
     ctx->model = o.handle_model;
     const bool straight = o.handle_model == BEM_HANDLE_STRAIGHT;
     ctx->npar = straight ? 10 : 20;
     ctx->ngeo = straight ? 4 : 8;
     ctx->ncol = straight ? 2 : 4;
-    int rc = ensure(ctx, ctx->A, (size_t)ctx->M * ctx->M * sizeof(double), stream);
+    const size_t ebytes = (size_t)ctx->M * 4 * sizeof(double);
+    int rc = ensure(ctx, ctx->egeo, ebytes, stream);
+    if (!rc) {
+        if (elems) {
+            if (hipMemcpyAsync(ctx->egeo.ptr, elems, ebytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                rc = set_error(ctx, BEM_EHIP, "element upload");
+        } else {
+            rc = launch_square_elements(ctx, stream);
+        }
+    }
+    if (!rc) rc = ensure(ctx, ctx->A, (size_t)ctx->M * ctx->M * sizeof(double), stream);
     if (!rc) rc = launch_assemble(ctx, stream);
     if (rc) {
         g_build_error = ctx->err;
@@ -198,6 +221,20 @@ int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
     ctx->state = 1;
     *out = ctx;
     return BEM_OK;
+}
+
+int bem_build(const bem_opts* opts, hipStream_t stream, bem_ctx** out)
+{
+    return build_context(opts, nullptr, 0, stream, out);
+}
+
+int bem_build_elements(const bem_opts* opts, const double* elems, int32_t M, hipStream_t stream, bem_ctx** out)
+{
+    if (!elems) {
+        g_build_error = "elems is null";
+        return BEM_EINVAL;
+    }
+    return build_context(opts, elems, M, stream, out);
 }
 
 int bem_factor(bem_ctx* ctx, hipStream_t stream)
@@ -322,6 +359,19 @@ int bem_prune(bem_ctx* ctx, double* theta, int32_t H, double threshold, int32_t*
     return BEM_OK;
 }
 
+int bem_partition_samples(bem_ctx* ctx, const int32_t* labels, int64_t N, int32_t D, const double* x, const double* T,
+                          double* x_out, double* T_out, int64_t* offsets, hipStream_t stream)
+{
+    if (!ctx) return BEM_EINVAL;
+    ctx->err.clear();
+    if (!offsets) return set_error(ctx, BEM_EINVAL, "offsets is null");
+    if (N < 0 || N > ((int64_t)1 << 31)) return set_error(ctx, BEM_EINVAL, "N = %lld out of range", (long long)N);
+    if (N > 0 && (!labels || !x || !x_out || (T && !T_out)))
+        return set_error(ctx, BEM_EINVAL, "null labels, x, x_out or T_out");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_error(ctx, BEM_EHIP, "hipSetDevice(%d)", ctx->device);
+    return run_partition(ctx, labels, N, D, x, T, x_out, T_out, offsets, stream);
+}
+
 int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, double* U, hipStream_t stream)
 {
     int rc = check_common(ctx, theta, H, nullptr, 0);
@@ -395,7 +445,7 @@ void bem_destroy(bem_ctx* ctx)
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
-                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw};
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo};
     for (DevBuf* b : bufs) release(*b);
     prof_resolve(ctx);
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);

@@ -87,7 +87,7 @@ struct bem_ctx {
     std::string err;
     bem::ProfState prof;
     // one-time boundary system
-    bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal;
+    bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal, egeo;   // egeo: outer elements [M][4] (a, b)
     // per-call workspaces
     bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw;
 };
@@ -114,6 +114,7 @@ inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) /
 
 // ---- kernels' host launchers (defined in the .hip files) ----------------------
 // factor.hip
+int launch_square_elements(bem_ctx* ctx, hipStream_t s);
 int launch_assemble(bem_ctx* ctx, hipStream_t s);
 int launch_factor(bem_ctx* ctx, hipStream_t s);
 // forward.hip
@@ -130,6 +131,9 @@ struct NearList;
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s,
                        NearList* out = nullptr);
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
+// partition.hip
+int run_partition(bem_ctx* ctx, const int32_t* labels, int64_t N, int D, const double* x, const double* T, double* xo,
+                  double* To, int64_t* off_host, hipStream_t s);
 // reg.hip
 bool reg_active(const bem_ctx* ctx);
 int check_reg(const bem_reg& r, char* why, size_t n);

@@ -13,15 +13,23 @@ constexpr double kGaussNode = 0.77459666924148337703585307995647992;   // sqrt(3
 constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
 
 
+// Element table of the counter-clockwise unit square with m elements per side.
+__global__ void k_square_elements(int M, int m, double* __restrict__ eg)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    square_element(i, m, eg[4 * i], eg[4 * i + 1], eg[4 * i + 2], eg[4 * i + 3]);
+}
+
 // A_ij = delta_ij |G_i|/2 + sum_{q,q'} w_q w_q' dG/dn_y(x_iq, y_jq'), the coincident term zero.
-__global__ void k_assemble(double* __restrict__ A, int M, int m)
+__global__ void k_assemble(double* __restrict__ A, int M, const double* __restrict__ eg)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= M) return;
     double ax, ay, bx, by, cx, cy, dx, dy;
-    square_element(i, m, ax, ay, bx, by);
-    square_element(j, m, cx, cy, dx, dy);
+    load_element(eg, i, ax, ay, bx, by);
+    load_element(eg, j, cx, cy, dx, dy);
     const double li = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
     const double lj = sqrt((dx - cx) * (dx - cx) + (dy - cy) * (dy - cy));
     double val = 0.0;
@@ -152,7 +160,10 @@ __device__ double block_sum(double v, double* red)
 }
 
 // Smallest singular triplet by inverse iteration on A^T A with the LU of A:
-// u <- A^{-T} v / |.|, x = A^{-1} u, sigma = 1/|x|, v = sigma x  (so A v = sigma u).
+// u <- A^{-T} v / |.|, x = A^{-1} u, sigma = 1/|x|, v = sigma x  (so A v = sigma u),
+// until v changes by less than 1e-14 (at most iters rounds).  Each round shrinks the error
+// by (sigma_n / sigma_{n-1})^2: a closed boundary's constant null space converges in a few
+// rounds, an open boundary's smallest singular value, less separated, in tens.
 __global__ void k_smallest_triplet(const double* __restrict__ LU, const double* __restrict__ LUt,
                                    const int* __restrict__ piv, int n, int iters,
                                    double* __restrict__ u_out, double* __restrict__ v_out, double* __restrict__ sig)
@@ -177,8 +188,14 @@ __global__ void k_smallest_triplet(const double* __restrict__ LU, const double* 
         for (int i = t; i < n; i += nt) s += x[i] * x[i];
         const double nx = sqrt(block_sum(s, red));
         sigma = 1.0 / nx;
-        for (int i = t; i < n; i += nt) { x[i] *= sigma; v_out[i] = x[i]; }
-        __syncthreads();
+        double d = 0.0;
+        for (int i = t; i < n; i += nt) {
+            x[i] *= sigma;
+            if (it > 0) d += (x[i] - v_out[i]) * (x[i] - v_out[i]);
+            v_out[i] = x[i];
+        }
+        const double change = sqrt(block_sum(d, red));
+        if (it > 0 && change < 1e-14) break;
     }
     if (t == 0) sig[0] = sigma;
 }
@@ -249,11 +266,18 @@ __global__ void k_set_shift(double* scal, int n)
 
 }  // namespace
 
+int launch_square_elements(bem_ctx* ctx, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_square_elements, dim3(blocks_for(ctx->M, 256)), dim3(256), 0, s, ctx->M, ctx->per_side,
+                       (double*)ctx->egeo.ptr);
+    return check_launch(ctx, "square elements");
+}
+
 int launch_assemble(bem_ctx* ctx, hipStream_t s)
 {
     const int M = ctx->M;
     dim3 grid(blocks_for(M, 256), M);
-    hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, (double*)ctx->A.ptr, M, ctx->per_side);
+    hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, (double*)ctx->A.ptr, M, (const double*)ctx->egeo.ptr);
     return check_launch(ctx, "assemble");
 }
 
@@ -296,7 +320,7 @@ int launch_factor(bem_ctx* ctx, hipStream_t s)
     double* LUt = X;      // the pseudo-inverse buffer holds the transposed factors until the end
     dim3 tgrid(blocks_for(n, 32), blocks_for(n, 32));
     hipLaunchKernelGGL(k_transpose, tgrid, dim3(32, 8), 0, s, LU, LUt, n);
-    hipLaunchKernelGGL(k_smallest_triplet, dim3(1), dim3(nt), shm, s, LU, LUt, piv, n, 4, u, v, scal + 2);
+    hipLaunchKernelGGL(k_smallest_triplet, dim3(1), dim3(nt), shm, s, LU, LUt, piv, n, 1000, u, v, scal + 2);
     hipLaunchKernelGGL(k_frobenius, dim3(1), dim3(1024), 0, s, A, (int64_t)nn, scal);
     hipLaunchKernelGGL(k_set_shift, dim3(1), dim3(1), 0, s, scal, n);
     dim3 grid(blocks_for(n, 256), n);

@@ -85,12 +85,13 @@ __device__ inline double block_reduce(double v, double* red)
 
 
 // F[i, c] = sum_q w_q |G_i|/2 f_c(x_iq): one block per element, threads over segments.
-__global__ void k_boundary_rhs(const double* __restrict__ seg, int K, int m, double eps2, double* __restrict__ F)
+__global__ void k_boundary_rhs(const double* __restrict__ seg, int K, const double* __restrict__ eg, double eps2,
+                               double* __restrict__ F)
 {
     __shared__ double red[256];
     const int i = blockIdx.x;
     double ax, ay, bx, by;
-    square_element(i, m, ax, ay, bx, by);
+    load_element(eg, i, ax, ay, bx, by);
     const double mx = 0.5 * (ax + bx), my = 0.5 * (ay + by), hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay);
     const double half = sqrt(hx * hx + hy * hy);
     const double node[3] = {-kGaussNode, 0.0, kGaussNode};
@@ -128,12 +129,13 @@ __global__ void k_apply_pinv(const double* __restrict__ Ap, int M, const double*
     }
 }
 
-__global__ void k_pack_elements(const double* __restrict__ U, int M, int m, double* __restrict__ e64, float* __restrict__ e32)
+__global__ void k_pack_elements(const double* __restrict__ U, int M, const double* __restrict__ eg,
+                                double* __restrict__ e64, float* __restrict__ e32)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     double ax, ay, bx, by;
-    square_element(i, m, ax, ay, bx, by);
+    load_element(eg, i, ax, ay, bx, by);
     const double rec[kElemStride] = {ax, ay, bx - ax, by - ay, U[3 * i], U[3 * i + 1], U[3 * i + 2], 0.0};
     for (int c = 0; c < kElemStride; ++c) {
         e64[(size_t)i * kElemStride + c] = rec[c];
@@ -191,7 +193,8 @@ int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s)
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     {
         ProfScope ps_(ctx, PT_BOUNDARY, s);
-        hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K, ctx->per_side,
+        hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K,
+                           (const double*)ctx->egeo.ptr,
                            eps2, F);
     }
     return check_launch(ctx, "boundary_rhs");
@@ -209,7 +212,7 @@ int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s)
     int rc;
     if ((rc = ensure(ctx, ctx->elem64, (size_t)ctx->M * kElemStride * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->elem32, (size_t)ctx->M * kElemStride * sizeof(float), s))) return rc;
-    hipLaunchKernelGGL(k_pack_elements, dim3(blocks_for(ctx->M, 256)), dim3(256), 0, s, U, ctx->M, ctx->per_side,
+    hipLaunchKernelGGL(k_pack_elements, dim3(blocks_for(ctx->M, 256)), dim3(256), 0, s, U, ctx->M, (const double*)ctx->egeo.ptr,
                        (double*)ctx->elem64.ptr, (float*)ctx->elem32.ptr);
     return check_launch(ctx, "pack_elements");
 }

@@ -357,26 +357,27 @@ __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x,
     Store<OutT>::put(Xt, Xlo, row0 + j, t, ld, b);
 }
 
-__global__ void k_gauss_points(int M, int m, double* __restrict__ gx)
+__global__ void k_gauss_points(int M, const double* __restrict__ eg, double* __restrict__ gx)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * M) return;
     const int i = t / 3, q = t % 3;
     double ax, ay, bx, by;
-    square_element(i, m, ax, ay, bx, by);
+    load_element(eg, i, ax, ay, bx, by);
     const double node = q == 0 ? -kGaussNode : (q == 1 ? 0.0 : kGaussNode);
     gx[2 * t] = 0.5 * (ax + bx) + node * 0.5 * (bx - ax);
     gx[2 * t + 1] = 0.5 * (ay + by) + node * 0.5 * (by - ay);
 }
 
 // dF[i][f] = sum_q w_q |G_i|/2 Xg[f][3i + q]
-__global__ void k_boundary_features(const double* __restrict__ Xg, int nf, int M, int m, double* __restrict__ dF)
+__global__ void k_boundary_features(const double* __restrict__ Xg, int nf, int M, const double* __restrict__ eg,
+                                    double* __restrict__ dF)
 {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (f >= nf) return;
     double ax, ay, bx, by;
-    square_element(i, m, ax, ay, bx, by);
+    load_element(eg, i, ax, ay, bx, by);
     const double half = 0.5 * sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
     const double* r = Xg + (size_t)f * 3 * M + 3 * i;
     dF[(size_t)i * nf + f] = half * (kGaussW0 * r[0] + kGaussW1 * r[1] + kGaussW0 * r[2]);
@@ -581,9 +582,10 @@ int boundary_derivatives(bem_ctx* ctx, int H, hipStream_t s, double** Zout)
     double* Xg = gx + gxs;
     double* dF = (double*)ctx->tmp4.ptr;
     double* Z = dF + (size_t)M * nf;
-    hipLaunchKernelGGL(k_gauss_points, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, M, ctx->per_side, gx);
+    hipLaunchKernelGGL(k_gauss_points, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, M, (const double*)ctx->egeo.ptr, gx);
     if ((rc = launch_features<double>(ctx, gx, 3 * (int64_t)M, H, false, false, Xg, nullptr, 3 * (int64_t)M, s))) return rc;
-    hipLaunchKernelGGL(k_boundary_features, dim3(blocks_for(nf, 256), M), dim3(256), 0, s, Xg, nf, M, ctx->per_side, dF);
+    hipLaunchKernelGGL(k_boundary_features, dim3(blocks_for(nf, 256), M), dim3(256), 0, s, Xg, nf, M,
+                       (const double*)ctx->egeo.ptr, dF);
     if ((rc = check_launch(ctx, "boundary features"))) return rc;
     if ((rc = gemm_f64(ctx, M, nf, M, 1.0, (const double*)ctx->Apinv.ptr, M, false, dF, nf, false, 0.0, Z, nf, s,
                        nullptr, 0)))

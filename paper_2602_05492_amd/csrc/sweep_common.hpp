@@ -24,6 +24,16 @@ __device__ inline void square_element(int i, int m, double& ax, double& ay, doub
     bx = cx0 + t1 * dx; by = cy0 + t1 * dy;
 }
 
+// Outer element i of the element table eg [M][4] (a x, a y, b x, b y).
+__device__ inline void load_element(const double* eg, int i, double& ax, double& ay, double& bx, double& by)
+{
+    const double* e = eg + 4 * (size_t)i;
+    ax = e[0];
+    ay = e[1];
+    bx = e[2];
+    by = e[3];
+}
+
 // ---- near-singular pairs of the mixed-precision sweeps ---------------------------
 // A pair is near when both end points of the segment lie within 2*near_factor*L
 // of the sample (this contains every sample closer than near_factor*L to the

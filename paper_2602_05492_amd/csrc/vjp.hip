@@ -294,14 +294,14 @@ __global__ void k_reduce_parts(const double* __restrict__ partial, int nparts, i
 }
 
 // Gauss points of the outer elements and their cotangents mu_i w_q |G_i|/2.
-__global__ void k_gauss_cotangent(const double* __restrict__ mu, int M, int m, double* __restrict__ gx,
+__global__ void k_gauss_cotangent(const double* __restrict__ mu, int M, const double* __restrict__ eg, double* __restrict__ gx,
                                   double* __restrict__ gc)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * M) return;
     const int i = t / 3, q = t % 3;
     double ax, ay, bx, by;
-    square_element(i, m, ax, ay, bx, by);
+    load_element(eg, i, ax, ay, bx, by);
     const double hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay);
     const double node = q == 0 ? -kGaussNode : (q == 1 ? 0.0 : kGaussNode);
     const double w = (q == 1 ? kGaussW1 : kGaussW0) * sqrt(hx * hx + hy * hy);
@@ -443,7 +443,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                            (int64_t)M * 3, psi);
         if ((rc = check_launch(ctx, "vjp sweeps"))) return rc;
         if ((rc = launch_boundary_solve(ctx, psi, mu, true, s))) return rc;
-        hipLaunchKernelGGL(k_gauss_cotangent, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, mu, M, ctx->per_side, gx, gc);
+        hipLaunchKernelGGL(k_gauss_cotangent, dim3(blocks_for(3 * M, 256)), dim3(256), 0, s, mu, M,
+                           (const double*)ctx->egeo.ptr, gx, gc);
         {
             ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
             hipLaunchKernelGGL((k_vjp_segments<false, double>), dim3(kgroups, ng), dim3(256), 0, s, gx, gc,
