@@ -1,5 +1,6 @@
 // api.hip - the C ABI of include/bem.h: argument checks, call order,
 // workspaces and the orchestration of the kernels of each entry point.
+#include <rocblas/rocblas.h>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -445,8 +446,9 @@ void bem_destroy(bem_ctx* ctx)
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
-                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo};
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw};
     for (DevBuf* b : bufs) release(*b);
+    if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
     prof_resolve(ctx);
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
     delete ctx;

@@ -1,9 +1,11 @@
 // chol.hip - float64 Cholesky of the damped approximate Hessian
 // lambda D + J^T J (Eq. optimstep: positive definite, solved by Cholesky,
 // Sec. 4.3) and the two triangular solves for the LM step.
-// Blocked right-looking factorisation with 64-column panels: diagonal block
-// in LDS, panel rows by per-row forward substitution, trailing update by the
-// float64 GEMM.  A non-positive or non-finite pivot raises a device flag.
+// Blocked right-looking factorisation with 64-column panels: the diagonal block
+// in one wavefront's registers, inverted in the same kernel; the panel as a GEMM
+// with that inverse; the trailing update as a rank-64 symmetric update.  The solves
+// use the inverted diagonal blocks too: one launch per block and direction.  A
+// non-positive or non-finite pivot raises a device flag.
 #include "common.hpp"
 #include "sweep_common.hpp"
 
@@ -47,127 +49,316 @@ __device__ inline double readlane_f64(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// Factor the diagonal block kb in place (lower triangle).  One wavefront, lane i
-// holds row i in registers; column j's pivot and entries come from the owning
-// lanes by readlane (the loops are unrolled, so every lane index is a constant).
-// Rows / columns past the matrix are an identity block.
-__global__ void __launch_bounds__(64) k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag)
+// Factor the diagonal block kb in place (lower triangle) and write its inverse to
+// Linv [64][64] (row-major).  One wavefront, lane i holds row i in registers; column j's
+// pivot and entries come from the owning lanes by readlane (the loops are unrolled, so
+// every lane index is a constant).  Then L goes to LDS (its diagonal as reciprocals) and
+// lane j solves L x = e_j for column j of the inverse by forward substitution, x in LDS
+// column j (L read by broadcast).  Rows / columns past the matrix are an identity block.
+__global__ void __launch_bounds__(64) k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag,
+                                                   double* __restrict__ Linv)
 {
+    __shared__ double Ls[NB][NB];
+    __shared__ double Xs[NB][NB];
     const int64_t o = (int64_t)kb * NB;
     const int nb = (int)(P - o < NB ? P - o : NB);
     const int i = threadIdx.x;
-    double a[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-        a[k] = (i < nb && k < nb) ? (k <= i ? A[(o + i) * P + o + k] : 0.0) : (i == k ? 1.0 : 0.0);
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const double d = readlane_f64(a[j], j);
-        const bool ok = d > 0.0 && isfinite(d);
-        bad |= !ok;
-        const double sj = ok ? sqrt(d) : 1.0;
-        a[j] = i == j ? sj : a[j] / sj;
-        // entries above the diagonal of a row are never read back, so all lanes update
-#pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
-    }
-    if (bad && i == 0) flag[0] = 1;
-    if (i < nb)
+    {
+        double a[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-            if (k <= i && k < nb) A[(o + i) * P + o + k] = a[k];
+            a[k] = (i < nb && k < nb) ? (k <= i ? A[(o + i) * P + o + k] : 0.0) : (i == k ? 1.0 : 0.0);
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double d = readlane_f64(a[j], j);
+            const bool ok = d > 0.0 && isfinite(d);
+            bad |= !ok;
+            const double sj = ok ? sqrt(d) : 1.0;
+            a[j] = i == j ? sj : a[j] / sj;
+            // entries above the diagonal of a row are never read back, so all lanes update
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
+        }
+        if (bad && i == 0) flag[0] = 1;
+        if (i < nb)
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (k <= i && k < nb) A[(o + i) * P + o + k] = a[k];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) Ls[i][k] = k < i ? a[k] : (k == i ? 1.0 / a[k] : 0.0);
+    }
+    __syncthreads();
+    // column i of L^{-1}: x_k = (delta_ki - acc_k) / L_kk, then acc_r += L_rk x_k for r > k (the
+    // updates of one k are independent, so the broadcast LDS reads pipeline)
+    {
+        double acc[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const double xk = ((k == i ? 1.0 : 0.0) - acc[k]) * Ls[k][k];
+            Xs[k][i] = xk;
+#pragma unroll
+            for (int r = k + 1; r < NB; ++r) acc[r] += Ls[r][k] * xk;
+        }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) Linv[r * NB + i] = Xs[r][i];
 }
 
-// Panel rows below diagonal block kb: row <- row L_kk^{-T}.  A block of 64 threads
-// stages 64 rows and L_kk in LDS with coalesced loads; thread r then substitutes row r.
-__global__ void __launch_bounds__(64) k_trsm_panel(double* __restrict__ A, int64_t P, int kb)
+// Panel rows below diagonal block kb, in place: row <- row Linv_kk^T (= row L_kk^{-T}), with
+// Linv pointing at block kb's inverse [64][64].
+// 256 threads; the block stages its 64 rows and Linv_kk in LDS with coalesced loads and
+// thread (w, t) forms column t of rows w, w + 4, ...
+__global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P, int kb,
+                                               const double* __restrict__ Linv)
 {
-    __shared__ double L[NB][NB + 1];
-    __shared__ double R[NB][NB + 1];
+    __shared__ double R[NB][NB];        // rows (read by broadcast)
+    __shared__ double LiT[NB][NB];      // LiT[k][j] = Linv[j][k]
     const int64_t o = (int64_t)kb * NB;
     const int64_t r0 = o + NB + (int64_t)blockIdx.x * NB;
     const int nr = (int)(P - r0 < NB ? P - r0 : NB);
-    const int t = threadIdx.x;
-    for (int i = 0; i < NB; ++i) {
-        L[i][t] = t <= i ? A[(o + i) * P + o + t] : 0.0;
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = w; i < NB; i += 4) {
         R[i][t] = i < nr ? A[(r0 + i) * P + o + t] : 0.0;
+        LiT[t][i] = Linv[(size_t)i * NB + t];
     }
     __syncthreads();
-    if (t < nr) {
-        for (int j = 0; j < NB; ++j) {
-            double sum = R[t][j];
-            for (int l = 0; l < j; ++l) sum -= R[t][l] * L[j][l];
-            R[t][j] = sum / L[j][j];
-        }
+    double out[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) out[q] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < NB; ++k) {
+        const double l = LiT[k][t];                   // (Linv^T)[k][t]
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) out[q] += R[w + 4 * q][k] * l;
     }
-    __syncthreads();
-    for (int i = 0; i < nr; ++i) A[(r0 + i) * P + o + t] = R[i][t];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q)
+        if (w + 4 * q < nr) A[(r0 + w + 4 * q) * P + o + t] = out[q];
 }
 
-// Triangular solve of diagonal block kb on the nrhs columns of B [P][nrhs] (in place):
-// L y = b (trans 0) or L^T y = b (trans 1).  One wavefront; thread t owns row t.
-constexpr int kMaxRhs = 4;
-__global__ void __launch_bounds__(64) k_trsv_diag(const double* __restrict__ A, int64_t P, int kb,
-                                                  double* __restrict__ B, int nrhs, int trans)
+// Trailing update of step kb on float64 MFMA: C -= L21 L21^T on the lower triangle of the
+// trailing matrix C = A[o2:, o2:], o2 = 64 (kb + 1), with the panel L21 = A[o2:, o:o+64].
+// One block per 64 x 64 tile (I, J), I >= J (linear block index -> (I, J)); 4 waves, each a
+// 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  The two 64-row panel slices are
+// staged in LDS transposed ([k][row], 32 k at a time) so that an MFMA operand (lane l:
+// row l mod 16, k l / 16, the same pattern for both operands) is one ds_read per lane.
+// Accumulator element q of lane l is row 4 q + l / 16, column l mod 16 of its 16 x 16 tile.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kSyrkK = 32;               // k per LDS stage
+constexpr int kSyrkLd = 72;              // LDS row stride (doubles) of the transposed slices
+__global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t P, int kb, int nt)
 {
-    __shared__ double x[NB][kMaxRhs];
+    __shared__ double SI[kSyrkK][kSyrkLd];
+    __shared__ double SJ[kSyrkK][kSyrkLd];
+    const int64_t o = (int64_t)kb * NB, o2 = o + NB;
+    const int64_t rem = P - o2;
+    // tile (I, J), I >= J, from the linear index b = I (I + 1) / 2 + J
+    const int b = blockIdx.x;
+    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int J = b - I * (I + 1) / 2;
+    if (I >= nt) return;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t rI = (int64_t)I * NB, rJ = (int64_t)J * NB;
+    d4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < NB; k0 += kSyrkK) {
+        // stage: thread (row r = tid / 4 .. , k) loads coalesced runs of the two slices
+        for (int e = tid; e < NB * kSyrkK; e += 256) {
+            const int r = e / kSyrkK, k = e % kSyrkK;
+            const int64_t gi = rI + r, gj = rJ + r;
+            SI[k][r] = gi < rem ? A[(o2 + gi) * P + o + k0 + k] : 0.0;
+            SJ[k][r] = gj < rem ? A[(o2 + gj) * P + o + k0 + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kSyrkK; ks += 4) {
+            const int kk = ks + (l >> 4), rr = l & 15;
+            const double a0 = SI[kk][32 * wr + rr], a1 = SI[kk][32 * wr + 16 + rr];
+            const double b0 = SJ[kk][32 * wc + rr], b1 = SJ[kk][32 * wc + 16 + rr];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gr = rI + 32 * wr + 16 * i + 4 * q + (l >> 4);
+                const int64_t gc = rJ + 32 * wc + 16 * j + (l & 15);
+                if (gr < rem && gc <= gr) A[(o2 + gr) * P + o2 + gc] -= acc[i][j][q];
+            }
+}
+
+// Forward step kb of L y = b with the inverted diagonal blocks, B [P][nrhs]: every block
+// forms y_kb = Linv_kb b_kb; block 0 writes it to Y, block t >= 1 subtracts L y_kb from the
+// 64 rows starting at o + 64 t (B rows of block kb itself are not modified in this step).
+// 256 threads: operand tiles are staged in LDS, each wave loading 16 rows, and the products
+// are split over the 4 waves by k and summed in LDS.
+constexpr int kMaxRhs = 4;
+// the four waves' partial sums of row t
+__device__ inline void solve_sum(const double (*part)[NB][kMaxRhs], int t, int nrhs, double* out)
+{
+    for (int c = 0; c < nrhs; ++c) out[c] = part[0][t][c] + part[1][t][c] + part[2][t][c] + part[3][t][c];
+}
+
+__global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, int64_t P, int kb,
+                                                  const double* __restrict__ Linv, double* __restrict__ B,
+                                                  double* __restrict__ Y, int nrhs)
+{
+    __shared__ double T[NB][NB + 1];
+    __shared__ double bk[NB][kMaxRhs];
+    __shared__ double y[NB][kMaxRhs];
+    __shared__ double part[4][NB][kMaxRhs];
     const int64_t o = (int64_t)kb * NB;
     const int nb = (int)(P - o < NB ? P - o : NB);
-    const int t = threadIdx.x;
-    if (t < nb)
-        for (int c = 0; c < nrhs; ++c) x[t][c] = B[(o + t) * nrhs + c];
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double* L0 = Linv + (size_t)kb * NB * NB;
+#pragma unroll
+    for (int r = w; r < NB; r += 4) T[r][t] = L0[(size_t)r * NB + t];
+    if (w == 0)
+        for (int c = 0; c < nrhs; ++c) bk[t][c] = t < nb ? B[(o + t) * nrhs + c] : 0.0;
     __syncthreads();
-    if (!trans) {
-        for (int j = 0; j < nb; ++j) {
-            if (t < nrhs) x[j][t] /= A[(o + j) * P + o + j];
-            __syncthreads();
-            if (t > j && t < nb) {
-                const double l = A[(o + t) * P + o + j];
-                for (int c = 0; c < nrhs; ++c) x[t][c] -= l * x[j][c];
-            }
-            __syncthreads();
+    {
+        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 16 * w; k < 16 * w + 16; ++k) {
+            const double l = T[t][k];
+            for (int c = 0; c < nrhs; ++c) acc[c] += l * bk[k][c];
         }
-    } else {
-        for (int j = nb - 1; j >= 0; --j) {
-            if (t < nrhs) x[j][t] /= A[(o + j) * P + o + j];
-            __syncthreads();
-            if (t < j) {
-                const double l = A[(o + j) * P + o + t];
-                for (int c = 0; c < nrhs; ++c) x[t][c] -= l * x[j][c];
-            }
-            __syncthreads();
-        }
+        for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
     }
-    if (t < nb)
-        for (int c = 0; c < nrhs; ++c) B[(o + t) * nrhs + c] = x[t][c];
+    __syncthreads();
+    if (w == 0) {
+        double v[kMaxRhs];
+        solve_sum(part, t, nrhs, v);
+        for (int c = 0; c < nrhs; ++c) y[t][c] = v[c];
+        if (blockIdx.x == 0 && t < nb)
+            for (int c = 0; c < nrhs; ++c) Y[(o + t) * nrhs + c] = v[c];
+    }
+    if (blockIdx.x == 0) return;
+    const int64_t r0 = o + (int64_t)blockIdx.x * NB;
+    const int nr = (int)(P - r0 < NB ? P - r0 : NB);
+#pragma unroll
+    for (int k = w; k < NB; k += 4) T[k][t] = (k < nr && t < nb) ? A[(r0 + k) * P + o + t] : 0.0;
+    __syncthreads();
+    {
+        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 16 * w; k < 16 * w + 16; ++k) {
+            const double l = T[t][k];
+            for (int c = 0; c < nrhs; ++c) acc[c] += l * y[k][c];
+        }
+        for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
+    }
+    __syncthreads();
+    if (w == 0 && t < nr) {
+        double v[kMaxRhs];
+        solve_sum(part, t, nrhs, v);
+        for (int c = 0; c < nrhs; ++c) B[(r0 + t) * nrhs + c] -= v[c];
+    }
+}
+
+// Backward step kb of L^T x = y: every block forms x_kb = Linv_kb^T y_kb; block 0 writes it
+// to X, block t >= 1 subtracts L[block kb rows, c]^T x_kb from the 64 entries of Y starting
+// at column c = 64 (t - 1) (only columns before block kb; Y rows of block kb are only read).
+__global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, int64_t P, int kb,
+                                                  const double* __restrict__ Linv, double* __restrict__ Y,
+                                                  double* __restrict__ X, int nrhs)
+{
+    __shared__ double T[NB][NB + 1];
+    __shared__ double yk[NB][kMaxRhs];
+    __shared__ double x[NB][kMaxRhs];
+    __shared__ double part[4][NB][kMaxRhs];
+    const int64_t o = (int64_t)kb * NB;
+    const int nb = (int)(P - o < NB ? P - o : NB);
+    const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double* L0 = Linv + (size_t)kb * NB * NB;
+#pragma unroll
+    for (int r = w; r < NB; r += 4) T[r][t] = L0[(size_t)r * NB + t];
+    if (w == 0)
+        for (int c = 0; c < nrhs; ++c) yk[t][c] = t < nb ? Y[(o + t) * nrhs + c] : 0.0;
+    __syncthreads();
+    {
+        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 16 * w; k < 16 * w + 16; ++k) {
+            const double l = T[k][t];                  // (Linv^T)[t][k]
+            for (int c = 0; c < nrhs; ++c) acc[c] += l * yk[k][c];
+        }
+        for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
+    }
+    __syncthreads();
+    if (w == 0) {
+        double v[kMaxRhs];
+        solve_sum(part, t, nrhs, v);
+        for (int c = 0; c < nrhs; ++c) x[t][c] = v[c];
+        if (blockIdx.x == 0 && t < nb)
+            for (int c = 0; c < nrhs; ++c) X[(o + t) * nrhs + c] = v[c];
+    }
+    if (blockIdx.x == 0) return;
+    const int64_t col = (int64_t)(blockIdx.x - 1) * NB + t;
+#pragma unroll
+    for (int r = w; r < NB; r += 4) T[r][t] = (r < nb && col < o) ? A[(o + r) * P + col] : 0.0;
+    __syncthreads();
+    {
+        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = 16 * w; r < 16 * w + 16; ++r) {
+            const double l = T[r][t];
+            for (int c = 0; c < nrhs; ++c) acc[c] += l * x[r][c];
+        }
+        for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
+    }
+    __syncthreads();
+    if (w == 0 && col < o) {
+        double v[kMaxRhs];
+        solve_sum(part, t, nrhs, v);
+        for (int c = 0; c < nrhs; ++c) Y[col * nrhs + c] -= v[c];
+    }
 }
 
 }  // namespace
 
-// Damp, factor and check: returns BEM_ENOTPD when a pivot fails (host sync).
+// Damp, factor and check: returns BEM_ENOTPD when a pivot fails (host sync).  Blocked
+// right-looking with 64-column panels: the diagonal block and its inverse by k_potrf_diag,
+// the panel as A21 Linv^T (one GEMM into a scratch panel, copied back), the trailing
+// lower triangle by a rank-64 update.  The inverted diagonal blocks stay in the context
+// for chol_solve.
 int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,
                 hipStream_t s)
 {
     int rc;
+    const int nblk = (int)((P + NB - 1) / NB);
+    // cholw: inverted diagonal blocks [nblk][64][64] | solve vector [P][4]
+    if ((rc = ensure(ctx, ctx->cholw, ((size_t)nblk * NB * NB + (size_t)P * kMaxRhs) * sizeof(double), s))) return rc;
+    double* linv = (double*)ctx->cholw.ptr;
     hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(256), 0, s, H, P, dscal);
     hipLaunchKernelGGL(k_damp, dim3(blocks_for(P, 256), P), dim3(256), 0, s, H, P, lam, dscal, A);
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
-    const int nblk = (int)((P + NB - 1) / NB);
     ProfScope ps_(ctx, PT_CHOLESKY, s);
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb, dflag);
+        double* Li = linv + (size_t)kb * NB * NB;
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb, dflag, Li);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
         if (rem > 0) {
-            hipLaunchKernelGGL(k_trsm_panel, dim3(blocks_for(rem, NB)), dim3(NB), 0, s, A, P, kb);
-            double* panel = A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB;
-            double* trail = A + (int64_t)(kb + 1) * NB * P + (int64_t)(kb + 1) * NB;
-            if ((rc = gemm_f64(ctx, (int)rem, (int)rem, NB, -1.0, panel, P, false, panel, P, true, 1.0, trail, P, s,
-                               nullptr, 0)))
-                return rc;
+            hipLaunchKernelGGL(k_panel, dim3(blocks_for(rem, NB)), dim3(256), 0, s, A, P, kb, (const double*)Li);
+            const int nt = blocks_for(rem, NB);
+            hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, P, kb, nt);
         }
     }
     if ((rc = check_launch(ctx, "cholesky"))) return rc;
+    ctx->chol_P = P;
     int hflag = 0;
     if (hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -175,29 +366,25 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     return hflag ? BEM_ENOTPD : BEM_OK;
 }
 
-// B <- (L L^T)^{-1} B with the factor in A; B [P][nrhs] row-major, nrhs <= 4.
+// B <- (L L^T)^{-1} B with the factor in A and the inverted diagonal blocks of the last
+// chol_factor; B [P][nrhs] row-major, nrhs <= 4.  One launch per block and direction.
 int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* B, int nrhs, hipStream_t s)
 {
-    int rc;
     if (nrhs < 1 || nrhs > kMaxRhs) return set_error(ctx, BEM_EINVAL, "chol_solve: 1..4 right-hand sides");
+    if (ctx->chol_P != P) return set_error(ctx, BEM_ESTATE, "chol_solve without a matching chol_factor");
     ProfScope ps_(ctx, PT_CHOLESKY, s);
     const int nblk = (int)((P + NB - 1) / NB);
+    const double* linv = (const double*)ctx->cholw.ptr;
+    double* Y = (double*)ctx->cholw.ptr + (size_t)nblk * NB * NB;
     for (int kb = 0; kb < nblk; ++kb) {
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, B, nrhs, 0);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
-        if (rem > 0 &&
-            (rc = gemm_f64(ctx, (int)rem, nrhs, NB, -1.0, A + (int64_t)(kb + 1) * NB * P + (int64_t)kb * NB, P, false,
-                           B + (int64_t)kb * NB * nrhs, nrhs, false, 1.0, B + (int64_t)(kb + 1) * NB * nrhs, nrhs, s,
-                           nullptr, 0)))
-            return rc;
+        const int nbk = 1 + (rem > 0 ? blocks_for(rem, NB) : 0);
+        hipLaunchKernelGGL(k_fwd_step, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, B, Y, nrhs);
     }
     for (int kb = nblk - 1; kb >= 0; --kb) {
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(NB), 0, s, A, P, kb, B, nrhs, 1);
         const int64_t o = (int64_t)kb * NB;
-        const int nb = (int)(P - o < NB ? P - o : NB);
-        if (o > 0 && (rc = gemm_f64(ctx, (int)o, nrhs, nb, -1.0, A + o * P, P, true, B + o * nrhs, nrhs, false, 1.0, B,
-                                    nrhs, s, nullptr, 0)))
-            return rc;
+        const int nbk = 1 + (o > 0 ? blocks_for(o, NB) : 0);
+        hipLaunchKernelGGL(k_bwd_step, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, Y, B, nrhs);
     }
     return check_launch(ctx, "cholesky solve");
 }

@@ -83,13 +83,15 @@ struct bem_ctx {
     // normal equations the geometry columns of one channel and the channel-shared colour columns
     int model = 0, npar = 20, ngeo = 8, ncol = 4;
     bem_reg reg{};           // regularisation terms of lm_step (all off by default)
+    void* blas = nullptr;    // rocBLAS handle (plain FP64 GEMMs), created on first use
+    int64_t chol_P = -1;     // order of the last Cholesky factor (its inverted diagonal blocks are in cholw)
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal, egeo;   // egeo: outer elements [M][4] (a, b)
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw;
 };
 
 namespace bem {

@@ -1,8 +1,11 @@
 // gemm.hip - float64 dense products used around the normal equations:
 //   C = alpha op(A) op(B) + beta C   (row-major, op = identity or transpose)
-// 64x64 output tiles, 16-deep k slabs staged through LDS, 4x4 outputs per
-// thread.  An optional list of output tiles restricts the launch to the
-// blocks a caller needs (the upper-triangle Gram blocks).
+// Plain products of more than 2^22 multiply-adds go to rocBLAS dgemm (FP64 MFMA;
+// atomics off, so results are reproducible); the rest, and every launch restricted
+// to a list of output tiles (the upper-triangle FP64 Gram), run in k_gemm_f64:
+// 64x64 output tiles, 16-deep k slabs staged through LDS, 4x4 outputs per thread.
+#include <rocblas/rocblas.h>
+
 #include "common.hpp"
 #include "sweep_common.hpp"
 
@@ -77,10 +80,35 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int k, double al
 
 }  // namespace
 
+// The context's rocBLAS handle on stream s (created on first use).
+static rocblas_handle blas(bem_ctx* ctx, hipStream_t s)
+{
+    if (!ctx->blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+        rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
+        ctx->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)ctx->blas;
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return nullptr;
+    return h;
+}
+
 int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta, const double* B,
              int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles)
 {
     if (m <= 0 || n <= 0) return BEM_OK;
+    if (!tiles && k > 0 && (double)m * n * k > (double)(1 << 22)) {
+        // row-major C = op(A) op(B) is column-major C^T = op(B)^T op(A)^T on the same memory
+        rocblas_handle h = blas(ctx, s);
+        if (!h) return set_error(ctx, BEM_EHIP, "rocBLAS handle");
+        const rocblas_status st =
+            rocblas_dgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                          ta ? rocblas_operation_transpose : rocblas_operation_none, n, m, k, &alpha, B, (int)ldb, A,
+                          (int)lda, &beta, C, (int)ldc);
+        if (st != rocblas_status_success) return set_error(ctx, BEM_EHIP, "rocblas_dgemm: status %d", (int)st);
+        return BEM_OK;
+    }
     if (tiles) {
         if (ntiles <= 0) return BEM_OK;
         hipLaunchKernelGGL(k_gemm_f64, dim3(ntiles), dim3(256), 0, s, m, n, k, alpha, A, lda, ta ? 1 : 0, B, ldb,
