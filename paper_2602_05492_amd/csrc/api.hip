@@ -44,6 +44,26 @@ int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream)
     return BEM_OK;
 }
 
+// The context's second stream (default priority) and its six events (no timing).
+int aux_stream(bem_ctx* ctx, hipStream_t* out)
+{
+    if (!ctx->s2) {
+        if (hipStreamCreateWithFlags(&ctx->s2, hipStreamNonBlocking) != hipSuccess) {
+            ctx->s2 = nullptr;
+            hipGetLastError();
+            return set_error(ctx, BEM_EHIP, "second stream");
+        }
+        for (hipEvent_t& e : ctx->ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                e = nullptr;
+                hipGetLastError();
+                return set_error(ctx, BEM_EHIP, "stream events");
+            }
+    }
+    *out = ctx->s2;
+    return BEM_OK;
+}
+
 int check_launch(bem_ctx* ctx, const char* what)
 {
     const hipError_t e = hipGetLastError();
@@ -449,6 +469,9 @@ void bem_destroy(bem_ctx* ctx)
                       &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw};
     for (DevBuf* b : bufs) release(*b);
     if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
+    for (hipEvent_t e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    if (ctx->s2) hipStreamDestroy(ctx->s2);
     prof_resolve(ctx);
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
     delete ctx;

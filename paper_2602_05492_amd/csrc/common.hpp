@@ -85,6 +85,10 @@ struct bem_ctx {
     bem_reg reg{};           // regularisation terms of lm_step (all off by default)
     void* blas = nullptr;    // rocBLAS handle (plain FP64 GEMMs), created on first use
     int64_t chol_P = -1;     // order of the last Cholesky factor (its inverted diagonal blocks are in cholw)
+    // second stream of the normal equations (the Gram of a sample tile runs on it while the next
+    // tile's feature rows are formed on the caller's stream) and its events, created on first use
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev[6] = {};
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;
@@ -110,6 +114,7 @@ struct ProfScope {
     ~ProfScope() { prof_end(ctx, tag, s, start); }
 };
 int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream);
+int aux_stream(bem_ctx* ctx, hipStream_t* out);
 int check_launch(bem_ctx* ctx, const char* what);
 
 inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }

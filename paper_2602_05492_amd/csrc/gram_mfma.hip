@@ -168,26 +168,26 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
                                              (void*)&SM[2 * ab + 1][d_], 16, 0, 0);            \
         }                                                                                      \
     }
-    // operand read offsets: rows of this lane, chunk 2 * h + lk for half h of the stage
-    int aoff[2][2], boff[2][4];
+    // operand read offsets: rows of this lane, chunk 2 * h + lk for half h of the stage.  Rows 32 m
+    // further on sit 1024 m elements further (the swizzle depends on row bits 1..3 only), so one
+    // offset per half and operand serves every 32-row tile with an immediate displacement.
+    int aoff[2], boff[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi) aoff[h][mi] = g2_lds(wr * 64 + mi * 32 + li, 2 * h + lk);
-#pragma unroll
-        for (int nj = 0; nj < 4; ++nj) boff[h][nj] = g2_lds(wc * 128 + nj * 32 + li, 2 * h + lk);
+        aoff[h] = g2_lds(wr * 64 + li, 2 * h + lk);
+        boff[h] = g2_lds(wc * 128 + li, 2 * h + lk);
     }
 // multiply the stage in LDS buffer SM: 8 steps (half h = step / 4, column tile nj = step % 4);
 // the B operands of the next step (and the A operands of the second half) are read from LDS
 // while the current step's MFMAs run
 #define G2_A(SM, h, ah, al)                                                                   \
     _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                        \
-        ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[0][aoff[h][mi]]);              \
-        al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[1][aoff[h][mi]]);              \
+        ah[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[0][aoff[h] + 1024 * mi]);      \
+        al[mi] = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[1][aoff[h] + 1024 * mi]);      \
     }
 #define G2_B(SM, h, nj, bh, bl)                                                               \
-    bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[2][boff[h][nj]]);                      \
-    bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[3][boff[h][nj]]);
+    bh = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[2][boff[h] + 1024 * (nj)]);            \
+    bl = __builtin_bit_cast(bf16x8, *(const u16x8*)&SM[3][boff[h] + 1024 * (nj)]);
 #define G2_STEP(ah, al, bh, bl, nj)                                                           \
     _Pragma("unroll") for (int mi = 0; mi < 2; ++mi) {                                        \
         acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh, acc[mi][nj], 0, 0, 0); \

@@ -688,8 +688,15 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // deterministic (no atomics)
     const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 3 : 1;
     const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
-    // tmp0: feature tile; tmp1: R [W][3] + G [parts][W][W] + X r partials; tmp2: residual in f64
-    if ((rc = ensure(ctx, ctx->tmp0, (size_t)W * T * elem, s))) return rc;
+    // MFMA Grams with several sample tiles: the Gram of tile t runs on a second stream while tile t+1's
+    // feature rows are formed on the caller's stream (two tile buffers), so the VALU-bound feature
+    // kernels and the MFMA-bound Gram share the chip
+    const bool overlap = gram != BEM_GRAM_FP64 && N > T;
+    const size_t tile_bytes = ((size_t)W * T * elem + 255) / 256 * 256;
+    hipStream_t sg = s;
+    if (overlap && (rc = aux_stream(ctx, &sg))) return rc;
+    // tmp0: feature tile(s); tmp1: R [W][3] + G [parts][W][W] + X r partials; tmp2: residual in f64
+    if ((rc = ensure(ctx, ctx->tmp0, tile_bytes * (overlap ? 2 : 1), s))) return rc;
     if ((rc = ensure(ctx, ctx->tmp1,
                      ((size_t)parts * W * W + (size_t)W * 3 + (size_t)kXrPartials * W * 3) * sizeof(double), s)))
         return rc;
@@ -730,11 +737,22 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // the tile list is read by every tile's Gram; keep the host copy alive until queued work is done
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, BEM_EHIP, "tile list sync");
     const int* dtiles = (const int*)ctx->tmp5.ptr;
-    for (int64_t t0 = 0; t0 < N; t0 += T) {
+    hipEvent_t* evF = ctx->ev;          // features of the tile in buffer b done
+    hipEvent_t* evG = ctx->ev + 2;      // Gram of the tile in buffer b done
+    if (overlap) {                      // the Gram stream starts after everything queued so far
+        if (hipEventRecord(ctx->ev[4], s) != hipSuccess || hipStreamWaitEvent(sg, ctx->ev[4], 0) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "stream fork");
+    }
+    int it = 0;
+    for (int64_t t0 = 0; t0 < N; t0 += T, ++it) {
         const int64_t n = N - t0 < T ? N - t0 : T;
         const double* xt = x + 2 * t0;
+        const int buf = overlap ? (it & 1) : 0;
+        void* tile = (char*)ctx->tmp0.ptr + (size_t)buf * tile_bytes;
+        if (overlap && it >= 2 && hipStreamWaitEvent(s, evG[buf], 0) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "stream wait");
         if (gram == BEM_GRAM_FP64) {
-            double* Xt = (double*)ctx->tmp0.ptr;
+            double* Xt = (double*)tile;
             if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
@@ -745,22 +763,31 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 (rc = gemm_f64(ctx, (int)W, 3, (int)n, 1.0, Xt, T, false, r64 + 3 * t0, 3, false, 1.0, R, 3, s, nullptr, 0)))
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
-            float* Xt = (float*)ctx->tmp0.ptr;
+            float* Xt = (float*)tile;
             if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
-            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
+            if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
+                return set_error(ctx, BEM_EHIP, "stream wait");
+            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, sg)))
                 return rc;
-            if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
         } else {
-            uint16_t* Xh = (uint16_t*)ctx->tmp0.ptr;
+            uint16_t* Xh = (uint16_t*)tile;
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
             if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab))) return rc;
             if (n & 31)
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
-            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, s)))
+            if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
+                return set_error(ctx, BEM_EHIP, "stream wait");
+            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, sg)))
                 return rc;
-            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, s))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
         }
+        if (overlap && hipEventRecord(evG[buf], sg) != hipSuccess) return set_error(ctx, BEM_EHIP, "stream event");
+    }
+    if (overlap) {                      // join: the caller's stream continues after the last Gram
+        if (hipEventRecord(ctx->ev[5], sg) != hipSuccess || hipStreamWaitEvent(s, ctx->ev[5], 0) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "stream join");
     }
     if (parts > 1) {
         hipLaunchKernelGGL(k_sum_parts, dim3(4096), dim3(256), 0, s, G, parts, W * W);
