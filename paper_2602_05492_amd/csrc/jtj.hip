@@ -184,7 +184,7 @@ constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] 
 // first sample, whose global index is t0 (a multiple of 64); flagged samples are
 // rewritten afterwards by k_features<true>.
 template <class OutT>
-__global__ void __launch_bounds__(256) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
+__global__ void __launch_bounds__(256, 6) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
                                                       const float* __restrict__ seg32, int H, int S, int model,
                                                       float eps2f,
                                                       float near2, const NearPair* __restrict__ list,
