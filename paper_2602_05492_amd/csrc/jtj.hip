@@ -104,10 +104,12 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
                                                   OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
 {
     using A = typename std::conditional<Mixed, float, double>::type;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = blockIdx.y;
-    if (t >= npts) return;
-    if (only && !only[t]) return;
+    // all points: one per thread; only the flagged ones (only != null): a few blocks stride
+    // over the tile, so that a tile with few or no flagged samples costs a small launch
+    const int64_t stride = only ? (int64_t)gridDim.x * blockDim.x : npts;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npts; t += stride) {
+    if (only && !only[t]) continue;
     const double X = x[2 * t], Y = x[2 * t + 1];
     const float Xf = (float)X, Yf = (float)Y;
     A geo[3][8];
@@ -173,6 +175,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
         }
     }
     store_handle_rows(model, Xt, Xlo, H, h, t, ld, geo, col);
+    }
 }
 
 constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] and col[4]
@@ -541,7 +544,8 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
                                H, S, model, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo, ld);
-            hipLaunchKernelGGL((k_features<true, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+            const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
+            hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, H, S, model, eps2, (float)eps2, near2, nl->flag + t0, Xt,
                                Xlo, ld);
         } else {
