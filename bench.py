@@ -318,9 +318,18 @@ def main() -> int:
     sweep_valu = None
     if fpp and pairs_fwd:
         tf = fpp * pairs_fwd / 1e12
+        sw = pmc_record()["sweep"]
+        samples_per_s = pairs_fwd / (K + M)
+        bytes_per_sample = (sw["fetch_kib"] * pmc_record()["fetch_scale"] + sw["write_kib"] * pmc_record()["write_scale"]) \
+            * 1024.0 / sw["samples"]
+        trans = sw["trans_per_pair"] * pairs_fwd / 1e12
         sweep_valu = {"kernel": "sweep_mixed", "pairs_per_s": pairs_fwd, "fp32_flops_per_pair": fpp, "achieved": tf,
                       "unit": "TFLOP/s", "peak": PEAKS["fp32_vector"] / 1e12, "frac": tf / (PEAKS["fp32_vector"] / 1e12),
-                      "frac_of_unpacked_peak": tf / (PEAKS["fp32_vector"] / 2e12)}
+                      "frac_of_unpacked_peak": tf / (PEAKS["fp32_vector"] / 2e12),
+                      # transcendental (quarter-rate) ops: 16 lanes per CU per clock = 157.3 / 16 T/s
+                      "transcendental_tops": trans, "transcendental_frac": trans / (PEAKS["fp32_vector"] / 16e12),
+                      "hbm_bytes_per_sample": bytes_per_sample,
+                      "hbm_gbps": bytes_per_sample * samples_per_s / 1e9, "hbm_frac": bytes_per_sample * samples_per_s / 8e12}
 
     speedup = None
     fp64_ms = None
