@@ -150,7 +150,9 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kSyrkK = 32;               // k per LDS stage
 constexpr int kSyrkLd = 72;              // LDS row stride (doubles) of the transposed slices
-__global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t P, int kb, int nt)
+// mode 0: every tile; 1: the first tile column only (J = 0: the next diagonal block and panel);
+// 2: the other tiles (J >= 1).
+__global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t P, int kb, int nt, int mode)
 {
     __shared__ double SI[kSyrkK][kSyrkLd];
     __shared__ double SJ[kSyrkK][kSyrkLd];
@@ -158,10 +160,17 @@ __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t 
     const int64_t rem = P - o2;
     // tile (I, J), I >= J, from the linear index b = I (I + 1) / 2 + J
     const int b = blockIdx.x;
-    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= b) ++I;
-    while (I * (I + 1) / 2 > b) --I;
-    const int J = b - I * (I + 1) / 2;
+    int I, J;
+    if (mode == 1) {
+        I = b;
+        J = 0;
+    } else {
+        I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) / 2 <= b) ++I;
+        while (I * (I + 1) / 2 > b) --I;
+        J = b - I * (I + 1) / 2;
+        if (mode == 2 && J == 0) return;
+    }
     if (I >= nt) return;
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -347,16 +356,37 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     hipLaunchKernelGGL(k_damp, dim3(blocks_for(P, 256), P), dim3(256), 0, s, H, P, lam, dscal, A);
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
     ProfScope ps_(ctx, PT_CHOLESKY, s);
+    // Look-ahead: after step kb's panel, the first tile column of the trailing update (the next
+    // diagonal block and panel) runs on the caller's stream and the next step's diagonal block
+    // and panel follow it there, while the rest of the trailing update runs on the second
+    // stream; the next step's first-column update waits for that rest.
+    hipStream_t s2 = s;
+    const bool ahead = nblk > 2;
+    if (ahead && (rc = aux_stream(ctx, &s2))) return rc;
+    hipEvent_t evA = ctx->ev[0], evB = ctx->ev[1];
+    if (ahead && (hipEventRecord(evB, s) != hipSuccess || hipStreamWaitEvent(s2, evB, 0) != hipSuccess))
+        return set_error(ctx, BEM_EHIP, "cholesky fork");
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, 0, dflag, linv);
     for (int kb = 0; kb < nblk; ++kb) {
         double* Li = linv + (size_t)kb * NB * NB;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb, dflag, Li);
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
-        if (rem > 0) {
-            hipLaunchKernelGGL(k_panel, dim3(blocks_for(rem, NB)), dim3(256), 0, s, A, P, kb, (const double*)Li);
-            const int nt = blocks_for(rem, NB);
-            hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, P, kb, nt);
+        if (rem <= 0) break;
+        const int nt = blocks_for(rem, NB);
+        hipLaunchKernelGGL(k_panel, dim3(nt), dim3(256), 0, s, A, P, kb, (const double*)Li);
+        if (!ahead) {
+            hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, P, kb, nt, 0);
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
+            continue;
         }
+        if (kb > 0 && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky wait");
+        hipLaunchKernelGGL(k_syrk64, dim3(nt), dim3(256), 0, s, A, P, kb, nt, 1);
+        if (hipEventRecord(evA, s) != hipSuccess || hipStreamWaitEvent(s2, evA, 0) != hipSuccess)
+            return set_error(ctx, BEM_EHIP, "cholesky event");
+        if (nt > 1) hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s2, A, P, kb, nt, 2);
+        if (hipEventRecord(evB, s2) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky event");
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
     }
+    if (ahead && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky join");
     if ((rc = check_launch(ctx, "cholesky"))) return rc;
     ctx->chol_P = P;
     int hflag = 0;

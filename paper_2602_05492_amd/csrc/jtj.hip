@@ -66,25 +66,39 @@ template <> struct Store<uint16_t> {
 
 // Feature rows of one (point, handle): the chained gradients geo[c][q] on the four weights of
 // vertex_weights and the coefficients col[m] of wd0, wd1, wc0, wc1 (jumps at t = 0 and t = 1).
-// Cubic handles (model 0): rows c*8H + 8h + q and 24H + 4h + m.  Straight handles (model 1):
-// the end-point gradients are geo[c][0..3], rows c*4H + 4h + q, and the constant jumps take
-// the sum of their two end coefficients, rows 12H + 2h + {0: wd, 1: wc}.
+// Channel c's geometry rows start at c * gp, gp = G H rounded up to a multiple of 256 (the
+// Gram's tile), so that no Gram tile mixes two channels; the colour rows start at 3 gp.
+// Cubic handles (model 0, G = 8): rows c gp + 8h + q and 3 gp + 4h + m.  Straight handles
+// (model 1, G = 4): the end-point gradients are geo[c][0..3], rows c gp + 4h + q, and the
+// constant jumps take the sum of their two end coefficients, rows 3 gp + 2h + {0: wd, 1: wc}.
 template <class OutT, class A>
 __device__ inline void store_handle_rows(int model, OutT* Xt, uint16_t* Xlo, int H, int h, int64_t t, int64_t ld,
-                                         const A (&geo)[3][8], const A (&col)[4])
+                                         int64_t gp, const A (&geo)[3][8], const A (&col)[4])
 {
     if (model == 1) {
         for (int c = 0; c < 3; ++c)
             for (int q = 0; q < 4; ++q)
-                Store<OutT>::put(Xt, Xlo, (int64_t)c * 4 * H + 4 * h + q, t, ld, (double)geo[c][q]);
-        Store<OutT>::put(Xt, Xlo, (int64_t)12 * H + 2 * h, t, ld, (double)col[0] + (double)col[1]);
-        Store<OutT>::put(Xt, Xlo, (int64_t)12 * H + 2 * h + 1, t, ld, (double)col[2] + (double)col[3]);
+                Store<OutT>::put(Xt, Xlo, (int64_t)c * gp + 4 * h + q, t, ld, (double)geo[c][q]);
+        Store<OutT>::put(Xt, Xlo, 3 * gp + 2 * h, t, ld, (double)col[0] + (double)col[1]);
+        Store<OutT>::put(Xt, Xlo, 3 * gp + 2 * h + 1, t, ld, (double)col[2] + (double)col[3]);
         return;
     }
     for (int c = 0; c < 3; ++c)
         for (int q = 0; q < 8; ++q)
-            Store<OutT>::put(Xt, Xlo, (int64_t)c * 8 * H + 8 * h + q, t, ld, (double)geo[c][q]);
-    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, (int64_t)24 * H + 4 * h + q, t, ld, (double)col[q]);
+            Store<OutT>::put(Xt, Xlo, (int64_t)c * gp + 8 * h + q, t, ld, (double)geo[c][q]);
+    for (int q = 0; q < 4; ++q) Store<OutT>::put(Xt, Xlo, 3 * gp + 4 * h + q, t, ld, (double)col[q]);
+}
+
+// Padding rows [c gp + G H, (c + 1) gp) of the three geometry blocks are zero in every tile.
+template <class OutT>
+__global__ void k_zero_pad(OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld, int64_t gp, int64_t gh,
+                           int64_t npts)
+{
+    const int64_t pad = gp - gh;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * pad * npts) return;
+    const int64_t r = i / npts, t = i % npts;
+    Store<OutT>::put(Xt, Xlo, (r / pad) * gp + gh + r % pad, t, ld, 0.0);
 }
 
 // Handle features of one point and one handle (thread per (point, handle)):
@@ -99,7 +113,7 @@ __device__ inline void store_handle_rows(int model, OutT* Xt, uint16_t* Xlo, int
 template <bool Mixed, class OutT>
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, int64_t npts,
                                                   const double* __restrict__ seg64, const float* __restrict__ seg32,
-                                                  int H, int S, int model, double eps2, float eps2f,
+                                                  int H, int S, int model, int64_t gp, double eps2, float eps2f,
                                                   float near2, const uint8_t* __restrict__ only,
                                                   OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
 {
@@ -109,72 +123,72 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
     // over the tile, so that a tile with few or no flagged samples costs a small launch
     const int64_t stride = only ? (int64_t)gridDim.x * blockDim.x : npts;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npts; t += stride) {
-    if (only && !only[t]) continue;
-    const double X = x[2 * t], Y = x[2 * t + 1];
-    const float Xf = (float)X, Yf = (float)Y;
-    A geo[3][8];
-    A col[4];
-    A pv[3][2];   // gradient carried to the next vertex (from the previous segment's b end)
-    for (int c = 0; c < 3; ++c) {
-        for (int q = 0; q < 8; ++q) geo[c][q] = A(0);
-        pv[c][0] = pv[c][1] = A(0);
-    }
-    for (int q = 0; q < 4; ++q) col[q] = A(0);
-    for (int j = 0; j <= S; ++j) {
-        // contributions to vertex j: a end of segment j (if j < S) + b end of segment j-1 (carried)
-        A va[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
-        A vb[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
-        if (j < S) {
-            const int k = h * S + j;
-            const double* s64 = seg64 + (size_t)k * kSegStride;
-            const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
-            Moments<A> m{A(0), A(0), A(0), A(0)};
-            bool done = false;
-            if (s64[6] == 0.0) done = true;                  // degenerate segment: nothing
-            if (!done && Mixed) {
-                const float* s32 = seg32 + (size_t)k * kSegStride;
-                const SegGeom<float> gf = load_geom(s32);
-                if (!near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
-                    const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-                    const Moments<float> mf = pair_moments(gf, st);
-                    m = Moments<A>{(A)mf.da, (A)mf.db, (A)mf.sa, (A)mf.sb};
-                    for (int c = 0; c < 3; ++c) {
-                        const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
-                                                              s32[kWcA + c], s32[kWcB + c]);
-                        va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
-                    }
-                    done = true;
-                }
-            }
-            if (!done) {
-                const SegGeom<double> g = load_geom(s64);
-                const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
-                const Moments<double> md = pair_moments(g, st);
-                m = Moments<A>{(A)md.da, (A)md.db, (A)md.sa, (A)md.sb};
-                for (int c = 0; c < 3; ++c) {
-                    const Grad4<double> gr = pair_backward(g, st, eps2, s64[kWdA + c], s64[kWdB + c], s64[kWcA + c],
-                                                           s64[kWcB + c]);
-                    va[c][0] = (A)gr.ax; va[c][1] = (A)gr.ay; vb[c][0] = (A)gr.bx; vb[c][1] = (A)gr.by;
-                }
-            }
-            col[0] += m.da * (A)(1.0 - ta) + m.db * (A)(1.0 - tb);
-            col[1] += m.da * (A)ta + m.db * (A)tb;
-            col[2] += m.sa * (A)(1.0 - ta) + m.sb * (A)(1.0 - tb);
-            col[3] += m.sa * (A)ta + m.sb * (A)tb;
-        }
-        double B[4];
-        vertex_weights(model, (double)j / (double)S, B);
+        if (only && !only[t]) continue;
+        const double X = x[2 * t], Y = x[2 * t + 1];
+        const float Xf = (float)X, Yf = (float)Y;
+        A geo[3][8];
+        A col[4];
+        A pv[3][2];   // gradient carried to the next vertex (from the previous segment's b end)
         for (int c = 0; c < 3; ++c) {
-            const A gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
-            for (int q = 0; q < 4; ++q) {
-                geo[c][2 * q] += (A)B[q] * gx;
-                geo[c][2 * q + 1] += (A)B[q] * gy;
-            }
-            pv[c][0] = vb[c][0];
-            pv[c][1] = vb[c][1];
+            for (int q = 0; q < 8; ++q) geo[c][q] = A(0);
+            pv[c][0] = pv[c][1] = A(0);
         }
-    }
-    store_handle_rows(model, Xt, Xlo, H, h, t, ld, geo, col);
+        for (int q = 0; q < 4; ++q) col[q] = A(0);
+        for (int j = 0; j <= S; ++j) {
+            // contributions to vertex j: a end of segment j (if j < S) + b end of segment j-1 (carried)
+            A va[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
+            A vb[3][2] = {{A(0), A(0)}, {A(0), A(0)}, {A(0), A(0)}};
+            if (j < S) {
+                const int k = h * S + j;
+                const double* s64 = seg64 + (size_t)k * kSegStride;
+                const double ta = (double)j / (double)S, tb = (double)(j + 1) / (double)S;
+                Moments<A> m{A(0), A(0), A(0), A(0)};
+                bool done = false;
+                if (s64[6] == 0.0) done = true;                  // degenerate segment: nothing
+                if (!done && Mixed) {
+                    const float* s32 = seg32 + (size_t)k * kSegStride;
+                    const SegGeom<float> gf = load_geom(s32);
+                    if (!near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
+                        const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                        const Moments<float> mf = pair_moments(gf, st);
+                        m = Moments<A>{(A)mf.da, (A)mf.db, (A)mf.sa, (A)mf.sb};
+                        for (int c = 0; c < 3; ++c) {
+                            const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
+                                                                  s32[kWcA + c], s32[kWcB + c]);
+                            va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
+                        }
+                        done = true;
+                    }
+                }
+                if (!done) {
+                    const SegGeom<double> g = load_geom(s64);
+                    const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
+                    const Moments<double> md = pair_moments(g, st);
+                    m = Moments<A>{(A)md.da, (A)md.db, (A)md.sa, (A)md.sb};
+                    for (int c = 0; c < 3; ++c) {
+                        const Grad4<double> gr = pair_backward(g, st, eps2, s64[kWdA + c], s64[kWdB + c], s64[kWcA + c],
+                                                               s64[kWcB + c]);
+                        va[c][0] = (A)gr.ax; va[c][1] = (A)gr.ay; vb[c][0] = (A)gr.bx; vb[c][1] = (A)gr.by;
+                    }
+                }
+                col[0] += m.da * (A)(1.0 - ta) + m.db * (A)(1.0 - tb);
+                col[1] += m.da * (A)ta + m.db * (A)tb;
+                col[2] += m.sa * (A)(1.0 - ta) + m.sb * (A)(1.0 - tb);
+                col[3] += m.sa * (A)ta + m.sb * (A)tb;
+            }
+            double B[4];
+            vertex_weights(model, (double)j / (double)S, B);
+            for (int c = 0; c < 3; ++c) {
+                const A gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
+                for (int q = 0; q < 4; ++q) {
+                    geo[c][2 * q] += (A)B[q] * gx;
+                    geo[c][2 * q + 1] += (A)B[q] * gy;
+                }
+                pv[c][0] = vb[c][0];
+                pv[c][1] = vb[c][1];
+            }
+        }
+        store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
     }
 }
 
@@ -189,7 +203,7 @@ constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] 
 template <class OutT>
 __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
                                                       const float* __restrict__ seg32, int H, int S, int model,
-                                                      float eps2f,
+                                                      int64_t gp, float eps2f,
                                                       float near2, const NearPair* __restrict__ list,
                                                       const int* __restrict__ wave_count,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
@@ -261,7 +275,7 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
             for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
         }
     }
-    store_handle_rows(model, Xt, Xlo, H, h, t, ld, geo, col);
+    store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
 }
 
 // Zero the samples [n, n rounded up to 32) of every row of a blocked split-bfloat16
@@ -403,14 +417,15 @@ __global__ void k_to_f64(const T* __restrict__ in, int64_t n, double* __restrict
 // [g_0 (GH) | g_1 | g_2 | e (CH) | beta (M)]).
 struct Layout {
     int G, C, H;
+    int64_t Gp;     // rows of one channel's geometry block in Xt (G H rounded up to the Gram tile)
     __host__ __device__ int64_t geo() const { return (int64_t)G * H; }
-    __host__ __device__ int64_t handle_rows() const { return (int64_t)(3 * G + C) * H; }
+    __host__ __device__ int64_t handle_rows() const { return 3 * Gp + (int64_t)C * H; }
     __host__ __device__ int compact() const { return (G + C) * H; }
     __host__ __device__ int params() const { return G + 3 * C; }
     // row of Xt of compact index a of channel c ([g_c | e | beta])
     __host__ __device__ int64_t row(int a, int c) const
     {
-        return a < geo() ? (int64_t)c * geo() + a : 2 * geo() + a;
+        return a < geo() ? (int64_t)c * Gp + a : 3 * Gp + (a - geo());
     }
 };
 
@@ -487,11 +502,11 @@ __global__ void k_assemble_jacobian(const double* __restrict__ Xt, int64_t ld, c
     for (int c = 0; c < 3; ++c) {
         double v;
         if (q < L.G) {
-            const int64_t f = (int64_t)c * L.geo() + (int64_t)L.G * h + q;
+            const int64_t f = (int64_t)c * L.Gp + (int64_t)L.G * h + q;
             v = Xt[(size_t)f * ld + t] + BZ[(size_t)t * nf + f];
         } else {
             const int m = (q - L.G) / 3, cc = (q - L.G) % 3;
-            const int64_t f = 3 * L.geo() + (int64_t)L.C * h + m;
+            const int64_t f = 3 * L.Gp + (int64_t)L.C * h + m;
             v = cc == c ? Xt[(size_t)f * ld + t] + BZ[(size_t)t * nf + f] : 0.0;
         }
         J[((size_t)t * 3 + c) * P + p] = v;
@@ -509,7 +524,12 @@ int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s)
     return check_launch(ctx, "fill");
 }
 
-static Layout layout_of(const bem_ctx* ctx, int H) { return Layout{ctx->ngeo, ctx->ncol, H}; }
+constexpr int64_t kGeoAlign = 256;   // the split-BF16 Gram's tile
+static Layout layout_of(const bem_ctx* ctx, int H)
+{
+    const int64_t gh = (int64_t)ctx->ngeo * H;
+    return Layout{ctx->ngeo, ctx->ncol, H, (gh + kGeoAlign - 1) / kGeoAlign * kGeoAlign};
+}
 
 // Feature rows of npts points into Xt (ld: row stride of float64 / float32 tiles,
 // row count of the blocked bfloat16 tile); rows 0..(3G + C)H - 1 handle
@@ -528,7 +548,9 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     const double nf = 2.0 * ctx->opts.near_factor;
     const float near2 = (float)(nf * nf);
-    const int64_t beta_row0 = layout_of(ctx, H).handle_rows();
+    const Layout L = layout_of(ctx, H);
+    const int64_t beta_row0 = L.handle_rows();
+    const int64_t gp = L.Gp;
     const dim3 grid(blocks_for(npts, 256), H);
     if (mixed && (!nl || !xg || !corr || !vtab || (t0 & 63)))
         return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
@@ -543,17 +565,22 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             }
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
-                               H, S, model, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo, ld);
+                               H, S, model, gp, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo,
+                               ld);
             const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
             hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, model, eps2, (float)eps2, near2, nl->flag + t0, Xt,
-                               Xlo, ld);
+                               (const float*)ctx->seg32.ptr, H, S, model, gp, eps2, (float)eps2, near2, nl->flag + t0,
+                               Xt, Xlo, ld);
         } else {
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
-                               (const float*)ctx->seg32.ptr, H, S, model, eps2, (float)eps2, near2,
+                               (const float*)ctx->seg32.ptr, H, S, model, gp, eps2, (float)eps2, near2,
                                (const uint8_t*)nullptr, Xt, Xlo, ld);
         }
+    }
+    if (H > 0 && gp > L.geo()) {
+        const int64_t nz = 3 * (gp - L.geo()) * npts;
+        hipLaunchKernelGGL((k_zero_pad<OutT>), dim3(blocks_for(nz, 256)), dim3(256), 0, s, Xt, Xlo, ld, gp, L.geo(), npts);
     }
     if (with_beta) {
         const dim3 gb(blocks_for(npts, 256), ctx->M);
@@ -603,7 +630,7 @@ static std::vector<int> gram_tiles(const Layout& L, int W, int ts)
     // upper-triangle ts x ts tiles, skipping pairs of tiles that lie inside two
     // different channels' geometry blocks (those products never enter J^T J)
     const int nt = (W + ts - 1) / ts;
-    const int64_t g = L.geo();
+    const int64_t g = L.Gp;
     auto region = [&](int t) {
         const int64_t lo = (int64_t)t * ts, hi = lo + ts - 1;
         if (lo >= 3 * g) return -1;                              // colour coefficients / beta: shared
