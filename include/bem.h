@@ -77,7 +77,13 @@ typedef enum {
  *        near pairs in bem_eval and bem_vjp are accumulated with atomics, so
  *        MIXED results can differ in their last bits from call to call; FP64
  *        results are reproducible.  The boundary system, its solves and the LM
- *        solve are float64 in both modes. */
+ *        solve are float64 in both modes.
+ *        Near pairs go to a list with a per-context capacity per 64 samples
+ *        (1024 at first, at most 16384 and 4 GiB of list); the samples whose
+ *        pairs do not fit are evaluated by a slower sweep that handles their
+ *        near pairs inline, with the same result to rounding.  lm_step raises
+ *        the capacity when its sweeps overflow (a workspace for later calls of
+ *        the context too); the other calls keep the capacity reached. */
 typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
 
 /* Arithmetic of the Gram contraction that forms J^T J and J^T r.
@@ -239,6 +245,8 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * With regularisation terms set (bem_set_regularization) their gradient and
  * Hessian are added to g and H, and their value to L0 and L1 (snapping pairs
  * chosen at theta); state->reg_value and state->snap_pairs report them.
+ * MIXED: if the near-pair list of the sweep at theta overflows, its capacity
+ * is raised and the sweep repeated before the adjoint and the normal equations.
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.
@@ -302,6 +310,10 @@ int bem_get_matrix(bem_ctx* ctx, int32_t which, double* out, hipStream_t stream)
 
 /* Number of outer elements M (host); 0 for a null context. */
 int32_t bem_num_elements(const bem_ctx* ctx);
+
+/* Near-pair list capacity of the MIXED sweeps in slots per 64 samples (the
+ * description of bem_prec says how it grows); 0 for a null context. */
+int32_t bem_near_capacity(const bem_ctx* ctx);
 
 /* Smallest singular value sigma_n and the deflation shift s found by bem_factor (host). */
 int bem_factor_info(const bem_ctx* ctx, double* sigma_n, double* shift);

@@ -75,6 +75,7 @@ _SIGS = {
     "bem_boundary_solve": (ctypes.c_int, [P, P, I32, P, P, P]),
     "bem_get_matrix": (ctypes.c_int, [P, I32, P, P]),
     "bem_num_elements": (I32, [P]),
+    "bem_near_capacity": (I32, [P]),
     "bem_factor_info": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "bem_profile": (ctypes.c_int, [P, I32]),
     "bem_profile_read": (ctypes.c_int, [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
@@ -167,6 +168,11 @@ class Context:
             self._check(L.bem_factor(self._h, st))
         self.M = L.bem_num_elements(self._h)
         self.device = torch.device("cuda", self.opts.device)
+
+    @property
+    def near_capacity(self) -> int:
+        """Near-pair list slots per 64 samples of the mixed sweeps (grown by lm_step)."""
+        return int(lib().bem_near_capacity(self._h))
 
     # -- helpers ---------------------------------------------------------------
     def _check(self, rc):

@@ -421,6 +421,8 @@ int bem_get_matrix(bem_ctx* ctx, int32_t which, double* out, hipStream_t stream)
 
 int32_t bem_num_elements(const bem_ctx* ctx) { return ctx ? ctx->M : 0; }
 
+int32_t bem_near_capacity(const bem_ctx* ctx) { return ctx ? ctx->near_slots : 0; }
+
 int bem_profile(bem_ctx* ctx, int32_t enable)
 {
     if (!ctx) return BEM_EINVAL;

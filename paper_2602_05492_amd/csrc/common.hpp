@@ -89,6 +89,11 @@ struct bem_ctx {
     // tile's feature rows are formed on the caller's stream) and its events, created on first use
     hipStream_t s2 = nullptr;
     hipEvent_t ev[6] = {};
+    // near-pair slots per wavefront of the mixed-precision sweeps (a multiple of 256, raised by
+    // lm_step when a wavefront's near pairs overflow it), and the device word in which the last
+    // mixed forward sweep left its largest overflowing count (0: none overflowed)
+    int near_slots = 1024;
+    int* sweep_need = nullptr;
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;

@@ -196,16 +196,17 @@ constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] 
 
 // Mixed handle features: float32 pairs, near pairs skipped (same predicate as the
 // classification), then the float64 contributions of this sample's listed near pairs
-// with this handle's segments are added.  List entries of a wavefront are sorted by
-// segment, so the handle's entries are found by bisection.  x points at the tile's
-// first sample, whose global index is t0 (a multiple of 64); flagged samples are
-// rewritten afterwards by k_features<true>.
+// with this handle's segments are added.  runs (k_near_runs) gives the range of the
+// handle's entries in the wavefront's slice; the wavefront walks it with uniform
+// (scalar) loads and each lane takes the entries of its own sample.  x points at the
+// tile's first sample, whose global index is t0 (a multiple of 64); flagged samples
+// are rewritten afterwards by k_features<true>.
 template <class OutT>
 __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restrict__ x, int64_t npts, int64_t t0,
                                                       const float* __restrict__ seg32, int H, int S, int model,
                                                       int64_t gp, float eps2f,
-                                                      float near2, const NearPair* __restrict__ list,
-                                                      const int* __restrict__ wave_count,
+                                                      float near2, const NearPair* __restrict__ list, int slots,
+                                                      const int2* __restrict__ runs,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
                                                       const float* __restrict__ vtab, OutT* __restrict__ Xt,
                                                       uint16_t* __restrict__ Xlo, int64_t ld)
@@ -256,26 +257,48 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
         }
     }
     const int64_t i = t0 + t;
-    if (!flag[i]) {
-        const int64_t w = i >> 6;
-        const NearPair* sl = list + w * kWaveSlots;
-        const int cnt = wave_count[w];
-        const int k0 = h * S, k1 = k0 + S;
+    const bool take = !flag[i];
+    // the wavefront's index within the tile (the same for all its lanes, as t0 is a multiple of 64)
+    const int wl = __builtin_amdgcn_readfirstlane((int)(t >> 6));
+    const int2 run = runs[(size_t)wl * H + h];
+    const NearPair* sl = list + ((t0 >> 6) + wl) * (int64_t)slots;
+    const float* cw = corr + (size_t)wl * slots * kFeatVals;
+    for (int e = run.x; e < run.y; ++e) {
+        const NearPair p = sl[e];
+        if (!take || p.sample != (int32_t)i) continue;
+        const float* cr = cw + (size_t)e * kFeatVals;
+        for (int c = 0; c < 3; ++c)
+            for (int q = 0; q < 8; ++q) geo[c][q] += cr[8 * c + q];
+        for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
+    }
+    store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
+}
+
+// Ranges of each handle's entries in the near-pair slices of a tile's wavefronts
+// w0 .. w0 + nw - 1 (entries sorted by segment; element entries come last):
+// runs[(w - w0) H + h] = [first entry with seg >= h S, first entry with seg >= (h + 1) S).
+__global__ void __launch_bounds__(256) k_near_runs(const NearPair* __restrict__ list, int slots,
+                                                   const int* __restrict__ wave_count, int64_t w0, int64_t nw, int H,
+                                                   int S, int2* __restrict__ runs)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nw * H) return;
+    const int64_t w = w0 + t / H;
+    const int h = (int)(t % H);
+    const NearPair* sl = list + w * slots;
+    const int cnt = wave_count[w];
+    int b[2];
+    for (int k = 0; k < 2; ++k) {
+        const int key = (h + k) * S;
         int lo = 0, hi = cnt;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (sl[mid].seg < k0) lo = mid + 1;
+            if (sl[mid].seg < key) lo = mid + 1;
             else hi = mid;
         }
-        for (int e = lo; e < cnt && sl[e].seg < k1; ++e) {
-            if (sl[e].sample != (int32_t)i) continue;
-            const float* cr = corr + ((size_t)(w - (t0 >> 6)) * kWaveSlots + e) * kFeatVals;
-            for (int c = 0; c < 3; ++c)
-                for (int q = 0; q < 8; ++q) geo[c][q] += cr[8 * c + q];
-            for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
-        }
+        b[k] = lo;
     }
-    store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
+    runs[t] = make_int2(b[0], b[1]);
 }
 
 // Zero the samples [n, n rounded up to 32) of every row of a blocked split-bfloat16
@@ -310,7 +333,7 @@ __global__ void k_vertex_table(int S, int model, float* __restrict__ vtab)
 // (wavefronts w0 .. w0 + nw - 1) to one handle's features: thread per list slot,
 // corr[slot][28] = geo[3][8] and col[4] as in store_handle_rows (geometry already
 // chained with the vertex weights).
-__global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list,
+__global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list, int slots,
                                                        const int* __restrict__ wave_count,
                                                        const uint8_t* __restrict__ flag, int64_t w0, int64_t nw,
                                                        const double* __restrict__ x, const double* __restrict__ seg64,
@@ -318,11 +341,11 @@ __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restric
                                                        float* __restrict__ corr)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nw * kWaveSlots) return;
-    const int64_t w = w0 + t / kWaveSlots;
-    const int e = (int)(t % kWaveSlots);
+    if (t >= nw * slots) return;
+    const int64_t w = w0 + t / slots;
+    const int e = (int)(t % slots);
     if (e >= wave_count[w]) return;
-    const NearPair p = list[w * kWaveSlots + e];
+    const NearPair p = list[w * slots + e];
     if (p.seg >= K || flag[p.sample]) return;
     const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
     const double* s64 = seg64 + (size_t)p.seg * kSegStride;
@@ -536,11 +559,13 @@ static Layout layout_of(const bem_ctx* ctx, int H)
 // features, the next M rows beta when with_beta.  OutT: double, float or uint16_t (bf16 hi, lo in Xlo).
 // Mixed precision needs the near-pair list of the whole sample set (nl), the tile's
 // first global sample index t0 (a multiple of 64), the global samples xg and a
-// correction buffer of ceil(npts / 64) * kWaveSlots * 28 floats.
+// correction buffer of ceil(npts / 64) * nl->slots * 28 floats and a run table of
+// ceil(npts / 64) * H entries.
 template <class OutT>
 static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
                            uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
-                           const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr)
+                           const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr,
+                           int2* runs = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -552,21 +577,23 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const int64_t beta_row0 = L.handle_rows();
     const int64_t gp = L.Gp;
     const dim3 grid(blocks_for(npts, 256), H);
-    if (mixed && (!nl || !xg || !corr || !vtab || (t0 & 63)))
+    if (mixed && (!nl || !xg || !corr || !vtab || !runs || (t0 & 63)))
         return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
     if (H > 0) {
         if (mixed) {
             const int64_t nw = (npts + 63) / 64;
             {
                 ProfScope ps_(ctx, PT_NEAR, s);
-                hipLaunchKernelGGL(k_features_near, dim3(blocks_for(nw * kWaveSlots, 256)), dim3(256), 0, s, nl->list,
-                                   nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, model,
+                hipLaunchKernelGGL(k_features_near, dim3(blocks_for(nw * nl->slots, 256)), dim3(256), 0, s, nl->list,
+                                   nl->slots, nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, model,
                                    eps2, corr);
+                hipLaunchKernelGGL(k_near_runs, dim3(blocks_for(nw * H, 256)), dim3(256), 0, s, nl->list, nl->slots,
+                                   nl->count, t0 >> 6, nw, H, S, runs);
             }
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
-                               H, S, model, gp, (float)eps2, near2, nl->list, nl->count, nl->flag, corr, vtab, Xt, Xlo,
-                               ld);
+                               H, S, model, gp, (float)eps2, near2, nl->list, nl->slots, (const int2*)runs, nl->flag, corr,
+                               vtab, Xt, Xlo, ld);
             const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
             hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, H, S, model, gp, eps2, (float)eps2, near2, nl->flag + t0,
@@ -749,20 +776,22 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(L, (int)W, ts)
                                                          : gram_work(gram_tiles(L, (int)W, ts), parts);
     const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
-    // tmp5: tile list, the vertex table, then the near-pair corrections of one sample tile
+    // tmp5: tile list, the vertex table, then the near-pair corrections and run table of one sample tile
     const int S = ctx->opts.segs_per_handle;
     const size_t tiles_bytes = (tiles.size() * sizeof(int) + 255) / 256 * 256;
     const size_t vtab_bytes = ((size_t)(S + 1) * 8 * sizeof(float) + 255) / 256 * 256;
-    const size_t corr_floats = mixed ? (size_t)((T + 63) / 64) * kWaveSlots * kFeatVals : 0;
-    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + vtab_bytes + corr_floats * sizeof(float) + 256, s))) return rc;
-    float* vtab = (float*)((char*)ctx->tmp5.ptr + tiles_bytes);
-    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes) : nullptr;
-    hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
     NearList nl{};
     if (mixed && N > 0) {
         if (pre) nl = *pre;
         else if ((rc = near_classify(ctx, ctx->nearf, x, N, H * ctx->opts.segs_per_handle, 0, &nl, s))) return rc;
     }
+    const size_t corr_bytes = mixed ? ((size_t)((T + 63) / 64) * nl.slots * kFeatVals * sizeof(float) + 255) / 256 * 256 : 0;
+    const size_t runs_bytes = mixed ? (size_t)((T + 63) / 64) * H * sizeof(int2) : 0;
+    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + vtab_bytes + corr_bytes + runs_bytes + 256, s))) return rc;
+    float* vtab = (float*)((char*)ctx->tmp5.ptr + tiles_bytes);
+    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes) : nullptr;
+    int2* runs = mixed ? (int2*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes + corr_bytes) : nullptr;
+    hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
     if (hipMemcpyAsync(ctx->tmp5.ptr, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "tile list upload");
     // the tile list is read by every tile's Gram; keep the host copy alive until queued work is done
@@ -784,7 +813,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             return set_error(ctx, BEM_EHIP, "stream wait");
         if (gram == BEM_GRAM_FP64) {
             double* Xt = (double*)tile;
-            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
+            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
@@ -795,7 +824,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)tile;
-            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab))) return rc;
+            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
             if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, sg)))
@@ -805,7 +834,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             uint16_t* Xh = (uint16_t*)tile;
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
-            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab))) return rc;
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab, runs))) return rc;
             if (n & 31)
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))

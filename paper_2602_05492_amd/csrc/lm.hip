@@ -250,6 +250,24 @@ static int row_sums(bem_ctx* ctx, const void* u, bool f32, const double* T, int6
     return BEM_OK;
 }
 
+// After a mixed sweep whose work the stream has finished: if a wavefront's near pairs overflowed
+// the list (slots per wavefront), raise the context's capacity to hold them (*grown: it rose
+// above slots).
+static int raise_near_slots(bem_ctx* ctx, const int* dneed, int64_t nwaves, int slots, hipStream_t s, bool* grown)
+{
+    *grown = false;
+    if (!dneed) return BEM_OK;
+    int need = 0;
+    if (hipMemcpyAsync(&need, dneed, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(ctx, BEM_EHIP, "near-pair count readback");
+    if (need <= slots) return BEM_OK;
+    const int want = near_slots_for(need, nwaves);
+    if (want > ctx->near_slots) ctx->near_slots = want;
+    *grown = want > slots;
+    return BEM_OK;
+}
+
 int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,
                 int gram, bool mixed, hipStream_t s)
 {
@@ -295,15 +313,23 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         for (int c = 0; c < 3; ++c) st->cbar[c] = N > 0 ? sums[c] / (double)N : 0.0;
     }
     // residual and loss at theta; the mixed sweep's near-pair list serves the adjoint and the
-    // normal equations below (same samples, same parameters)
+    // normal equations below (same samples, same parameters).  Should the list overflow, its
+    // capacity is raised and the sweep repeated, so that they find every near pair in it.
     NearList nl{};
     if (mixed) {
         if ((rc = prepare_forward(ctx, theta, H, s))) return rc;
-        if ((rc = launch_sweep_mixed(ctx, x, N, H * ctx->opts.segs_per_handle, st->cbar, (float*)u, s, &nl))) return rc;
-    } else if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) {
-        return rc;
+        for (int pass = 0;; ++pass) {
+            if ((rc = launch_sweep_mixed(ctx, x, N, H * ctx->opts.segs_per_handle, st->cbar, (float*)u, s, &nl)))
+                return rc;
+            if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
+            bool grown = false;
+            if (pass == 0 && (rc = raise_near_slots(ctx, nl.need, nl.nwaves, nl.slots, s, &grown))) return rc;
+            if (!grown) break;
+        }
+    } else {
+        if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) return rc;
+        if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
     }
-    if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
     const double L0 = N > 0 ? 0.5 * sums[0] / (double)N : 0.0;
     st->loss_before = L0;
     st->loss_after = L0;
@@ -373,9 +399,15 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         if (hipMemcpyAsync(&st->compat_violation, cviol, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
             return set_error(ctx, BEM_EHIP, "violation readback");
     }
-    // trial loss on the same samples and mean colour
+    // trial loss on the same samples and mean colour (an overflow of its near-pair list raises the
+    // capacity for later calls)
     if ((rc = bem_eval(ctx, th1, H, x, N, st->cbar, u, prec, s))) return rc;
     if ((rc = row_sums(ctx, u, mixed, T, N, 0, nullptr, sums, dpart, s))) return rc;
+    if (mixed) {
+        bool grown = false;
+        const int64_t nw = (int64_t)blocks_for(N, 256) * 4;
+        if ((rc = raise_near_slots(ctx, ctx->sweep_need, nw, near_slots_for(ctx->near_slots, nw), s, &grown))) return rc;
+    }
     int hflag = 0;
     if (hipMemcpy(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "flag readback");

@@ -63,19 +63,35 @@ struct NearPair {
     int32_t seg;      // < K: handle segment, else outer element seg - K
 };
 
-// Each wavefront of 64 consecutive samples owns kWaveSlots list slots; entries
-// are appended in increasing segment order, so the entries of one handle form a
-// contiguous run of a slice.
-constexpr int kNearPerSample = 16;
-constexpr int kWaveSlots = kNearPerSample * 64;
+// Each wavefront of 64 consecutive samples owns a slice of `slots` list slots (a
+// multiple of 256; the context's capacity, bem_ctx::near_slots); entries are
+// appended in increasing segment order, so the entries of one handle form a
+// contiguous run of a slice.  A wavefront whose near pairs do not fit records its
+// count in *need (atomic maximum), from which lm_step raises the capacity.
+constexpr int kWaveSlotsMin = 16 * 64;
+constexpr int kWaveSlotsMax = 256 * 64;
+constexpr size_t kNearListMaxBytes = (size_t)1 << 32;
 
 // Workspace of one classification: slices, per-wavefront counts, per-sample
-// overflow flags.
+// overflow flags, the largest overflowing count.
 struct NearList {
     NearPair* list = nullptr;
     int* count = nullptr;
     uint8_t* flag = nullptr;
+    int* need = nullptr;
     int64_t nwaves = 0;
+    int slots = kWaveSlotsMin;
 };
+
+// Capacity for wavefronts of `need` near pairs over nwaves wavefronts: need rounded up to
+// 256, within [kWaveSlotsMin, kWaveSlotsMax] and a list of at most kNearListMaxBytes.
+inline int near_slots_for(int need, int64_t nwaves)
+{
+    int64_t cap = nwaves > 0 ? (int64_t)(kNearListMaxBytes / ((size_t)nwaves * sizeof(NearPair))) : kWaveSlotsMax;
+    cap = cap < kWaveSlotsMax ? cap & ~(int64_t)255 : kWaveSlotsMax;
+    if (cap < kWaveSlotsMin) cap = kWaveSlotsMin;
+    const int64_t want = ((int64_t)need + 255) / 256 * 256;
+    return (int)(want < cap ? (want > kWaveSlotsMin ? want : kWaveSlotsMin) : cap);
+}
 
 }  // namespace bem

@@ -22,15 +22,15 @@ namespace {
 // Appending needs no atomics: each wavefront owns a slice and counts its entries
 // in a wave-uniform register.
 
-__device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearPair* __restrict__ slice, int& used,
-                                   bool& overflow)
+__device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearPair* __restrict__ slice, int slots,
+                                   int& used, bool& overflow)
 {
     const uint64_t mask = __ballot(near);
     if (mask == 0) return;
     const int lane = threadIdx.x & 63;
     if (near) {
         const int slot = used + __popcll(mask & ((1ull << lane) - 1ull));
-        if (slot < kWaveSlots) slice[slot] = NearPair{sample, seg};
+        if (slot < slots) slice[slot] = NearPair{sample, seg};
         else overflow = true;
     }
     used += __popcll(mask);
@@ -41,12 +41,13 @@ __device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearP
 __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x, int64_t N,
                                                    const float* __restrict__ seg32, int K,
                                                    const float* __restrict__ el32, int M, float eps2f, float near2,
-                                                   float* __restrict__ u, NearPair* __restrict__ list,
-                                                   int* __restrict__ wave_count, uint8_t* __restrict__ flag)
+                                                   float* __restrict__ u, NearPair* __restrict__ list, int slots,
+                                                   int* __restrict__ wave_count, uint8_t* __restrict__ flag,
+                                                   int* __restrict__ need)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t wave = i >> 6;
-    NearPair* slice = list + wave * kWaveSlots;
+    NearPair* slice = list + wave * slots;
     const bool live = i < N;                       // the tail wave keeps its idle lanes for the ballots
     const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
@@ -59,7 +60,7 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
 #pragma unroll
         for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
         const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
-        append_near(near, (int32_t)i, k, slice, used, overflow);
+        append_near(near, (int32_t)i, k, slice, slots, used, overflow);
         const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
         const float on = near ? 0.0f : 1.0f;
         f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
@@ -70,11 +71,14 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
     for (int j = 0; j < M; ++j) {
         const float* e = el32 + (size_t)j * kElemStride;
         const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
-        append_near(near, (int32_t)i, K + j, slice, used, overflow);
+        append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
         const float beta = near ? 0.0f : element_beta<float, DevF32>(e[0], e[1], e[2], e[3], Xf, Yf);
         b0 += beta * e[4]; b1 += beta * e[5]; b2 += beta * e[6];
     }
-    if ((threadIdx.x & 63) == 0) wave_count[wave] = used < kWaveSlots ? used : kWaveSlots;
+    if ((threadIdx.x & 63) == 0) {
+        wave_count[wave] = used < slots ? used : slots;
+        if (used > slots) atomicMax(need, used);
+    }
     if (!live) return;
     u[3 * i + 0] = b0 + f0;
     u[3 * i + 1] = b1 + f1;
@@ -87,12 +91,12 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
 __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, int64_t N,
                                                   const float* __restrict__ seg32, int K,
                                                   const float* __restrict__ el32, int M, float near2,
-                                                  NearPair* __restrict__ list, int* __restrict__ wave_count,
-                                                  uint8_t* __restrict__ flag)
+                                                  NearPair* __restrict__ list, int slots, int* __restrict__ wave_count,
+                                                  uint8_t* __restrict__ flag, int* __restrict__ need)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t wave = i >> 6;
-    NearPair* slice = list + wave * kWaveSlots;
+    NearPair* slice = list + wave * slots;
     const bool live = i < N;
     const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
     bool overflow = false;
@@ -100,27 +104,30 @@ __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, 
     for (int k = 0; k < K; ++k) {
         const float* s = seg32 + (size_t)k * kSegStride;
         const bool near = live & near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2);
-        append_near(near, (int32_t)i, k, slice, used, overflow);
+        append_near(near, (int32_t)i, k, slice, slots, used, overflow);
     }
     for (int j = 0; j < M; ++j) {
         const float* e = el32 + (size_t)j * kElemStride;
         const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
-        append_near(near, (int32_t)i, K + j, slice, used, overflow);
+        append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
     }
-    if ((threadIdx.x & 63) == 0) wave_count[wave] = used < kWaveSlots ? used : kWaveSlots;
+    if ((threadIdx.x & 63) == 0) {
+        wave_count[wave] = used < slots ? used : slots;
+        if (used > slots) atomicMax(need, used);
+    }
     if (live) flag[i] = overflow ? 1 : 0;
 }
 
 // Listed near pairs in float64, added into acc[3 * sample + c]; thread per slot.
 __global__ void __launch_bounds__(256) k_near_pairs(const NearPair* __restrict__ list,
-                                                    const int* __restrict__ wave_count, int64_t nslots,
+                                                    const int* __restrict__ wave_count, int slots, int64_t nslots,
                                                     const double* __restrict__ x, const double* __restrict__ seg64,
                                                     int K, const double* __restrict__ el64, double eps2,
                                                     double* __restrict__ acc)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nslots) return;
-    if ((int)(t % kWaveSlots) >= wave_count[t / kWaveSlots]) return;
+    if ((int)(t % slots) >= wave_count[t / slots]) return;
     const NearPair p = list[t];
     const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
     double v0, v1, v2;
@@ -209,18 +216,24 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     int rc;
     const double nf = 2.0 * ctx->opts.near_factor;
     const int64_t nwaves = N > 0 ? (int64_t)blocks_for(N, 256) * 4 : 0;
-    const size_t list_bytes = ((size_t)nwaves * kWaveSlots * sizeof(NearPair) + 255) / 256 * 256;
+    const int slots = near_slots_for(ctx->near_slots, nwaves);
+    // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N]
+    const size_t list_bytes = ((size_t)nwaves * slots * sizeof(NearPair) + 255) / 256 * 256;
     const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
-    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + (size_t)N + 256, s))) return rc;
+    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + 256 + (size_t)N + 256, s))) return rc;
     char* base = (char*)buf.ptr;
     out->list = (NearPair*)base;
     out->count = (int*)(base + list_bytes);
-    out->flag = (uint8_t*)(base + list_bytes + cnt_bytes);
+    out->need = (int*)(base + list_bytes + cnt_bytes);
+    out->flag = (uint8_t*)(base + list_bytes + cnt_bytes + 256);
     out->nwaves = nwaves;
+    out->slots = slots;
+    if ((rc = fill_i32(ctx, out->need, 1, 0, s))) return rc;
     if (N == 0) return BEM_OK;
     ProfScope ps_(ctx, PT_NEAR, s);
     hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, K,
-                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), out->list, out->count, out->flag);
+                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), out->list, slots, out->count, out->flag,
+                       out->need);
     return check_launch(ctx, "classify");
 }
 
@@ -228,6 +241,7 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
                        NearList* out)
 {
     if (out) *out = NearList{};
+    ctx->sweep_need = nullptr;
     if (N == 0) return BEM_OK;
     int rc;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
@@ -235,27 +249,33 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     const float near2 = (float)(nf * nf);
     // per-wavefront near-pair slices, their counts, float64 sums, overflow flags
     const int64_t nwaves = (int64_t)blocks_for(N, 256) * 4;     // every launched wavefront, idle tail ones too
-    const int64_t nslots = nwaves * kWaveSlots;
+    const int slots = near_slots_for(ctx->near_slots, nwaves);
+    const int64_t nslots = nwaves * slots;
+    // list [nwaves][slots] | float64 sums [N][3] | counts [nwaves] | overflow count (256 bytes) | flags [N]
     const size_t list_bytes = (size_t)nslots * sizeof(NearPair);
     const size_t acc_bytes = (size_t)N * 3 * sizeof(double);
     const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
-    if ((rc = ensure(ctx, ctx->nearw, list_bytes + acc_bytes + cnt_bytes + (size_t)N + 256, s))) return rc;
+    if ((rc = ensure(ctx, ctx->nearw, list_bytes + acc_bytes + cnt_bytes + 256 + (size_t)N + 256, s))) return rc;
     char* base = (char*)ctx->nearw.ptr;
     NearPair* list = (NearPair*)base;
     double* acc = (double*)(base + list_bytes);
     int* wave_count = (int*)(base + list_bytes + acc_bytes);
-    uint8_t* flag = (uint8_t*)(base + list_bytes + acc_bytes + cnt_bytes);
+    int* need = (int*)(base + list_bytes + acc_bytes + cnt_bytes);
+    uint8_t* flag = (uint8_t*)(base + list_bytes + acc_bytes + cnt_bytes + 256);
+    ctx->sweep_need = need;
     if ((rc = fill_f64(ctx, acc, 3 * N, 0.0, s))) return rc;
-    if (out) *out = NearList{list, wave_count, flag, nwaves};
+    if ((rc = fill_i32(ctx, need, 1, 0, s))) return rc;
+    if (out) *out = NearList{list, wave_count, flag, need, nwaves, slots};
     {
         ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
         hipLaunchKernelGGL(k_sweep_far, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
-                           K, (const float*)ctx->elem32.ptr, ctx->M, (float)eps2, near2, u, list, wave_count, flag);
+                           K, (const float*)ctx->elem32.ptr, ctx->M, (float)eps2, near2, u, list, slots, wave_count,
+                           flag, need);
     }
     {
         ProfScope ps_(ctx, PT_NEAR, s);
-        hipLaunchKernelGGL(k_near_pairs, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, list, wave_count, nslots, x,
-                           (const double*)ctx->seg64.ptr, K, (const double*)ctx->elem64.ptr, eps2, acc);
+        hipLaunchKernelGGL(k_near_pairs, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, list, wave_count, slots, nslots,
+                           x, (const double*)ctx->seg64.ptr, K, (const double*)ctx->elem64.ptr, eps2, acc);
     }
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(N, 256)), dim3(256), 0, s, u, acc, N, cbar[0], cbar[1], cbar[2]);
     hipLaunchKernelGGL(k_sweep_inline, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, flag,

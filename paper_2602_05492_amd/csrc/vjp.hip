@@ -204,7 +204,8 @@ __device__ inline void near_element_adjoint(const double* __restrict__ e, double
 // one lane per segment adds the sums (atomics into one extra partial row of each
 // fixed-order reduction).  Pairs of flagged samples are left to k_vjp_flagged,
 // which redoes all near pairs of such a sample.
-__global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ list, const int* __restrict__ wave_count,
+__global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ list, int slots,
+                                                  const int* __restrict__ wave_count,
                                                   const uint8_t* __restrict__ flag, int64_t nslots,
                                                   const double* __restrict__ x, const float* __restrict__ gbar,
                                                   const double* __restrict__ seg64, int K,
@@ -212,8 +213,8 @@ __global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ l
                                                   double* __restrict__ segsum, double* __restrict__ psisum)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // nslots is a multiple of the block size
-    const int e = (int)(t % kWaveSlots);
-    const int cnt = wave_count[t / kWaveSlots];
+    const int e = (int)(t % slots);
+    const int cnt = wave_count[t / slots];
     if ((e & ~63) >= cnt) return;                     // the whole wavefront lies past the slice's entries
     const int lane = threadIdx.x & 63;
     constexpr int kNone = 0x7fffffff;                 // key of an empty slot: after every entry
@@ -432,8 +433,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             }
             {
                 ProfScope ps_(ctx, PT_NEAR, s);
-                const int64_t nslots = nl.nwaves * kWaveSlots;
-                hipLaunchKernelGGL(k_vjp_near, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nl.list, nl.count,
+                const int64_t nslots = nl.nwaves * nl.slots;
+                hipLaunchKernelGGL(k_vjp_near, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nl.list, nl.slots, nl.count,
                                    nl.flag, nslots, x, (const float*)gbar, seg64, K, el64, eps2, segnear, psinear);
                 hipLaunchKernelGGL(k_vjp_flagged, dim3(blocks_for(N, 256)), dim3(256), 0, s, nl.flag, N, x,
                                    (const float*)gbar, seg32, seg64, K, el32, el64, M, eps2, near2, segnear, psinear);

@@ -59,6 +59,7 @@ def test_null_arguments():
     cb = (ctypes.c_double * 3)(0, 0, 0)
     assert L.bem_eval(None, None, 0, None, 0, cb, None, 0, None) == -1
     assert L.bem_num_elements(None) == 0
+    assert L.bem_near_capacity(None) == 0
     assert L.bem_set_regularization(None, None) == -1
     v, k = ctypes.c_double(), ctypes.c_int32()
     assert L.bem_regularization(None, None, 0, ctypes.byref(v), None, None, None, None) == -1
