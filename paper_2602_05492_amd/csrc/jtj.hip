@@ -595,7 +595,8 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
                                H, S, model, gp, (float)eps2, near2, nl->list, nl->slots, (const int2*)runs, nl->flag, corr,
                                vtab, Xt, Xlo, ld);
             const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
-            hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
+            if (nl->overflowed)
+                hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, H, S, model, gp, eps2, (float)eps2, near2, nl->flag + t0,
                                Xt, Xlo, ld);
         } else {
@@ -748,8 +749,13 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
     // MFMA Grams with several sample tiles: the Gram of tile t runs on a second stream while tile t+1's
     // feature rows are formed on the caller's stream (two tile buffers), so the VALU-bound feature
-    // kernels and the MFMA-bound Gram share the chip
-    const bool overlap = gram != BEM_GRAM_FP64 && N > T;
+    // kernels and the MFMA-bound Gram share the chip.  Sharing slows a Gram launch by about a third
+    // and short launches beside it several-fold (measured), so it pays only when the feature work
+    // (handle segment pairs per sample, H S) is a sizeable share of the Gram's (its distinct output
+    // area): from about a third of the Gram's time, H S >= area / 8000.
+    const int64_t gram_area = (int64_t)(gram_tiles(L, (int)W, 256).size() / 2) * 256 * 256;
+    const bool overlap = gram != BEM_GRAM_FP64 && N > T &&
+                         (int64_t)H * ctx->opts.segs_per_handle * 8000 >= gram_area;
     const size_t tile_bytes = ((size_t)W * T * elem + 255) / 256 * 256;
     hipStream_t sg = s;
     if (overlap && (rc = aux_stream(ctx, &sg))) return rc;

@@ -250,22 +250,25 @@ static int row_sums(bem_ctx* ctx, const void* u, bool f32, const double* T, int6
     return BEM_OK;
 }
 
-// After a mixed sweep whose work the stream has finished: if a wavefront's near pairs overflowed
-// the list (slots per wavefront), raise the context's capacity to hold them (*grown: it rose
-// above slots).
-static int raise_near_slots(bem_ctx* ctx, const int* dneed, int64_t nwaves, int slots, hipStream_t s, bool* grown)
+// Largest overflowing near-pair count of a wavefront in a mixed sweep (0: no slice overflowed).
+static int read_need(bem_ctx* ctx, const int* dneed, hipStream_t s, int* need)
 {
-    *grown = false;
+    *need = 0;
     if (!dneed) return BEM_OK;
-    int need = 0;
-    if (hipMemcpyAsync(&need, dneed, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (hipMemcpyAsync(need, dneed, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "near-pair count readback");
-    if (need <= slots) return BEM_OK;
+    return BEM_OK;
+}
+
+// Raise the context's near-pair capacity to hold wavefronts of `need` pairs; true if that is
+// more than the slots per wavefront of the list that overflowed.
+static bool raise_near_slots(bem_ctx* ctx, int need, int64_t nwaves, int slots)
+{
+    if (need <= slots) return false;
     const int want = near_slots_for(need, nwaves);
     if (want > ctx->near_slots) ctx->near_slots = want;
-    *grown = want > slots;
-    return BEM_OK;
+    return want > slots;
 }
 
 int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,
@@ -322,9 +325,10 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
             if ((rc = launch_sweep_mixed(ctx, x, N, H * ctx->opts.segs_per_handle, st->cbar, (float*)u, s, &nl)))
                 return rc;
             if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
-            bool grown = false;
-            if (pass == 0 && (rc = raise_near_slots(ctx, nl.need, nl.nwaves, nl.slots, s, &grown))) return rc;
-            if (!grown) break;
+            int need = 0;
+            if ((rc = read_need(ctx, nl.need, s, &need))) return rc;
+            nl.overflowed = need > 0;        // without overflow the flagged-sample kernels are skipped
+            if (pass > 0 || !raise_near_slots(ctx, need, nl.nwaves, nl.slots)) break;
         }
     } else {
         if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) return rc;
@@ -404,9 +408,10 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     if ((rc = bem_eval(ctx, th1, H, x, N, st->cbar, u, prec, s))) return rc;
     if ((rc = row_sums(ctx, u, mixed, T, N, 0, nullptr, sums, dpart, s))) return rc;
     if (mixed) {
-        bool grown = false;
+        int need = 0;
         const int64_t nw = (int64_t)blocks_for(N, 256) * 4;
-        if ((rc = raise_near_slots(ctx, ctx->sweep_need, nw, near_slots_for(ctx->near_slots, nw), s, &grown))) return rc;
+        if ((rc = read_need(ctx, ctx->sweep_need, s, &need))) return rc;
+        raise_near_slots(ctx, need, nw, near_slots_for(ctx->near_slots, nw));
     }
     int hflag = 0;
     if (hipMemcpy(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)

@@ -81,6 +81,7 @@ struct NearList {
     int* need = nullptr;
     int64_t nwaves = 0;
     int slots = kWaveSlotsMin;
+    bool overflowed = true;     // false only once a readback of *need has shown that no slice overflowed
 };
 
 // Capacity for wavefronts of `need` near pairs over nwaves wavefronts: need rounded up to

@@ -265,7 +265,7 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     ctx->sweep_need = need;
     if ((rc = fill_f64(ctx, acc, 3 * N, 0.0, s))) return rc;
     if ((rc = fill_i32(ctx, need, 1, 0, s))) return rc;
-    if (out) *out = NearList{list, wave_count, flag, need, nwaves, slots};
+    if (out) *out = NearList{list, wave_count, flag, need, nwaves, slots, true};
     {
         ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
         hipLaunchKernelGGL(k_sweep_far, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,

@@ -436,7 +436,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 const int64_t nslots = nl.nwaves * nl.slots;
                 hipLaunchKernelGGL(k_vjp_near, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nl.list, nl.slots, nl.count,
                                    nl.flag, nslots, x, (const float*)gbar, seg64, K, el64, eps2, segnear, psinear);
-                hipLaunchKernelGGL(k_vjp_flagged, dim3(blocks_for(N, 256)), dim3(256), 0, s, nl.flag, N, x,
+                if (nl.overflowed)
+                    hipLaunchKernelGGL(k_vjp_flagged, dim3(blocks_for(N, 256)), dim3(256), 0, s, nl.flag, N, x,
                                    (const float*)gbar, seg32, seg64, K, el32, el64, M, eps2, near2, segnear, psinear);
             }
         }
