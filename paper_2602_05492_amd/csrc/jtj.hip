@@ -371,30 +371,35 @@ __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restric
     o[27] = (float)(m.sa * ta + m.sb * tb);
 }
 
-// beta rows: Xt[row0 + j][t] = beta_j(x_t); thread per (point, element).
+// beta rows: Xt[row0 + j][t] = beta_j(x_t); thread per point, each block row of the grid a
+// run of kBetaRun elements (element data by uniform loads), so that a launch has few, long
+// blocks rather than one short block per element.
+constexpr int kBetaRun = 32;
 template <bool Mixed, class OutT>
 __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x, int64_t npts,
                                                    const double* __restrict__ el64, const float* __restrict__ el32,
-                                                   float near2, OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo,
+                                                   int M, float near2, OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo,
                                                    int64_t ld, int64_t row0)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
     if (t >= npts) return;
     const double X = x[2 * t], Y = x[2 * t + 1];
-    const double* e = el64 + (size_t)j * kElemStride;
-    double b;
-    if (Mixed) {
-        const float* f = el32 + (size_t)j * kElemStride;
-        const float Xf = (float)X, Yf = (float)Y;
-        if (near_element(f[0], f[1], f[2], f[3], Xf, Yf, near2))
+    const float Xf = (float)X, Yf = (float)Y;
+    const int j0 = blockIdx.y * kBetaRun, j1 = j0 + kBetaRun < M ? j0 + kBetaRun : M;
+    for (int j = j0; j < j1; ++j) {
+        const double* e = el64 + (size_t)j * kElemStride;
+        double b;
+        if (Mixed) {
+            const float* f = el32 + (size_t)j * kElemStride;
+            if (near_element(f[0], f[1], f[2], f[3], Xf, Yf, near2))
+                b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+            else
+                b = (double)element_beta<float, DevF32>(f[0], f[1], f[2], f[3], Xf, Yf);
+        } else {
             b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
-        else
-            b = (double)element_beta<float, DevF32>(f[0], f[1], f[2], f[3], Xf, Yf);
-    } else {
-        b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+        }
+        Store<OutT>::put(Xt, Xlo, row0 + j, t, ld, b);
     }
-    Store<OutT>::put(Xt, Xlo, row0 + j, t, ld, b);
 }
 
 __global__ void k_gauss_points(int M, const double* __restrict__ eg, double* __restrict__ gx)
@@ -611,18 +616,18 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
         hipLaunchKernelGGL((k_zero_pad<OutT>), dim3(blocks_for(nz, 256)), dim3(256), 0, s, Xt, Xlo, ld, gp, L.geo(), npts);
     }
     if (with_beta) {
-        const dim3 gb(blocks_for(npts, 256), ctx->M);
+        const dim3 gb(blocks_for(npts, 256), blocks_for(ctx->M, kBetaRun));
         if (mixed)
             {
                 ProfScope ps_(ctx, PT_BETA_ROWS, s);
                 hipLaunchKernelGGL((k_beta_rows<true, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, beta_row0);
+                                   (const float*)ctx->elem32.ptr, ctx->M, near2, Xt, Xlo, ld, beta_row0);
             }
         else
             {
                 ProfScope ps_(ctx, PT_BETA_ROWS, s);
                 hipLaunchKernelGGL((k_beta_rows<false, OutT>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                                   (const float*)ctx->elem32.ptr, near2, Xt, Xlo, ld, beta_row0);
+                                   (const float*)ctx->elem32.ptr, ctx->M, near2, Xt, Xlo, ld, beta_row0);
             }
     }
     return check_launch(ctx, "features");
@@ -742,6 +747,16 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     T = (T + 63) / 64 * 64;
     if (gram == BEM_GRAM_BF16X3_MFMA)
         while (T > 64 && W * T >= ((int64_t)1 << 31)) T = (T / 2 + 63) / 64 * 64;   // 32-bit offsets in the Gram
+    // default tile size: a short last tile (at most a quarter of a tile) is spread over the others,
+    // since it would cost a Gram launch of its own (the launch's partial-Gram traffic does not
+    // shrink with the samples)
+    if (ctx->opts.tile_rows <= 0 && N > T) {
+        const int64_t nt = N / T, tail = N - nt * T;
+        const int64_t T2 = ((N + nt - 1) / nt + 63) / 64 * 64;
+        if (tail > 0 && tail <= T / 4 && (size_t)W * T2 * elem <= ((size_t)3 << 30) &&
+            (gram != BEM_GRAM_BF16X3_MFMA || W * T2 < ((int64_t)1 << 31)))
+            T = T2;
+    }
     // split-BF16 Gram: the sample tile is split into 3 parts with partial Grams of their own,
     // so that a launch has 3x the blocks (fewer idle CUs in its last round) and stays
     // deterministic (no atomics)
