@@ -50,62 +50,148 @@ __device__ inline double readlane_f64(double v, int lane)
 }
 
 // Factor the diagonal block kb in place (lower triangle) and write its inverse to
-// Linv [64][64] (row-major).  One wavefront, lane i holds row i in registers; column j's
-// pivot and entries come from the owning lanes by readlane (the loops are unrolled, so
-// every lane index is a constant).  Then L goes to LDS (its diagonal as reciprocals) and
-// lane j solves L x = e_j for column j of the inverse by forward substitution, x in LDS
-// column j (L read by broadcast).  Rows / columns past the matrix are an identity block.
-__global__ void __launch_bounds__(64) k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag,
-                                                   double* __restrict__ Linv)
+// Linv [64][64] (row-major).  256 threads, the block in LDS, factored by 16-column
+// sub-blocks p = 0..3: wavefront 0 factors the 16 x 16 diagonal sub-block in registers
+// (lane i < 16 holds row i; pivot and column entries by readlane, loops unrolled so every
+// lane index is a constant; a reciprocal square root per pivot, no divisions) and inverts it (lane j forms column j by forward
+// substitution); all threads then form the sub-panel below it (rows times the
+// sub-block's inverse transposed) and apply the rank-16 update to the trailing lower
+// triangle.  The inverse of the whole block follows by block rows:
+// X_ij = -D_i^{-1} sum_{k=j}^{i-1} L_ik X_kj for j < i, X_ii = D_i^{-1}.  Rows / columns
+// past the matrix are an identity block.
+constexpr int DB = 16;                  // sub-block of the diagonal-block factorization
+__global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int64_t P, int kb, int* __restrict__ flag,
+                                                    double* __restrict__ Linv)
 {
-    __shared__ double Ls[NB][NB];
-    __shared__ double Xs[NB][NB];
+    __shared__ double S[NB][NB + 1];    // the block, factored in place (lower triangle)
+    __shared__ double X[NB][NB + 1];    // its inverse (lower triangle; zero above)
     const int64_t o = (int64_t)kb * NB;
     const int nb = (int)(P - o < NB ? P - o : NB);
-    const int i = threadIdx.x;
-    {
-        double a[NB];
-#pragma unroll
-        for (int k = 0; k < NB; ++k)
-            a[k] = (i < nb && k < nb) ? (k <= i ? A[(o + i) * P + o + k] : 0.0) : (i == k ? 1.0 : 0.0);
-        bool bad = false;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const double d = readlane_f64(a[j], j);
-            const bool ok = d > 0.0 && isfinite(d);
-            bad |= !ok;
-            const double sj = ok ? sqrt(d) : 1.0;
-            a[j] = i == j ? sj : a[j] / sj;
-            // entries above the diagonal of a row are never read back, so all lanes update
-#pragma unroll
-            for (int k = j + 1; k < NB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
-        }
-        if (bad && i == 0) flag[0] = 1;
-        if (i < nb)
-#pragma unroll
-            for (int k = 0; k < NB; ++k)
-                if (k <= i && k < nb) A[(o + i) * P + o + k] = a[k];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) Ls[i][k] = k < i ? a[k] : (k == i ? 1.0 / a[k] : 0.0);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        S[r][c] = (r < nb && c < nb) ? (c <= r ? A[(o + r) * P + o + c] : 0.0) : (r == c ? 1.0 : 0.0);
+        X[r][c] = 0.0;
     }
     __syncthreads();
-    // column i of L^{-1}: x_k = (delta_ki - acc_k) / L_kk, then acc_r += L_rk x_k for r > k (the
-    // updates of one k are independent, so the broadcast LDS reads pipeline)
-    {
-        double acc[NB];
+    bool bad = false;
+    for (int p = 0; p < NB / DB; ++p) {
+        const int d0 = p * DB;
+        if (w == 0) {
+            double a[DB];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) acc[r] = 0.0;
+            for (int k = 0; k < DB; ++k) a[k] = (lane < DB && k <= lane) ? S[d0 + lane][d0 + k] : 0.0;
+            double ri[DB];                  // 1 / L_jj (the pivots' reciprocal square roots)
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const double xk = ((k == i ? 1.0 : 0.0) - acc[k]) * Ls[k][k];
-            Xs[k][i] = xk;
+            for (int j = 0; j < DB; ++j) {
+                const double dj = readlane_f64(a[j], j);
+                const bool ok = dj > 0.0 && isfinite(dj);
+                bad |= !ok;
+                ri[j] = ok ? rsqrt(dj) : 1.0;
+                a[j] = lane == j ? (ok ? dj * ri[j] : 1.0) : a[j] * ri[j];
+                // entries above the diagonal of a row are never read back, so all lanes update
 #pragma unroll
-            for (int r = k + 1; r < NB; ++r) acc[r] += Ls[r][k] * xk;
+                for (int k = j + 1; k < DB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
+            }
+            // column `lane` of the sub-block's inverse: x_k = (delta_k,lane - sum_{m<k} L_km x_m) / L_kk
+            double x[DB];
+#pragma unroll
+            for (int k = 0; k < DB; ++k) {
+                double acc = lane == k ? 1.0 : 0.0;
+#pragma unroll
+                for (int m = 0; m < k; ++m) acc -= readlane_f64(a[m], k) * x[m];
+                x[k] = acc * ri[k];
+            }
+            if (lane < DB) {
+#pragma unroll
+                for (int k = 0; k < DB; ++k) {
+                    if (k <= lane) S[d0 + lane][d0 + k] = a[k];
+                    if (k >= lane) X[d0 + k][d0 + lane] = x[k];
+                }
+            }
         }
+        __syncthreads();
+        // sub-panel: rows r >= d0 + 16, columns d0 .. d0 + 15: S[r][d0 + j] = sum_{m<=j} S[r][d0 + m] X[d0 + j][d0 + m]
+        const int nr = NB - d0 - DB;
+        double v[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 256 * q;
+            v[q] = 0.0;
+            if (e < nr * DB) {
+                const int r = d0 + DB + e / DB, j = e % DB;
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < DB; ++m) acc += S[r][d0 + m] * X[d0 + j][d0 + m];
+                v[q] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 256 * q;
+            if (e < nr * DB) S[d0 + DB + e / DB][d0 + e % DB] = v[q];
+        }
+        __syncthreads();
+        // trailing lower triangle: S[r][c] -= sum_m S[r][d0 + m] S[c][d0 + m], d0 + 16 <= c <= r
+        for (int e = tid; e < nr * nr; e += 256) {
+            const int r = d0 + DB + e / nr, c = d0 + DB + e % nr;
+            if (c > r) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < DB; ++m) acc += S[r][d0 + m] * S[c][d0 + m];
+            S[r][c] -= acc;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int r = 0; r < NB; ++r) Linv[r * NB + i] = Xs[r][i];
+    // off-diagonal blocks of the inverse, block row by block row
+    for (int i = 1; i < NB / DB; ++i) {
+        const int n = i * DB * DB;       // entries of the blocks (i, j), j < i
+        double v[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {    // T_ij = sum_{k=j}^{i-1} L_ik X_kj
+            const int e = tid + 256 * q;
+            v[q] = 0.0;
+            if (e < n) {
+                const int a = e / (i * DB), col = e % (i * DB), j = col / DB;
+                double acc = 0.0;
+                for (int k = j * DB; k < i * DB; ++k) acc += S[i * DB + a][k] * X[k][col];
+                v[q] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 256 * q;
+            if (e < n) X[i * DB + e / (i * DB)][e % (i * DB)] = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {    // X_ij = -D_i^{-1} T_ij
+            const int e = tid + 256 * q;
+            v[q] = 0.0;
+            if (e < n) {
+                const int a = e / (i * DB), col = e % (i * DB);
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < DB; ++m) acc += X[i * DB + a][i * DB + m] * X[i * DB + m][col];
+                v[q] = -acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 256 * q;
+            if (e < n) X[i * DB + e / (i * DB)][e % (i * DB)] = v[q];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && bad) flag[0] = 1;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        if (r < nb && c <= r) A[(o + r) * P + o + c] = S[r][c];
+        Linv[e] = X[r][c];
+    }
 }
 
 // Panel rows below diagonal block kb, in place: row <- row Linv_kk^T (= row L_kk^{-T}), with
@@ -366,7 +452,7 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     hipEvent_t evA = ctx->ev[0], evB = ctx->ev[1];
     if (ahead && (hipEventRecord(evB, s) != hipSuccess || hipStreamWaitEvent(s2, evB, 0) != hipSuccess))
         return set_error(ctx, BEM_EHIP, "cholesky fork");
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, 0, dflag, linv);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, 0, dflag, linv);
     for (int kb = 0; kb < nblk; ++kb) {
         double* Li = linv + (size_t)kb * NB * NB;
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
@@ -375,7 +461,7 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
         hipLaunchKernelGGL(k_panel, dim3(nt), dim3(256), 0, s, A, P, kb, (const double*)Li);
         if (!ahead) {
             hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, P, kb, nt, 0);
-            hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
+            hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
             continue;
         }
         if (kb > 0 && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky wait");
@@ -384,7 +470,7 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
             return set_error(ctx, BEM_EHIP, "cholesky event");
         if (nt > 1) hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s2, A, P, kb, nt, 2);
         if (hipEventRecord(evB, s2) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky event");
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
     }
     if (ahead && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky join");
     if ((rc = check_launch(ctx, "cholesky"))) return rc;
