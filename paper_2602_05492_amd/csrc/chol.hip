@@ -316,6 +316,7 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
                                                   double* __restrict__ Y, int nrhs)
 {
     __shared__ double T[NB][NB + 1];
+    __shared__ double At[NB][NB + 1];   // the block's rows of L (loaded with T: it does not depend on y)
     __shared__ double bk[NB][kMaxRhs];
     __shared__ double y[NB][kMaxRhs];
     __shared__ double part[4][NB][kMaxRhs];
@@ -323,8 +324,13 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
     const int nb = (int)(P - o < NB ? P - o : NB);
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double* L0 = Linv + (size_t)kb * NB * NB;
+    const int64_t r0 = o + (int64_t)blockIdx.x * NB;
+    const int nr = blockIdx.x == 0 ? 0 : (int)(P - r0 < NB ? P - r0 : NB);
 #pragma unroll
-    for (int r = w; r < NB; r += 4) T[r][t] = L0[(size_t)r * NB + t];
+    for (int r = w; r < NB; r += 4) {
+        T[r][t] = L0[(size_t)r * NB + t];
+        if (blockIdx.x != 0) At[r][t] = (r < nr && t < nb) ? A[(r0 + r) * P + o + t] : 0.0;
+    }
     if (w == 0)
         for (int c = 0; c < nrhs; ++c) bk[t][c] = t < nb ? B[(o + t) * nrhs + c] : 0.0;
     __syncthreads();
@@ -345,15 +351,11 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
             for (int c = 0; c < nrhs; ++c) Y[(o + t) * nrhs + c] = v[c];
     }
     if (blockIdx.x == 0) return;
-    const int64_t r0 = o + (int64_t)blockIdx.x * NB;
-    const int nr = (int)(P - r0 < NB ? P - r0 : NB);
-#pragma unroll
-    for (int k = w; k < NB; k += 4) T[k][t] = (k < nr && t < nb) ? A[(r0 + k) * P + o + t] : 0.0;
     __syncthreads();
     {
         double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
         for (int k = 16 * w; k < 16 * w + 16; ++k) {
-            const double l = T[t][k];
+            const double l = At[t][k];
             for (int c = 0; c < nrhs; ++c) acc[c] += l * y[k][c];
         }
         for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
@@ -374,6 +376,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
                                                   double* __restrict__ X, int nrhs)
 {
     __shared__ double T[NB][NB + 1];
+    __shared__ double At[NB][NB + 1];   // block kb's rows of L at this block's columns (loaded with T)
     __shared__ double yk[NB][kMaxRhs];
     __shared__ double x[NB][kMaxRhs];
     __shared__ double part[4][NB][kMaxRhs];
@@ -381,8 +384,12 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
     const int nb = (int)(P - o < NB ? P - o : NB);
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double* L0 = Linv + (size_t)kb * NB * NB;
+    const int64_t col = (int64_t)(blockIdx.x - 1) * NB + t;
 #pragma unroll
-    for (int r = w; r < NB; r += 4) T[r][t] = L0[(size_t)r * NB + t];
+    for (int r = w; r < NB; r += 4) {
+        T[r][t] = L0[(size_t)r * NB + t];
+        if (blockIdx.x != 0) At[r][t] = (r < nb && col < o) ? A[(o + r) * P + col] : 0.0;
+    }
     if (w == 0)
         for (int c = 0; c < nrhs; ++c) yk[t][c] = t < nb ? Y[(o + t) * nrhs + c] : 0.0;
     __syncthreads();
@@ -403,14 +410,11 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
             for (int c = 0; c < nrhs; ++c) X[(o + t) * nrhs + c] = v[c];
     }
     if (blockIdx.x == 0) return;
-    const int64_t col = (int64_t)(blockIdx.x - 1) * NB + t;
-#pragma unroll
-    for (int r = w; r < NB; r += 4) T[r][t] = (r < nb && col < o) ? A[(o + r) * P + col] : 0.0;
     __syncthreads();
     {
         double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
         for (int r = 16 * w; r < 16 * w + 16; ++r) {
-            const double l = T[r][t];
+            const double l = At[r][t];
             for (int c = 0; c < nrhs; ++c) acc[c] += l * x[r][c];
         }
         for (int c = 0; c < nrhs; ++c) part[w][t][c] = acc[c];
