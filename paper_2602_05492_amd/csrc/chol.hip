@@ -311,9 +311,10 @@ __device__ inline void solve_sum(const double (*part)[NB][kMaxRhs], int t, int n
     for (int c = 0; c < nrhs; ++c) out[c] = part[0][t][c] + part[1][t][c] + part[2][t][c] + part[3][t][c];
 }
 
+template <int nrhs>
 __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, int64_t P, int kb,
                                                   const double* __restrict__ Linv, double* __restrict__ B,
-                                                  double* __restrict__ Y, int nrhs)
+                                                  double* __restrict__ Y)
 {
     __shared__ double T[NB][NB + 1];
     __shared__ double At[NB][NB + 1];   // the block's rows of L (loaded with T: it does not depend on y)
@@ -335,7 +336,7 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
         for (int c = 0; c < nrhs; ++c) bk[t][c] = t < nb ? B[(o + t) * nrhs + c] : 0.0;
     __syncthreads();
     {
-        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        double acc[nrhs] = {};
         for (int k = 16 * w; k < 16 * w + 16; ++k) {
             const double l = T[t][k];
             for (int c = 0; c < nrhs; ++c) acc[c] += l * bk[k][c];
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
     }
     __syncthreads();
     if (w == 0) {
-        double v[kMaxRhs];
+        double v[nrhs];
         solve_sum(part, t, nrhs, v);
         for (int c = 0; c < nrhs; ++c) y[t][c] = v[c];
         if (blockIdx.x == 0 && t < nb)
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
     if (blockIdx.x == 0) return;
     __syncthreads();
     {
-        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        double acc[nrhs] = {};
         for (int k = 16 * w; k < 16 * w + 16; ++k) {
             const double l = At[t][k];
             for (int c = 0; c < nrhs; ++c) acc[c] += l * y[k][c];
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
     }
     __syncthreads();
     if (w == 0 && t < nr) {
-        double v[kMaxRhs];
+        double v[nrhs];
         solve_sum(part, t, nrhs, v);
         for (int c = 0; c < nrhs; ++c) B[(r0 + t) * nrhs + c] -= v[c];
     }
@@ -371,9 +372,10 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
 // Backward step kb of L^T x = y: every block forms x_kb = Linv_kb^T y_kb; block 0 writes it
 // to X, block t >= 1 subtracts L[block kb rows, c]^T x_kb from the 64 entries of Y starting
 // at column c = 64 (t - 1) (only columns before block kb; Y rows of block kb are only read).
+template <int nrhs>
 __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, int64_t P, int kb,
                                                   const double* __restrict__ Linv, double* __restrict__ Y,
-                                                  double* __restrict__ X, int nrhs)
+                                                  double* __restrict__ X)
 {
     __shared__ double T[NB][NB + 1];
     __shared__ double At[NB][NB + 1];   // block kb's rows of L at this block's columns (loaded with T)
@@ -394,7 +396,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
         for (int c = 0; c < nrhs; ++c) yk[t][c] = t < nb ? Y[(o + t) * nrhs + c] : 0.0;
     __syncthreads();
     {
-        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        double acc[nrhs] = {};
         for (int k = 16 * w; k < 16 * w + 16; ++k) {
             const double l = T[k][t];                  // (Linv^T)[t][k]
             for (int c = 0; c < nrhs; ++c) acc[c] += l * yk[k][c];
@@ -403,7 +405,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
     }
     __syncthreads();
     if (w == 0) {
-        double v[kMaxRhs];
+        double v[nrhs];
         solve_sum(part, t, nrhs, v);
         for (int c = 0; c < nrhs; ++c) x[t][c] = v[c];
         if (blockIdx.x == 0 && t < nb)
@@ -412,7 +414,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
     if (blockIdx.x == 0) return;
     __syncthreads();
     {
-        double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+        double acc[nrhs] = {};
         for (int r = 16 * w; r < 16 * w + 16; ++r) {
             const double l = At[r][t];
             for (int c = 0; c < nrhs; ++c) acc[c] += l * x[r][c];
@@ -421,7 +423,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
     }
     __syncthreads();
     if (w == 0 && col < o) {
-        double v[kMaxRhs];
+        double v[nrhs];
         solve_sum(part, t, nrhs, v);
         for (int c = 0; c < nrhs; ++c) Y[col * nrhs + c] -= v[c];
     }
@@ -488,6 +490,22 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
 
 // B <- (L L^T)^{-1} B with the factor in A and the inverted diagonal blocks of the last
 // chol_factor; B [P][nrhs] row-major, nrhs <= 4.  One launch per block and direction.
+// Forward then backward block steps for nrhs right-hand sides (B [P][nrhs] in, solution out; Y [P][nrhs] scratch).
+template <int nrhs>
+static void solve_steps(const double* A, int64_t P, int nblk, const double* linv, double* B, double* Y, hipStream_t s)
+{
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int64_t rem = P - (int64_t)(kb + 1) * NB;
+        const int nbk = 1 + (rem > 0 ? blocks_for(rem, NB) : 0);
+        hipLaunchKernelGGL(k_fwd_step<nrhs>, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, B, Y);
+    }
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int64_t o = (int64_t)kb * NB;
+        const int nbk = 1 + (o > 0 ? blocks_for(o, NB) : 0);
+        hipLaunchKernelGGL(k_bwd_step<nrhs>, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, Y, B);
+    }
+}
+
 int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* B, int nrhs, hipStream_t s)
 {
     if (nrhs < 1 || nrhs > kMaxRhs) return set_error(ctx, BEM_EINVAL, "chol_solve: 1..4 right-hand sides");
@@ -496,15 +514,11 @@ int chol_solve(bem_ctx* ctx, const double* A, int64_t P, double* B, int nrhs, hi
     const int nblk = (int)((P + NB - 1) / NB);
     const double* linv = (const double*)ctx->cholw.ptr;
     double* Y = (double*)ctx->cholw.ptr + (size_t)nblk * NB * NB;
-    for (int kb = 0; kb < nblk; ++kb) {
-        const int64_t rem = P - (int64_t)(kb + 1) * NB;
-        const int nbk = 1 + (rem > 0 ? blocks_for(rem, NB) : 0);
-        hipLaunchKernelGGL(k_fwd_step, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, B, Y, nrhs);
-    }
-    for (int kb = nblk - 1; kb >= 0; --kb) {
-        const int64_t o = (int64_t)kb * NB;
-        const int nbk = 1 + (o > 0 ? blocks_for(o, NB) : 0);
-        hipLaunchKernelGGL(k_bwd_step, dim3(nbk), dim3(256), 0, s, A, P, kb, linv, Y, B, nrhs);
+    switch (nrhs) {
+    case 1: solve_steps<1>(A, P, nblk, linv, B, Y, s); break;
+    case 2: solve_steps<2>(A, P, nblk, linv, B, Y, s); break;
+    case 3: solve_steps<3>(A, P, nblk, linv, B, Y, s); break;
+    default: solve_steps<4>(A, P, nblk, linv, B, Y, s); break;
     }
     return check_launch(ctx, "cholesky solve");
 }
