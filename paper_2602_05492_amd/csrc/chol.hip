@@ -68,9 +68,19 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int6
     const int64_t o = (int64_t)kb * NB;
     const int nb = (int)(P - o < NB ? P - o : NB);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e >> 6, c = e & 63;
-        S[r][c] = (r < nb && c < nb) ? (c <= r ? A[(o + r) * P + o + c] : 0.0) : (r == c ? 1.0 : 0.0);
+    // all 16 loads of a thread in flight at once: entries outside the lower triangle load the
+    // block's first element (always in bounds) and are then replaced
+    double g[NB * NB / 256];
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+        const int e = tid + 256 * q, r = e >> 6, c = e & 63;
+        const bool in = r < nb && c <= r;
+        g[q] = A[(o + (in ? r : 0)) * P + o + (in ? c : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+        const int e = tid + 256 * q, r = e >> 6, c = e & 63;
+        S[r][c] = (r < nb && c <= r) ? g[q] : ((r == c && r >= nb) ? 1.0 : 0.0);
         X[r][c] = 0.0;
     }
     __syncthreads();
@@ -93,21 +103,26 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int6
 #pragma unroll
                 for (int k = j + 1; k < DB; ++k) a[k] -= a[j] * readlane_f64(a[j], k);
             }
-            // column `lane` of the sub-block's inverse: x_k = (delta_k,lane - sum_{m<k} L_km x_m) / L_kk
+            if (lane < DB) {
+#pragma unroll
+                for (int k = 0; k < DB; ++k)
+                    if (k <= lane) S[d0 + lane][d0 + k] = a[k];
+            }
+            __threadfence_block();          // the stores complete before the broadcast reads below
+            // column `lane` of the sub-block's inverse: x_k = (delta_k,lane - sum_{m<k} L_km x_m) / L_kk,
+            // L_km read back from LDS by broadcast (the wavefront's own stores above, in order)
             double x[DB];
 #pragma unroll
             for (int k = 0; k < DB; ++k) {
                 double acc = lane == k ? 1.0 : 0.0;
 #pragma unroll
-                for (int m = 0; m < k; ++m) acc -= readlane_f64(a[m], k) * x[m];
+                for (int m = 0; m < k; ++m) acc -= S[d0 + k][d0 + m] * x[m];
                 x[k] = acc * ri[k];
             }
             if (lane < DB) {
 #pragma unroll
-                for (int k = 0; k < DB; ++k) {
-                    if (k <= lane) S[d0 + lane][d0 + k] = a[k];
+                for (int k = 0; k < DB; ++k)
                     if (k >= lane) X[d0 + k][d0 + lane] = x[k];
-                }
             }
         }
         __syncthreads();
@@ -153,9 +168,13 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int6
             const int e = tid + 256 * q;
             v[q] = 0.0;
             if (e < n) {
-                const int a = e / (i * DB), col = e % (i * DB), j = col / DB;
+                // X[k][col] is zero for k below col's block, so the sum may start at 0
+                const int a = e / (i * DB), col = e % (i * DB);
                 double acc = 0.0;
-                for (int k = j * DB; k < i * DB; ++k) acc += S[i * DB + a][k] * X[k][col];
+                for (int kq = 0; kq < i; ++kq) {
+#pragma unroll
+                    for (int m = 0; m < DB; ++m) acc += S[i * DB + a][kq * DB + m] * X[kq * DB + m][col];
+                }
                 v[q] = acc;
             }
         }
@@ -187,6 +206,7 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int6
         __syncthreads();
     }
     if (tid == 0 && bad) flag[0] = 1;
+#pragma unroll
     for (int e = tid; e < NB * NB; e += 256) {
         const int r = e >> 6, c = e & 63;
         if (r < nb && c <= r) A[(o + r) * P + o + c] = S[r][c];
@@ -207,9 +227,19 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P
     const int64_t r0 = o + NB + (int64_t)blockIdx.x * NB;
     const int nr = (int)(P - r0 < NB ? P - r0 : NB);
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = w; i < NB; i += 4) {
-        R[i][t] = i < nr ? A[(r0 + i) * P + o + t] : 0.0;
-        LiT[t][i] = Linv[(size_t)i * NB + t];
+    // loads first (all in flight; rows past the matrix read row r0 and are then zeroed)
+    double gr[NB / 4], gl[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+        const int i = w + 4 * q;
+        gr[q] = A[(r0 + (i < nr ? i : 0)) * P + o + t];
+        gl[q] = Linv[(size_t)i * NB + t];
+    }
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+        const int i = w + 4 * q;
+        R[i][t] = i < nr ? gr[q] : 0.0;
+        LiT[t][i] = gl[q];
     }
     __syncthreads();
     double out[NB / 4];
@@ -327,10 +357,19 @@ __global__ void __launch_bounds__(256) k_fwd_step(const double* __restrict__ A, 
     const double* L0 = Linv + (size_t)kb * NB * NB;
     const int64_t r0 = o + (int64_t)blockIdx.x * NB;
     const int nr = blockIdx.x == 0 ? 0 : (int)(P - r0 < NB ? P - r0 : NB);
+    // loads first (all in flight; entries past the matrix read an in-bounds one and are then zeroed)
+    double gl[NB / 4], ga[NB / 4];
 #pragma unroll
-    for (int r = w; r < NB; r += 4) {
-        T[r][t] = L0[(size_t)r * NB + t];
-        if (blockIdx.x != 0) At[r][t] = (r < nr && t < nb) ? A[(r0 + r) * P + o + t] : 0.0;
+    for (int q = 0; q < NB / 4; ++q) {
+        const int r = w + 4 * q;
+        gl[q] = L0[(size_t)r * NB + t];
+        ga[q] = blockIdx.x != 0 ? A[(r0 + (r < nr ? r : 0)) * P + o + (t < nb ? t : 0)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+        const int r = w + 4 * q;
+        T[r][t] = gl[q];
+        At[r][t] = (r < nr && t < nb) ? ga[q] : 0.0;
     }
     if (w == 0)
         for (int c = 0; c < nrhs; ++c) bk[t][c] = t < nb ? B[(o + t) * nrhs + c] : 0.0;
@@ -387,10 +426,19 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double* L0 = Linv + (size_t)kb * NB * NB;
     const int64_t col = (int64_t)(blockIdx.x - 1) * NB + t;
+    // loads first (all in flight; entries past the matrix read an in-bounds one and are then zeroed)
+    double gl[NB / 4], ga[NB / 4];
 #pragma unroll
-    for (int r = w; r < NB; r += 4) {
-        T[r][t] = L0[(size_t)r * NB + t];
-        if (blockIdx.x != 0) At[r][t] = (r < nb && col < o) ? A[(o + r) * P + col] : 0.0;
+    for (int q = 0; q < NB / 4; ++q) {
+        const int r = w + 4 * q;
+        gl[q] = L0[(size_t)r * NB + t];
+        ga[q] = blockIdx.x != 0 ? A[(o + (r < nb ? r : 0)) * P + (col < o ? col : 0)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) {
+        const int r = w + 4 * q;
+        T[r][t] = gl[q];
+        At[r][t] = (r < nb && col < o) ? ga[q] : 0.0;
     }
     if (w == 0)
         for (int c = 0; c < nrhs; ++c) yk[t][c] = t < nb ? Y[(o + t) * nrhs + c] : 0.0;
