@@ -260,18 +260,18 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P
 // trailing matrix C = A[o2:, o2:], o2 = 64 (kb + 1), with the panel L21 = A[o2:, o:o+64].
 // One block per 64 x 64 tile (I, J), I >= J (linear block index -> (I, J)); 4 waves, each a
 // 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  The two 64-row panel slices are
-// staged in LDS transposed ([k][row], 32 k at a time) so that an MFMA operand (lane l:
-// row l mod 16, k l / 16, the same pattern for both operands) is one ds_read per lane.
+// staged in LDS transposed ([k][row], all 64 k in one pass, every global load of the block
+// issued before the first wait) so that an MFMA operand (lane l: row l mod 16, k l / 16, the
+// same pattern for both operands) is one ds_read per lane.
 // Accumulator element q of lane l is row 4 q + l / 16, column l mod 16 of its 16 x 16 tile.
 typedef double d4_t __attribute__((ext_vector_type(4)));
-constexpr int kSyrkK = 32;               // k per LDS stage
 constexpr int kSyrkLd = 72;              // LDS row stride (doubles) of the transposed slices
 // mode 0: every tile; 1: the first tile column only (J = 0: the next diagonal block and panel);
 // 2: the other tiles (J >= 1).
 __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t P, int kb, int nt, int mode)
 {
-    __shared__ double SI[kSyrkK][kSyrkLd];
-    __shared__ double SJ[kSyrkK][kSyrkLd];
+    __shared__ double SI[NB][kSyrkLd];   // [k][row] of the panel rows of tile row I
+    __shared__ double SJ[NB][kSyrkLd];   // and of tile column J
     const int64_t o = (int64_t)kb * NB, o2 = o + NB;
     const int64_t rem = P - o2;
     // tile (I, J), I >= J, from the linear index b = I (I + 1) / 2 + J
@@ -291,31 +291,50 @@ __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t 
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int64_t rI = (int64_t)I * NB, rJ = (int64_t)J * NB;
+    // every global load first, all in flight: the 16 entries of C this thread updates and the two
+    // 64-row x 64-k panel slices (entries past the matrix read an in-bounds one and are then
+    // replaced)
+    double c[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gr = rI + 32 * wr + 16 * i + 4 * q + (l >> 4);
+                const int64_t gc = rJ + 32 * wc + 16 * j + (l & 15);
+                const bool in = gr < rem && gc <= gr;
+                c[i][j][q] = A[(o2 + (in ? gr : 0)) * P + o2 + (in ? gc : 0)];
+            }
+    double vi[NB * NB / 256], vj[NB * NB / 256];
+#pragma unroll
+    for (int m = 0; m < NB * NB / 256; ++m) {
+        const int e = tid + 256 * m, r = e >> 6, k = e & 63;
+        const int64_t gi = rI + r, gj = rJ + r;
+        vi[m] = A[(o2 + (gi < rem ? gi : 0)) * P + o + k];
+        vj[m] = A[(o2 + (gj < rem ? gj : 0)) * P + o + k];
+    }
+#pragma unroll
+    for (int m = 0; m < NB * NB / 256; ++m) {
+        const int e = tid + 256 * m, r = e >> 6, k = e & 63;
+        SI[k][r] = rI + r < rem ? vi[m] : 0.0;
+        SJ[k][r] = rJ + r < rem ? vj[m] : 0.0;
+    }
+    __syncthreads();
     d4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < NB; k0 += kSyrkK) {
-        // stage: thread (row r = tid / 4 .. , k) loads coalesced runs of the two slices
-        for (int e = tid; e < NB * kSyrkK; e += 256) {
-            const int r = e / kSyrkK, k = e % kSyrkK;
-            const int64_t gi = rI + r, gj = rJ + r;
-            SI[k][r] = gi < rem ? A[(o2 + gi) * P + o + k0 + k] : 0.0;
-            SJ[k][r] = gj < rem ? A[(o2 + gj) * P + o + k0 + k] : 0.0;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < kSyrkK; ks += 4) {
-            const int kk = ks + (l >> 4), rr = l & 15;
-            const double a0 = SI[kk][32 * wr + rr], a1 = SI[kk][32 * wr + 16 + rr];
-            const double b0 = SJ[kk][32 * wc + rr], b1 = SJ[kk][32 * wc + 16 + rr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
+    for (int ks = 0; ks < NB; ks += 4) {
+        const int kk = ks + (l >> 4), rr = l & 15;
+        const double a0 = SI[kk][32 * wr + rr], a1 = SI[kk][32 * wr + 16 + rr];
+        const double b0 = SJ[kk][32 * wc + rr], b1 = SJ[kk][32 * wc + 16 + rr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -325,7 +344,7 @@ __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t 
             for (int q = 0; q < 4; ++q) {
                 const int64_t gr = rI + 32 * wr + 16 * i + 4 * q + (l >> 4);
                 const int64_t gc = rJ + 32 * wc + 16 * j + (l & 15);
-                if (gr < rem && gc <= gr) A[(o2 + gr) * P + o2 + gc] -= acc[i][j][q];
+                if (gr < rem && gc <= gr) A[(o2 + gr) * P + o2 + gc] = c[i][j][q] - acc[i][j][q];
             }
 }
 
