@@ -490,17 +490,15 @@ __device__ inline int64_t param_col(int a, Layout L, int c)
     return (int64_t)L.params() * (b / L.C) + L.G + 3 * (b % L.C) + c;
 }
 
-// JtJ[col(a)][col(b)] += s * (Gc[a][b] + T1[a][b] + T1[b][a] + T2[a][b]), T2 symmetrised so
-// that J^T J is exactly symmetric
-__global__ void k_scatter_h(const double* __restrict__ Gc, int Wc, const double* __restrict__ T1,
-                            const double* __restrict__ T2, Layout L, int c, double s, double* __restrict__ JtJ, int64_t P)
+// JtJ[col(a)][col(b)] += s * (Gc[a][b] + S[a][b] + S[b][a]): exactly symmetric
+__global__ void k_scatter_h(const double* __restrict__ Gc, int Wc, const double* __restrict__ S, Layout L, int c,
+                            double s, double* __restrict__ JtJ, int64_t P)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const int a = blockIdx.y;
     const int n = L.compact();
     if (b >= n) return;
-    const double v = Gc[(size_t)a * Wc + b] + T1[(size_t)a * n + b] + T1[(size_t)b * n + a] +
-                     0.5 * (T2[(size_t)a * n + b] + T2[(size_t)b * n + a]);
+    const double v = Gc[(size_t)a * Wc + b] + S[(size_t)a * n + b] + S[(size_t)b * n + a];
     JtJ[param_col(a, L, c) * P + param_col(b, L, c)] += s * v;
 }
 
@@ -880,27 +878,23 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     if (want_r && (rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
     const size_t wc2 = (size_t)Wc * Wc;
     const size_t szc = (size_t)M * n12;
-    if ((rc = ensure(ctx, ctx->tmp2, (wc2 + szc + 2 * (size_t)n12 * n12 + (size_t)M * n12 + (size_t)(N > 0 ? N : 1) * 3) *
-                                         sizeof(double), s)))
+    if ((rc = ensure(ctx, ctx->tmp2, (wc2 + szc + (size_t)n12 * n12 + (size_t)(N > 0 ? N : 1) * 3) * sizeof(double), s)))
         return rc;
     double* Gc = (double*)ctx->tmp2.ptr + (size_t)(N > 0 ? N : 1) * 3;   // keep r64 (not needed anymore, but harmless)
     double* Zc = Gc + wc2;
-    double* T1 = Zc + szc;
-    double* T2 = T1 + (size_t)n12 * n12;
-    double* W1 = T2 + (size_t)n12 * n12;
+    double* S1 = Zc + szc;
     for (int c = 0; c < 3; ++c) {
         hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, L, c, Wc, Gc);
         hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, L, M, c, Zc);
         if ((rc = check_launch(ctx, "gather"))) return rc;
-        // T1 = B_c Zc   (B_c = Gc[0:n12, n12:Wc])
-        if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, T1, n12, s, nullptr, 0))) return rc;
-        // W1 = D Zc    (D = Gc[n12:, n12:])
-        if ((rc = gemm_f64(ctx, M, n12, M, 1.0, Gc + (size_t)n12 * Wc + n12, Wc, false, Zc, n12, false, 0.0, W1, n12, s,
+        // The channel's block of J^T J is G + B Zc + (B Zc)^T + Zc^T D Zc with B = Gc[0:n12, n12:Wc]
+        // and D = Gc[n12:, n12:] (symmetric), which equals G + S + S^T with S = Y Zc and
+        // Y = B + (1/2) Zc^T D: two products instead of three.  Y overwrites B in Gc.
+        if ((rc = gemm_f64(ctx, n12, M, M, 0.5, Zc, n12, true, Gc + (size_t)n12 * Wc + n12, Wc, false, 1.0, Gc + n12, Wc, s,
                            nullptr, 0)))
             return rc;
-        // T2 = Zc^T W1
-        if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Zc, n12, true, W1, n12, false, 0.0, T2, n12, s, nullptr, 0))) return rc;
-        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, T1, T2, L, c, sc, JtJ, P);
+        if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, S1, n12, s, nullptr, 0))) return rc;
+        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, S1, L, c, sc, JtJ, P);
         if (want_r)
             hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, L, M, c, sc, Jtr);
         if ((rc = check_launch(ctx, "scatter"))) return rc;
