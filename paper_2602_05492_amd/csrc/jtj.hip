@@ -329,24 +329,14 @@ __global__ void k_vertex_table(int S, int model, float* __restrict__ vtab)
     vtab[8 * j + 6] = vtab[8 * j + 7] = 0.0f;
 }
 
-// Float64 contributions of the listed near (sample, segment) pairs of one tile
-// (wavefronts w0 .. w0 + nw - 1) to one handle's features: thread per list slot,
-// corr[slot][28] = geo[3][8] and col[4] as in store_handle_rows (geometry already
-// chained with the vertex weights).
-__global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list, int slots,
-                                                       const int* __restrict__ wave_count,
-                                                       const uint8_t* __restrict__ flag, int64_t w0, int64_t nw,
-                                                       const double* __restrict__ x, const double* __restrict__ seg64,
-                                                       int K, int S, int model, double eps2,
-                                                       float* __restrict__ corr)
+// Float64 contributions of one listed near (sample, segment) pair to its handle's
+// features: o[28] = geo[3][8] and col[4] as in store_handle_rows (geometry already
+// chained with the vertex weights); k_features_near stores them at the pair's slot
+// of the tile (wavefronts w0 .. w0 + nw - 1), corr[slot][28].
+__device__ inline void features_near_pair(const NearPair p, const double* __restrict__ x,
+                                          const double* __restrict__ seg64, int S, int model, double eps2,
+                                          float* __restrict__ o)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nw * slots) return;
-    const int64_t w = w0 + t / slots;
-    const int e = (int)(t % slots);
-    if (e >= wave_count[w]) return;
-    const NearPair p = list[w * slots + e];
-    if (p.seg >= K || flag[p.sample]) return;
     const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
     const double* s64 = seg64 + (size_t)p.seg * kSegStride;
     const SegGeom<double> g = load_geom(s64);
@@ -355,7 +345,6 @@ __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restric
     double Ba[4], Bb[4];
     vertex_weights(model, ta, Ba);
     vertex_weights(model, tb, Bb);
-    float* o = corr + (size_t)t * kFeatVals;
     const PairState<double> st = pair_forward<double, DevF64, true>(g, X, Y, eps2);
     const Moments<double> m = pair_moments(g, st);
     for (int c = 0; c < 3; ++c) {
@@ -369,6 +358,23 @@ __global__ void __launch_bounds__(256) k_features_near(const NearPair* __restric
     o[25] = (float)(m.da * ta + m.db * tb);
     o[26] = (float)(m.sa * (1.0 - ta) + m.sb * (1.0 - tb));
     o[27] = (float)(m.sa * ta + m.sb * tb);
+}
+
+// block per wavefront slice w0 + blockIdx.x, its threads looping over the slice's entries
+__global__ void __launch_bounds__(256) k_features_near(const NearPair* __restrict__ list, int slots,
+                                                       const int* __restrict__ wave_count,
+                                                       const uint8_t* __restrict__ flag, int64_t w0,
+                                                       const double* __restrict__ x, const double* __restrict__ seg64,
+                                                       int K, int S, int model, double eps2,
+                                                       float* __restrict__ corr)
+{
+    const int64_t w = w0 + blockIdx.x;
+    const int cnt = wave_count[w];
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const NearPair p = list[w * slots + e];
+        if (p.seg >= K || flag[p.sample]) continue;
+        features_near_pair(p, x, seg64, S, model, eps2, corr + ((size_t)blockIdx.x * slots + e) * kFeatVals);
+    }
 }
 
 // beta rows: Xt[row0 + j][t] = beta_j(x_t); thread per point, each block row of the grid a
@@ -587,9 +593,8 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             const int64_t nw = (npts + 63) / 64;
             {
                 ProfScope ps_(ctx, PT_NEAR, s);
-                hipLaunchKernelGGL(k_features_near, dim3(blocks_for(nw * nl->slots, 256)), dim3(256), 0, s, nl->list,
-                                   nl->slots, nl->count, nl->flag, t0 >> 6, nw, xg, (const double*)ctx->seg64.ptr, H * S, S, model,
-                                   eps2, corr);
+                hipLaunchKernelGGL(k_features_near, dim3(nw), dim3(256), 0, s, nl->list, nl->slots, nl->count, nl->flag,
+                                   t0 >> 6, xg, (const double*)ctx->seg64.ptr, H * S, S, model, eps2, corr);
                 hipLaunchKernelGGL(k_near_runs, dim3(blocks_for(nw * H, 256)), dim3(256), 0, s, nl->list, nl->slots,
                                    nl->count, t0 >> 6, nw, H, S, runs);
             }

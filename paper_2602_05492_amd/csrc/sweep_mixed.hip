@@ -118,34 +118,47 @@ __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, 
     if (live) flag[i] = overflow ? 1 : 0;
 }
 
-// Listed near pairs in float64, added into acc[3 * sample + c]; thread per slot.
+// Listed near pairs in float64: block per wavefront slice (its threads loop over the
+// slice's entries only), the sums of the slice's 64 samples in LDS, then stored to
+// acc[3 * sample + c] (every sample belongs to exactly one slice, so no global atomics).
 __global__ void __launch_bounds__(256) k_near_pairs(const NearPair* __restrict__ list,
-                                                    const int* __restrict__ wave_count, int slots, int64_t nslots,
+                                                    const int* __restrict__ wave_count, int slots, int64_t N,
                                                     const double* __restrict__ x, const double* __restrict__ seg64,
                                                     int K, const double* __restrict__ el64, double eps2,
                                                     double* __restrict__ acc)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nslots) return;
-    if ((int)(t % slots) >= wave_count[t / slots]) return;
-    const NearPair p = list[t];
-    const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
-    double v0, v1, v2;
-    if (p.seg < K) {
-        const double* s = seg64 + (size_t)p.seg * kSegStride;
-        const SegGeom<double> g = load_geom(s);
-        const Moments<double> m = seg_moments<double, DevF64>(g, X, Y, eps2);
-        v0 = m.da * s[kWdA + 0] + m.db * s[kWdB + 0] + m.sa * s[kWcA + 0] + m.sb * s[kWcB + 0];
-        v1 = m.da * s[kWdA + 1] + m.db * s[kWdB + 1] + m.sa * s[kWcA + 1] + m.sb * s[kWcB + 1];
-        v2 = m.da * s[kWdA + 2] + m.db * s[kWdB + 2] + m.sa * s[kWcA + 2] + m.sb * s[kWcB + 2];
-    } else {
-        const double* e = el64 + (size_t)(p.seg - K) * kElemStride;
-        const double beta = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
-        v0 = beta * e[4]; v1 = beta * e[5]; v2 = beta * e[6];
+    __shared__ double sacc[64 * 3];
+    const int64_t w = blockIdx.x;
+    const int cnt = wave_count[w];
+    if (threadIdx.x < 64 * 3) sacc[threadIdx.x] = 0.0;
+    __syncthreads();
+    const NearPair* sl = list + w * slots;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const NearPair p = sl[e];
+        const double X = x[2 * (int64_t)p.sample], Y = x[2 * (int64_t)p.sample + 1];
+        double v0, v1, v2;
+        if (p.seg < K) {
+            const double* s = seg64 + (size_t)p.seg * kSegStride;
+            const SegGeom<double> g = load_geom(s);
+            const Moments<double> m = seg_moments<double, DevF64>(g, X, Y, eps2);
+            v0 = m.da * s[kWdA + 0] + m.db * s[kWdB + 0] + m.sa * s[kWcA + 0] + m.sb * s[kWcB + 0];
+            v1 = m.da * s[kWdA + 1] + m.db * s[kWdB + 1] + m.sa * s[kWcA + 1] + m.sb * s[kWcB + 1];
+            v2 = m.da * s[kWdA + 2] + m.db * s[kWdB + 2] + m.sa * s[kWcA + 2] + m.sb * s[kWcB + 2];
+        } else {
+            const double* el = el64 + (size_t)(p.seg - K) * kElemStride;
+            const double beta = element_beta<double, DevF64>(el[0], el[1], el[2], el[3], X, Y);
+            v0 = beta * el[4]; v1 = beta * el[5]; v2 = beta * el[6];
+        }
+        const int ls = p.sample - (int)(w * 64);     // the slice lists its own wavefront's samples
+        atomicAdd(&sacc[3 * ls + 0], v0);
+        atomicAdd(&sacc[3 * ls + 1], v1);
+        atomicAdd(&sacc[3 * ls + 2], v2);
     }
-    atomicAdd(acc + 3 * (int64_t)p.sample + 0, v0);
-    atomicAdd(acc + 3 * (int64_t)p.sample + 1, v1);
-    atomicAdd(acc + 3 * (int64_t)p.sample + 2, v2);
+    __syncthreads();
+    if (threadIdx.x < 64 * 3) {
+        const int64_t gi = w * 64 * 3 + threadIdx.x;
+        if (gi < 3 * N) acc[gi] = sacc[threadIdx.x];
+    }
 }
 
 __global__ void k_combine(float* __restrict__ u, const double* __restrict__ acc, int64_t N, double c0, double c1,
@@ -263,7 +276,6 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     int* need = (int*)(base + list_bytes + acc_bytes + cnt_bytes);
     uint8_t* flag = (uint8_t*)(base + list_bytes + acc_bytes + cnt_bytes + 256);
     ctx->sweep_need = need;
-    if ((rc = fill_f64(ctx, acc, 3 * N, 0.0, s))) return rc;
     if ((rc = fill_i32(ctx, need, 1, 0, s))) return rc;
     if (out) *out = NearList{list, wave_count, flag, need, nwaves, slots, true};
     {
@@ -274,8 +286,8 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     }
     {
         ProfScope ps_(ctx, PT_NEAR, s);
-        hipLaunchKernelGGL(k_near_pairs, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, list, wave_count, slots, nslots,
-                           x, (const double*)ctx->seg64.ptr, K, (const double*)ctx->elem64.ptr, eps2, acc);
+        hipLaunchKernelGGL(k_near_pairs, dim3(nwaves), dim3(256), 0, s, list, wave_count, slots, N, x,
+                           (const double*)ctx->seg64.ptr, K, (const double*)ctx->elem64.ptr, eps2, acc);
     }
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(N, 256)), dim3(256), 0, s, u, acc, N, cbar[0], cbar[1], cbar[2]);
     hipLaunchKernelGGL(k_sweep_inline, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, flag,

@@ -24,6 +24,7 @@ namespace bem {
 namespace {
 
 constexpr int kV = kSegVjpVals;   // 16 sums per segment
+constexpr int kNearCopies = 16;   // partial rows the listed near pairs add into
 constexpr double kGaussNode = 0.77459666924148337703585307995647992;
 constexpr double kGaussW0 = 5.0 / 9.0, kGaussW1 = 8.0 / 9.0;
 
@@ -198,63 +199,70 @@ __device__ inline void near_element_adjoint(const double* __restrict__ e, double
     atomicAdd(o + 2, b * g2);
 }
 
-// Listed near pairs of the mixed adjoint (thread per list slot; a wavefront covers
-// 64 consecutive slots of one slice).  Entries of a slice are sorted by segment, so
-// the wavefront first sums equal segments by a segmented scan over its lanes and
-// one lane per segment adds the sums (atomics into one extra partial row of each
-// fixed-order reduction).  Pairs of flagged samples are left to k_vjp_flagged,
-// which redoes all near pairs of such a sample.
+// Listed near pairs of the mixed adjoint: block per wavefront slice, a wavefront
+// taking 64 consecutive entries at a time.  Entries of a slice are sorted by segment,
+// so the wavefront first sums equal segments by a segmented scan over its lanes, and
+// one lane per run adds the sums with atomics into kNearCopies extra partial rows of
+// each fixed-order reduction: value c into row (slice + c) mod kNearCopies, so that
+// the 16 atomics of a run (most runs hold one pair) go to 16 cache lines and slices
+// near the same segment to different rows, rather than queueing on one line.  Pairs
+// of flagged samples are left to k_vjp_flagged (into the first row), which redoes all
+// near pairs of such a sample.
 __global__ void __launch_bounds__(256) k_vjp_near(const NearPair* __restrict__ list, int slots,
                                                   const int* __restrict__ wave_count,
-                                                  const uint8_t* __restrict__ flag, int64_t nslots,
+                                                  const uint8_t* __restrict__ flag,
                                                   const double* __restrict__ x, const float* __restrict__ gbar,
                                                   const double* __restrict__ seg64, int K,
-                                                  const double* __restrict__ el64, double eps2,
+                                                  const double* __restrict__ el64, int M, double eps2,
                                                   double* __restrict__ segsum, double* __restrict__ psisum)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // nslots is a multiple of the block size
-    const int e = (int)(t % slots);
-    const int cnt = wave_count[t / slots];
-    if ((e & ~63) >= cnt) return;                     // the whole wavefront lies past the slice's entries
+    // block per wavefront slice; wavefront q of the block takes the slice's 64-entry chunks q, q + 4, ...
+    const int64_t wv = blockIdx.x;
+    const int cnt = wave_count[wv];
+    const NearPair* sl = list + wv * slots;
     const int lane = threadIdx.x & 63;
     constexpr int kNone = 0x7fffffff;                 // key of an empty slot: after every entry
-    double v[kV];
-    for (int c = 0; c < kV; ++c) v[c] = 0.0;
-    int key = kNone;
-    if (e < cnt && t < nslots) {
-        const NearPair p = list[t];
-        key = p.seg;
-        const int64_t i = p.sample;
-        if (!flag[i]) {
-            const double X = x[2 * i], Y = x[2 * i + 1];
-            const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
-            if (p.seg < K) {
-                near_segment_values(seg64 + (size_t)p.seg * kSegStride, X, Y, g0, g1, g2, eps2, v);
-            } else {
-                const double* el = el64 + (size_t)(p.seg - K) * kElemStride;
-                const double b = element_beta<double, DevF64>(el[0], el[1], el[2], el[3], X, Y);
-                v[0] = b * g0; v[1] = b * g1; v[2] = b * g2;
+    for (int c0 = (threadIdx.x >> 6) * 64; c0 < cnt; c0 += 256) {
+        const int e = c0 + lane;
+        double v[kV];
+        for (int c = 0; c < kV; ++c) v[c] = 0.0;
+        int key = kNone;
+        if (e < cnt) {
+            const NearPair p = sl[e];
+            key = p.seg;
+            const int64_t i = p.sample;
+            if (!flag[i]) {
+                const double X = x[2 * i], Y = x[2 * i + 1];
+                const double g0 = gbar[3 * i], g1 = gbar[3 * i + 1], g2 = gbar[3 * i + 2];
+                if (p.seg < K) {
+                    near_segment_values(seg64 + (size_t)p.seg * kSegStride, X, Y, g0, g1, g2, eps2, v);
+                } else {
+                    const double* el = el64 + (size_t)(p.seg - K) * kElemStride;
+                    const double b = element_beta<double, DevF64>(el[0], el[1], el[2], el[3], X, Y);
+                    v[0] = b * g0; v[1] = b * g1; v[2] = b * g2;
+                }
             }
         }
-    }
-    // inclusive segmented scan: after the step with offset o, v holds the sum over the lanes
-    // (l - 2o, l] with the same key (keys ascend along the lanes)
-    for (int o = 1; o < 64; o <<= 1) {
-        const int ko = __shfl_up(key, o);
-        const bool take = lane >= o && ko == key;
-        for (int c = 0; c < kV; ++c) {
-            const double w = __shfl_up(v[c], o);
-            if (take) v[c] += w;
+        // inclusive segmented scan: after the step with offset o, v holds the sum over the lanes
+        // (l - 2o, l] with the same key (keys ascend along the lanes)
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ko = __shfl_up(key, o);
+            const bool take = lane >= o && ko == key;
+            for (int c = 0; c < kV; ++c) {
+                const double w = __shfl_up(v[c], o);
+                if (take) v[c] += w;
+            }
         }
-    }
-    const int kn = __shfl_down(key, 1);
-    if ((lane == 63 || kn != key) && key != kNone) {
-        if (key < K) {
-            double* o = segsum + (size_t)key * kV;
-            for (int c = 0; c < kV; ++c) atomicAdd(o + c, v[c]);
-        } else {
-            double* o = psisum + 3 * (size_t)(key - K);
-            for (int c = 0; c < 3; ++c) atomicAdd(o + c, v[c]);
+        // value c of a run goes to partial row (slice + c) mod kNearCopies
+        const int kn = __shfl_down(key, 1);
+        if ((lane == 63 || kn != key) && key != kNone) {
+            if (key < K) {
+                for (int c = 0; c < kV; ++c)
+                    atomicAdd(segsum + (size_t)((wv + c) % kNearCopies) * K * kV + (size_t)key * kV + c, v[c]);
+            } else {
+                for (int c = 0; c < 3; ++c)
+                    atomicAdd(psisum + (size_t)((wv + c) % kNearCopies) * M * 3 + 3 * (size_t)(key - K) + c, v[c]);
+            }
         }
     }
 }
@@ -383,7 +391,7 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int ns = N > 0 ? chunks_for(N, kgroups, chunk_s) : 0;
     const int ng = chunks_for(3 * (int64_t)M, kgroups, chunk_g);
     const int ne = N > 0 ? chunks_for(N, mgroups, chunk_e) : 0;
-    const int extra = mixed && N > 0 ? 1 : 0;           // one partial row for the float64 near pairs
+    const int extra = mixed && N > 0 ? kNearCopies : 0; // partial rows for the float64 near pairs
     const size_t seg_part = (size_t)(ns + ng + extra) * K * kV;
     const size_t el_rows = (size_t)(ne > 0 ? ne : 1) + extra;
     // workspaces: tmp1 segment partials, tmp2 element partials + psi + mu, tmp3 Gauss points, red segment sums
@@ -419,8 +427,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             NearList nl;
             if (pre) nl = *pre;
             else if ((rc = near_classify(ctx, ctx->nearv, x, N, K, M, &nl, s))) return rc;
-            if ((rc = fill_f64(ctx, segnear, (int64_t)K * kV, 0.0, s))) return rc;
-            if ((rc = fill_f64(ctx, psinear, (int64_t)M * 3, 0.0, s))) return rc;
+            if ((rc = fill_f64(ctx, segnear, (int64_t)kNearCopies * K * kV, 0.0, s))) return rc;
+            if ((rc = fill_f64(ctx, psinear, (int64_t)kNearCopies * M * 3, 0.0, s))) return rc;
             {
                 ProfScope ps_(ctx, PT_VJP_SEGMENTS, s);
                 hipLaunchKernelGGL((k_vjp_segments<true, float>), dim3(kgroups, ns), dim3(256), 0, s, x,
@@ -433,9 +441,8 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             }
             {
                 ProfScope ps_(ctx, PT_NEAR, s);
-                const int64_t nslots = nl.nwaves * nl.slots;
-                hipLaunchKernelGGL(k_vjp_near, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, nl.list, nl.slots, nl.count,
-                                   nl.flag, nslots, x, (const float*)gbar, seg64, K, el64, eps2, segnear, psinear);
+                hipLaunchKernelGGL(k_vjp_near, dim3(nl.nwaves), dim3(256), 0, s, nl.list, nl.slots, nl.count, nl.flag, x,
+                                   (const float*)gbar, seg64, K, el64, M, eps2, segnear, psinear);
                 if (nl.overflowed)
                     hipLaunchKernelGGL(k_vjp_flagged, dim3(blocks_for(N, 256)), dim3(256), 0, s, nl.flag, N, x,
                                    (const float*)gbar, seg32, seg64, K, el32, el64, M, eps2, near2, segnear, psinear);
