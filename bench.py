@@ -47,6 +47,26 @@ def sources_sha(names) -> str:
     return h.hexdigest()
 
 
+def gram_tile_pairs(H: int, M: int, model: str) -> int:
+    """256 x 256 output tiles the split-BF16 Gram computes: the upper triangle of the feature
+    rows' tiles (three channel geometry blocks, each padded to 256 rows, then the shared colour
+    and beta rows) without the pairs that lie in two different channels' geometry blocks."""
+    G, C = (8, 4) if model == "cubic" else (4, 2)
+    gp = -(-G * H // 256) * 256
+    nt = -(-(3 * gp + C * H + M) // 256)
+
+    def region(t):
+        lo, hi = 256 * t, 256 * t + 255
+        if lo >= 3 * gp:
+            return -1
+        if hi >= 3 * gp or lo // gp != hi // gp:
+            return -2
+        return lo // gp
+
+    return sum(1 for i in range(nt) for j in range(i, nt)
+               if not (region(i) >= 0 and region(j) >= 0 and region(i) != region(j)))
+
+
 def pmc_record():
     try:
         return json.load(open(PMC_FILE))
@@ -307,6 +327,17 @@ def main() -> int:
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (peak / 1e12), "traffic": traffic, "launches": launches,
                 "avg_launch_ms": tot_ms / launches}
+    if traffic is not None:
+        # context from the same counter run: the clock under the Gram launch alone (GRBM_GUI_ACTIVE
+        # per XCD over its duration) and the MFMA work it issues (3 products per entry) against
+        # the dense bf16 peak at that clock
+        g = pmc_record()["gram"]
+        if g.get("clock_ghz"):
+            issued = gram_tile_pairs(H, M, wl.spec.model) * 256 * 256 * 2.0 * GRAM_TILE * 3
+            roofline["alone"] = {"ms": g["duration_ms_in_counter_run"], "clock_ghz": g["clock_ghz"],
+                                 "mfma_issued_pflops": issued / (g["duration_ms_in_counter_run"] * 1e-3) / 1e15,
+                                 "frac_of_peak_at_clock": issued / (g["duration_ms_in_counter_run"] * 1e-3)
+                                 / (2.5e15 * g["clock_ghz"] / 2.4)}
     fwd_ms = prof["sweep_mixed" if args.prec == "mixed" else "sweep_f64"]
     pairs_fwd = (N * (K + M)) / (fwd_ms[0] / fwd_ms[1] * 1e-3) if fwd_ms[1] else None
     vjp_ms = prof["vjp_segments"][0] + prof["vjp_elements"][0]
