@@ -62,6 +62,21 @@ def test_jtj_reduced_precision_modes(gram, prec):
     assert eh < 1e-4 and eg < 1e-3
 
 
+def test_jtj_default_tiles_absorb_short_tail():
+    """33,000 samples with the default sample tile (32,768 for the split-BF16 Gram): the
+    968-sample tail is spread over one tile of 33,024 samples instead of a second tile;
+    split-BF16 / mixed J^T J against the oracle."""
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S)
+    x = W.random_points(54, 33000)
+    r = W.random_vector(55, (len(x), 3))
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r, torch.float32), "bf16x3_mfma", "mixed")
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"jtj 33,000 samples, default tiles: rel err JtJ {eh:.3e} Jtr {eg:.3e}")
+    assert eh < 1e-4 and eg < 1e-3
+
+
 def test_jtj_medium_fp64_matches_oracle():
     wl = W.make_config(2)
     ctx = ctx_for(wl.S)
