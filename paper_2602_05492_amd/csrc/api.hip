@@ -225,6 +225,13 @@ static int build_context(const bem_opts* opts, const double* elems, int M, hipSt
     int rc = ensure(ctx, ctx->egeo, ebytes, stream);
     if (!rc) {
         if (elems) {
+            double bb[4] = {elems[0], elems[1], elems[0], elems[1]};
+            for (int i = 0; i < 2 * ctx->M; ++i) {
+                const double px = elems[2 * i], py = elems[2 * i + 1];
+                bb[0] = std::fmin(bb[0], px); bb[1] = std::fmin(bb[1], py);
+                bb[2] = std::fmax(bb[2], px); bb[3] = std::fmax(bb[3], py);
+            }
+            for (int k = 0; k < 4; ++k) ctx->bbox[k] = bb[k];
             if (hipMemcpyAsync(ctx->egeo.ptr, elems, ebytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
                 hipStreamSynchronize(stream) != hipSuccess)
                 rc = set_error(ctx, BEM_EHIP, "element upload");
@@ -468,7 +475,7 @@ void bem_destroy(bem_ctx* ctx)
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
-                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw};
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw, &ctx->sortw};
     for (DevBuf* b : bufs) release(*b);
     if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
     for (hipEvent_t e : ctx->ev)

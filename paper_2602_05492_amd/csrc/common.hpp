@@ -94,13 +94,14 @@ struct bem_ctx {
     // mixed forward sweep left its largest overflowing count (0: none overflowed)
     int near_slots = 1024;
     int* sweep_need = nullptr;
+    double bbox[4] = {0.0, 0.0, 1.0, 1.0};   // outer boundary's bounding box (x0, y0, x1, y1)
     double sigma_n = 0.0, shift = 0.0;
     std::string err;
     bem::ProfState prof;
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal, egeo;   // egeo: outer elements [M][4] (a, b)
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw, sortw;
 };
 
 namespace bem {

@@ -4,6 +4,7 @@
 // solve, trial evaluation on the same samples, accept / reject and damping
 // update (lambda / 10 on a decrease of the loss, * 10 otherwise).
 #include <cmath>
+#include <vector>
 
 #include "common.hpp"
 #include "sweep_common.hpp"
@@ -250,6 +251,25 @@ static int row_sums(bem_ctx* ctx, const void* u, bool f32, const double* T, int6
     return BEM_OK;
 }
 
+// Morton index of each sample's cell in a kCellSide x kCellSide grid over the outer boundary's
+// bounding box (coordinates clamped into it).  The mixed LM step visits the samples cell by cell,
+// so that the 64 samples of a wavefront are neighbours: a segment near one of them is then near
+// many, the near pairs of a wavefront fall into long runs of equal segments, and the adjoint
+// adds one set of sums per run instead of one per pair.
+constexpr int kCellBits = 5, kCellSide = 1 << kCellBits, kCells = kCellSide * kCellSide;
+__global__ void k_cell_labels(const double* __restrict__ x, int64_t N, double x0, double y0, double sx, double sy,
+                              int32_t* __restrict__ lab)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    // fmax first, so that a NaN coordinate lands in cell 0
+    const int cx = (int)fmin(fmax((x[2 * i] - x0) * sx, 0.0), (double)(kCellSide - 1));
+    const int cy = (int)fmin(fmax((x[2 * i + 1] - y0) * sy, 0.0), (double)(kCellSide - 1));
+    int m = 0;
+    for (int b = 0; b < kCellBits; ++b) m |= (((cx >> b) & 1) << (2 * b)) | (((cy >> b) & 1) << (2 * b + 1));
+    lab[i] = m;
+}
+
 // Largest overflowing near-pair count of a wavefront in a mixed sweep (0: no slice overflowed).
 static int read_need(bem_ctx* ctx, const int* dneed, hipStream_t s, int* need)
 {
@@ -302,6 +322,24 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     const bem_prec prec = mixed ? BEM_PREC_MIXED : BEM_PREC_FP64;
     st->accepted = 0;
     st->chol_retries = 0;
+    // mixed precision: samples and targets reordered cell by cell into a workspace (the step's
+    // results depend on the order only through rounding)
+    if (mixed && N > 0) {
+        const size_t lb = ((size_t)N * sizeof(int32_t) + 255) / 256 * 256;
+        if ((rc = ensure(ctx, ctx->sortw, lb + (size_t)N * 5 * sizeof(double), s))) return rc;
+        int32_t* lab = (int32_t*)ctx->sortw.ptr;
+        double* xs = (double*)((char*)ctx->sortw.ptr + lb);
+        double* Ts = xs + 2 * N;
+        const double bw = ctx->bbox[2] - ctx->bbox[0], bh = ctx->bbox[3] - ctx->bbox[1];
+        hipLaunchKernelGGL(k_cell_labels, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, ctx->bbox[0], ctx->bbox[1],
+                           bw > 0.0 ? kCellSide / bw : 0.0, bh > 0.0 ? kCellSide / bh : 0.0, lab);
+        std::vector<int64_t> off(kCells + 1);
+        if ((rc = run_partition(ctx, lab, N, kCells, x, T, xs, Ts, off.data(), s))) return rc;
+        if (off[kCells] != N) return set_error(ctx, BEM_EHIP, "sample reordering kept %lld of %lld samples",
+                                               (long long)off[kCells], (long long)N);
+        x = xs;
+        T = Ts;
+    }
     // mean colour
     double sums[3];
     if (st->mean_rule == 0) {

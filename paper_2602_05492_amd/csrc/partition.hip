@@ -1,8 +1,9 @@
 // partition.hip - samples grouped by subdomain (Sec. 4.1: every sample belongs to the one
 // subdomain its camera ray hits first; each subdomain's LM problem uses only its samples).
-// A stable counting sort by label: per-chunk label histograms (LDS), one exclusive scan in
-// label-major order, and a scatter in which each chunk hands out destinations in sample
-// order, so every subdomain's samples keep their original order.
+// A stable counting sort by label: per-chunk label histograms (LDS), an exclusive scan in
+// label-major order (per label, then over the label totals), and a scatter in which each
+// chunk hands out destinations in sample order, so every subdomain's samples keep their
+// original order.  The mixed LM step uses the same sort to visit samples cell by cell.
 #include "common.hpp"
 
 namespace bem {
@@ -27,46 +28,64 @@ __global__ void __launch_bounds__(256) k_part_hist(const int32_t* __restrict__ l
     for (int d = threadIdx.x; d < D; d += 256) cnt[(size_t)d * nb + blockIdx.x] = h[d];
 }
 
-// One block: exclusive scan of cnt [D * nb] (label-major) into base; off[d] = first row of
-// label d, off[D] = rows kept.  Thread t scans the contiguous chunk [t c, (t + 1) c).
-__global__ void __launch_bounds__(1024) k_part_scan(const int* __restrict__ cnt, int64_t n, int D, int nb,
-                                                    int64_t* __restrict__ base, int64_t* __restrict__ off)
+// Exclusive scan of cnt [D * nb] (label-major) into base, in two steps.  Block d scans its
+// label's nb chunk counts into base[d * nb + b] (relative to the label's first row) and writes
+// the label's total; then one block scans the D totals into off[d] (first row of label d,
+// off[D] = rows kept) and the scatter adds off[d] to base.
+__global__ void __launch_bounds__(256) k_part_scan_label(const int* __restrict__ cnt, int nb,
+                                                         int64_t* __restrict__ base, int64_t* __restrict__ total)
 {
-    __shared__ int64_t pre[1024];
+    __shared__ int64_t s[256];
+    const int d = blockIdx.x, t = threadIdx.x;
+    int64_t run = 0;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + t;
+        const int64_t c = b < nb ? cnt[(size_t)d * nb + b] : 0;
+        s[t] = c;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {      // inclusive scan of the 256 counts
+            const int64_t v = t >= o ? s[t - o] : 0;
+            __syncthreads();
+            s[t] += v;
+            __syncthreads();
+        }
+        if (b < nb) base[(size_t)d * nb + b] = run + s[t] - c;
+        run += s[255];
+        __syncthreads();
+    }
+    if (t == 0) total[d] = run;
+}
+
+__global__ void __launch_bounds__(1024) k_part_scan_totals(const int64_t* __restrict__ total, int D,
+                                                           int64_t* __restrict__ off)
+{
+    __shared__ int64_t s[kMaxLabels];
     const int t = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t lo = t * chunk < n ? t * chunk : n, hi = lo + chunk < n ? lo + chunk : n;
-    int64_t c = 0;
-    for (int64_t k = lo; k < hi; ++k) c += cnt[k];
-    pre[t] = c;
+    const int64_t c = t < D ? total[t] : 0;
+    s[t] = c;
     __syncthreads();
-    for (int s = 1; s < 1024; s <<= 1) {
-        const int64_t v = t >= s ? pre[t - s] : 0;
+    for (int o = 1; o < kMaxLabels; o <<= 1) {
+        const int64_t v = t >= o ? s[t - o] : 0;
         __syncthreads();
-        pre[t] += v;
+        s[t] += v;
         __syncthreads();
     }
-    int64_t run = pre[t] - c;
-    for (int64_t k = lo; k < hi; ++k) {
-        base[k] = run;
-        run += cnt[k];
-    }
-    __syncthreads();
-    for (int d = t; d < D; d += 1024) off[d] = base[(size_t)d * nb];
-    if (t == 1023) off[D] = pre[1023];
+    if (t < D) off[t] = s[t] - c;
+    if (t == kMaxLabels - 1) off[D] = s[t];
 }
 
 // Scatter of block b's chunk: 256 samples per round; a sample's destination is its label's
 // running position plus the number of earlier samples of the round with the same label.
 __global__ void __launch_bounds__(256) k_part_scatter(const int32_t* __restrict__ labels, int64_t N, int D, int nb,
-                                                      const int64_t* __restrict__ base, const double* __restrict__ x,
+                                                      const int64_t* __restrict__ base, const int64_t* __restrict__ off,
+                                                      const double* __restrict__ x,
                                                       const double* __restrict__ T, double* __restrict__ xo,
                                                       double* __restrict__ To)
 {
     __shared__ int64_t cur[kMaxLabels];
     __shared__ int lab[256];
     const int t = threadIdx.x;
-    for (int d = t; d < D; d += 256) cur[d] = base[(size_t)d * nb + blockIdx.x];
+    for (int d = t; d < D; d += 256) cur[d] = off[d] + base[(size_t)d * nb + blockIdx.x];
     const int64_t lo = (int64_t)blockIdx.x * kChunk, hi = lo + kChunk < N ? lo + kChunk : N;
     __syncthreads();
     for (int64_t r0 = lo; r0 < hi; r0 += 256) {
@@ -109,21 +128,23 @@ int run_partition(bem_ctx* ctx, const int32_t* labels, int64_t N, int D, const d
     if (D < 1 || D > kMaxLabels) return set_error(ctx, BEM_EINVAL, "D = %d labels not in [1, %d]", D, kMaxLabels);
     const int nb = N > 0 ? (int)((N + kChunk - 1) / kChunk) : 1;
     const int64_t n = (int64_t)D * nb;
-    // tmp5: cnt [D * nb] int | base [D * nb] int64 | off [D + 1] int64
+    // tmp5: cnt [D * nb] int | base [D * nb] int64 | off [D + 1] int64 | total [D] int64
     const size_t cnt_bytes = ((size_t)n * sizeof(int) + 255) / 256 * 256;
-    if ((rc = ensure(ctx, ctx->tmp5, cnt_bytes + (size_t)(n + D + 1) * sizeof(int64_t), s))) return rc;
+    if ((rc = ensure(ctx, ctx->tmp5, cnt_bytes + (size_t)(n + 2 * D + 1) * sizeof(int64_t), s))) return rc;
     int* cnt = (int*)ctx->tmp5.ptr;
     int64_t* base = (int64_t*)((char*)ctx->tmp5.ptr + cnt_bytes);
     int64_t* off = base + n;
+    int64_t* total = off + D + 1;
     if (N > 0) {
         hipLaunchKernelGGL(k_part_hist, dim3(nb), dim3(256), 0, s, labels, N, D, nb, cnt);
     } else {
         hipLaunchKernelGGL(k_part_hist, dim3(1), dim3(256), 0, s, labels, (int64_t)0, D, nb, cnt);
     }
-    hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(1024), 0, s, (const int*)cnt, n, D, nb, base, off);
+    hipLaunchKernelGGL(k_part_scan_label, dim3(D), dim3(256), 0, s, (const int*)cnt, nb, base, total);
+    hipLaunchKernelGGL(k_part_scan_totals, dim3(1), dim3(kMaxLabels), 0, s, (const int64_t*)total, D, off);
     if (N > 0)
-        hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, labels, N, D, nb, (const int64_t*)base, x, T, xo,
-                           To);
+        hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, labels, N, D, nb, (const int64_t*)base,
+                           (const int64_t*)off, x, T, xo, To);
     if ((rc = check_launch(ctx, "partition"))) return rc;
     if (hipMemcpyAsync(off_host, off, (size_t)(D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

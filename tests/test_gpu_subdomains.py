@@ -92,6 +92,27 @@ def test_L_shape_normal_equations_and_lm_step():
     assert bool(st.accepted) == bool(st_o.accepted) and e < 1e-8
 
 
+def test_L_shape_mixed_lm_step():
+    """Mixed precision / split-BF16 LM step on the L-shape (samples visited cell by cell over
+    the boundary's bounding box inside lm_step) against the oracle's step."""
+    ea, eb, th, x = _L_case(n_per_edge=12)
+    bnd = O.boundary_from_elements(ea, eb)
+    ctx = B.Context(segs_per_handle=8, elements=_elements(ea, eb), tile_rows=1024)
+    th0 = th + 0.01 * W.random_vector(57, th.shape)
+    T = O.evaluate(th, x, np.full(3, 0.5), 8, 1e-2, bnd) + 0.1 * W.random_vector(58, (len(x), 3))
+    st_o = O.LMState(lam=1e-1, mean_rule=0)
+    th_o, st_o = O.lm_step(th0, x, T, st_o, 8, 1e-2, bnd)
+    d = dev(th0)
+    st = B.new_lm_state(1e-1, 0)
+    ctx.lm_step(d, dev(x), dev(T), st, "bf16x3_mfma", "mixed")
+    e = _rel(host(d) - th0, th_o - th0) if st_o.accepted else float(np.abs(host(d) - th0).max())
+    log(f"L-shape mixed lm: accepted {st.accepted}/{st_o.accepted}, loss {st.loss_before:.9e}/{st_o.loss_before:.9e}, "
+        f"step rel err {e:.3e}")
+    assert st.loss_before == pytest.approx(st_o.loss_before, rel=1e-5)
+    assert bool(st.accepted) == bool(st_o.accepted)
+    assert e < 1e-2
+
+
 def test_build_elements_validation():
     with pytest.raises(B.BemError):
         B.Context(segs_per_handle=4, elements=np.zeros((1, 4)))
