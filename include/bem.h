@@ -245,8 +245,12 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * With regularisation terms set (bem_set_regularization) their gradient and
  * Hessian are added to g and H, and their value to L0 and L1 (snapping pairs
  * chosen at theta); state->reg_value and state->snap_pairs report them.
- * MIXED: if the near-pair list of the sweep at theta overflows, its capacity
- * is raised and the sweep repeated before the adjoint and the normal equations.
+ * MIXED: the step works on a copy of x and target reordered cell by cell (a
+ * 32 x 32 grid of Morton-ordered cells over the outer boundary's bounding box),
+ * so that neighbouring samples share wavefronts; x and target themselves are
+ * not modified, and the result depends on the order only through rounding.
+ * If the near-pair list of the sweep at theta overflows, its capacity is raised
+ * and the sweep repeated before the adjoint and the normal equations.
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.
