@@ -76,8 +76,10 @@ typedef enum {
  *        reduction over samples is finished in float64.  The float64 sums of
  *        near pairs in bem_eval and bem_vjp are accumulated with atomics, so
  *        MIXED results can differ in their last bits from call to call; FP64
- *        results are reproducible.  The boundary system, its solves and the LM
- *        solve are float64 in both modes.
+ *        results are reproducible.  The boundary matrix, its factorisation and
+ *        solves and the LM solve are float64 in both modes; the boundary
+ *        right-hand side (the handles' field at the elements' Gauss points)
+ *        takes the same float32 / float64 split as the sweeps in MIXED.
  *        Near pairs go to a list with a per-context capacity per 64 samples
  *        (1024 at first, at most 16384 and 4 GiB of list); the samples whose
  *        pairs do not fit are evaluated by a slower sweep that handles their

@@ -157,14 +157,14 @@ int prepare_forward_tables(bem_ctx* ctx, const double* theta, int32_t H, hipStre
 }
 
 // expand -> F -> U -> element table.  Leaves F in ctx->F and U in ctx->U.
-int prepare_forward(bem_ctx* ctx, const double* theta, int32_t H, hipStream_t s)
+int prepare_forward(bem_ctx* ctx, const double* theta, int32_t H, bool mixed, hipStream_t s)
 {
     int rc;
     const int K = H * ctx->opts.segs_per_handle;
     if ((rc = ensure(ctx, ctx->F, (size_t)ctx->M * 3 * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->U, (size_t)ctx->M * 3 * sizeof(double), s))) return rc;
     if ((rc = launch_expand(ctx, theta, H, s))) return rc;
-    if ((rc = launch_boundary_rhs(ctx, K, (double*)ctx->F.ptr, s))) return rc;
+    if ((rc = launch_boundary_rhs(ctx, K, (double*)ctx->F.ptr, mixed, s))) return rc;
     if ((rc = launch_boundary_solve(ctx, (const double*)ctx->F.ptr, (double*)ctx->U.ptr, false, s))) return rc;
     return launch_pack_elements(ctx, (const double*)ctx->U.ptr, s);
 }
@@ -285,7 +285,7 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
     if (!cbar) return set_error(ctx, BEM_EINVAL, "cbar is null");
     if (N > 0 && !u) return set_error(ctx, BEM_EINVAL, "u is null");
     if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
-    if ((rc = prepare_forward(ctx, theta, H, stream))) return rc;
+    if ((rc = prepare_forward(ctx, theta, H, prec == BEM_PREC_MIXED, stream))) return rc;
     const int K = H * ctx->opts.segs_per_handle;
     if (prec == BEM_PREC_FP64) return launch_sweep_f64(ctx, x, N, K, cbar, (double*)u, stream);
     return launch_sweep_mixed(ctx, x, N, K, cbar, (float*)u, stream);
@@ -404,7 +404,7 @@ int bem_boundary_solve(bem_ctx* ctx, const double* theta, int32_t H, double* F, 
 {
     int rc = check_common(ctx, theta, H, nullptr, 0);
     if (rc) return rc;
-    if ((rc = prepare_forward(ctx, theta, H, stream))) return rc;
+    if ((rc = prepare_forward(ctx, theta, H, false, stream))) return rc;
     const size_t bytes = (size_t)ctx->M * 3 * sizeof(double);
     if (F && hipMemcpyAsync(F, ctx->F.ptr, bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "copy F");

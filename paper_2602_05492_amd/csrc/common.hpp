@@ -132,7 +132,7 @@ int launch_assemble(bem_ctx* ctx, hipStream_t s);
 int launch_factor(bem_ctx* ctx, hipStream_t s);
 // forward.hip
 int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
-int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s);
+int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, bool mixed, hipStream_t s);
 int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpose, hipStream_t s);
 int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
 int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
@@ -157,9 +157,9 @@ int run_prune(bem_ctx* ctx, double* theta, int H, double thr, int* H_out, hipStr
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
             double* grad, hipStream_t s, const NearList* pre = nullptr);
 // api.hip: expand + element tables (no boundary solve); and the whole forward set-up
-// (expand, boundary right-hand side, boundary solve, element tables)
+// (expand, boundary right-hand side (float32 far pairs when mixed), boundary solve, element tables)
 int prepare_forward_tables(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
-int prepare_forward(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
+int prepare_forward(bem_ctx* ctx, const double* theta, int H, bool mixed, hipStream_t s);
 // gemm.hip
 int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta, const double* B,
              int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles);

@@ -112,6 +112,53 @@ __global__ void k_boundary_rhs(const double* __restrict__ seg, int K, const doub
     }
 }
 
+// Mixed-precision boundary right-hand side: as k_boundary_rhs, with the pairs of a Gauss
+// point and a segment in float32 from the float32 tables unless they are near (the sweeps'
+// predicate), then in float64; sums in float64.
+__global__ void k_boundary_rhs_mixed(const double* __restrict__ seg, const float* __restrict__ seg32, int K,
+                                     const double* __restrict__ eg, double eps2, float near2, double* __restrict__ F)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    double ax, ay, bx, by;
+    load_element(eg, i, ax, ay, bx, by);
+    const double mx = 0.5 * (ax + bx), my = 0.5 * (ay + by), hx = 0.5 * (bx - ax), hy = 0.5 * (by - ay);
+    const double half = sqrt(hx * hx + hy * hy);
+    const double node[3] = {-kGaussNode, 0.0, kGaussNode};
+    const double w[3] = {kGaussW0 * half, kGaussW1 * half, kGaussW0 * half};
+    double px[3], py[3];
+    float pxf[3], pyf[3];
+    for (int q = 0; q < 3; ++q) {
+        px[q] = mx + node[q] * hx;
+        py[q] = my + node[q] * hy;
+        pxf[q] = (float)px[q];
+        pyf[q] = (float)py[q];
+    }
+    const float eps2f = (float)eps2;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const float* s32 = seg32 + (size_t)k * kSegStride;
+        const SegGeom<float> gf = load_geom(s32);
+        for (int q = 0; q < 3; ++q) {
+            if (near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, pxf[q], pyf[q], near2)) {
+                const double* s = seg + (size_t)k * kSegStride;
+                const Moments<double> mo = seg_moments<double, DevF64>(load_geom(s), px[q], py[q], eps2);
+                for (int c = 0; c < 3; ++c)
+                    acc[c] += w[q] * (mo.da * s[kWdA + c] + mo.db * s[kWdB + c] + mo.sa * s[kWcA + c] + mo.sb * s[kWcB + c]);
+            } else {
+                const Moments<float> mo = seg_moments<float, DevF32, false>(gf, pxf[q], pyf[q], eps2f);
+                for (int c = 0; c < 3; ++c)
+                    acc[c] += w[q] * (double)(mo.da * s32[kWdA + c] + mo.db * s32[kWdB + c] + mo.sa * s32[kWcA + c] +
+                                              mo.sb * s32[kWcB + c]);
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        const double r = block_reduce(acc[c], red);
+        if (threadIdx.x == 0) F[(size_t)i * 3 + c] = r;
+    }
+}
+
 // out[i, c] = sum_j A+[i, j] in[j, c]   (transpose: sum_j A+[j, i] in[j, c])
 __global__ void k_apply_pinv(const double* __restrict__ Ap, int M, const double* __restrict__ in, double* __restrict__ out,
                              int transpose)
@@ -188,14 +235,19 @@ int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s)
     return check_launch(ctx, "expand");
 }
 
-int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, hipStream_t s)
+int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, bool mixed, hipStream_t s)
 {
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
     {
         ProfScope ps_(ctx, PT_BOUNDARY, s);
-        hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K,
-                           (const double*)ctx->egeo.ptr,
-                           eps2, F);
+        if (mixed) {
+            const double nf = 2.0 * ctx->opts.near_factor;
+            hipLaunchKernelGGL(k_boundary_rhs_mixed, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr,
+                               (const float*)ctx->seg32.ptr, K, (const double*)ctx->egeo.ptr, eps2, (float)(nf * nf), F);
+        } else {
+            hipLaunchKernelGGL(k_boundary_rhs, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr, K,
+                               (const double*)ctx->egeo.ptr, eps2, F);
+        }
     }
     return check_launch(ctx, "boundary_rhs");
 }

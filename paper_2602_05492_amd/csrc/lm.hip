@@ -358,7 +358,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     // capacity is raised and the sweep repeated, so that they find every near pair in it.
     NearList nl{};
     if (mixed) {
-        if ((rc = prepare_forward(ctx, theta, H, s))) return rc;
+        if ((rc = prepare_forward(ctx, theta, H, true, s))) return rc;
         for (int pass = 0;; ++pass) {
             if ((rc = launch_sweep_mixed(ctx, x, N, H * ctx->opts.segs_per_handle, st->cbar, (float*)u, s, &nl)))
                 return rc;
