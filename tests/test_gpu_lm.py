@@ -179,6 +179,28 @@ def test_lm_iterations_medium_full_size_decrease():
     assert st.loss_after < 0.5 * wl.spec.sigma ** 2 * 3 * 1.2
 
 
+def test_lm_step_full_size_direction_vs_fp64():
+    """LM workload at full size (256 cubic handles x 32 segments, 2,097,152 samples): the
+    split-BF16 / mixed step and the FP32-MFMA / mixed step from the same start on the same batch
+    stay within 1.5e-3 (relative, 2-norm) of the FP64 step (measured 1.1e-3 and 8.3e-4).  Guards
+    the mixed path's accumulation order: with the samples summed in plain cell order the two
+    read 2.0e-3 and 2.2e-3."""
+    wl = W.make_config(5)
+    ctx = ctx_for(wl.S)
+    x = dev(wl.samples(0))
+    T = ctx.eval(dev(wl.theta_true), x, wl.cbar_true, "fp64") + wl.spec.sigma * dev(wl.noise(0))
+    th0 = dev(wl.theta0)
+    d = {}
+    for gram, prec in (("fp64", "fp64"), ("bf16x3_mfma", "mixed"), ("fp32_mfma", "mixed")):
+        th = th0.clone()
+        st = B.new_lm_state(wl.lam0, 0)
+        ctx.lm_step(th, x, T, st, gram, prec)
+        d[gram] = (th - th0).flatten()
+    e = {g: float(torch.linalg.norm(d[g] - d["fp64"]) / torch.linalg.norm(d["fp64"])) for g in ("bf16x3_mfma", "fp32_mfma")}
+    log(f"full-size LM step direction vs FP64: {e}")
+    assert e["bf16x3_mfma"] < 1.5e-3 and e["fp32_mfma"] < 1.5e-3
+
+
 def test_lm_step_rejects_non_finite_parameters():
     wl = W.make_config(1)
     ctx = ctx_for(wl.S)
