@@ -170,7 +170,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
 int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, double* J, hipStream_t s);
 // gram_mfma.hip
 int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-                     const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, hipStream_t s);
+                     const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, bool accumulate,
+                     hipStream_t s);
 int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
               const double* r, double* R, double* Rp, hipStream_t s);
 constexpr int kXrPartials = 32;   // sample-block groups of the split-BF16 X r (workspace kXrPartials * W * 3)

@@ -34,7 +34,18 @@ __device__ inline floatx4 load_f32x4(const float* __restrict__ p, int64_t k, int
     return v;
 }
 
-__device__ inline void epilogue(const floatx16 (&acc)[2][2], int64_t rbase, int64_t cbase, int W, double* __restrict__ G)
+// Zero output tile [row0, row0 + ts) x [col0, col0 + ts) of G (clipped to W): the part of a work entry
+// that holds no samples, when the Gram writes rather than accumulates.
+__device__ inline void zero_tile(double* __restrict__ G, int64_t row0, int64_t col0, int ts, int W)
+{
+    for (int e = threadIdx.x; e < ts * ts; e += blockDim.x) {
+        const int64_t i = row0 + e / ts, j = col0 + e % ts;
+        if (i < W && j < W) G[i * W + j] = 0.0;
+    }
+}
+
+__device__ inline void epilogue(const floatx16 (&acc)[2][2], int64_t rbase, int64_t cbase, int W, int accumulate,
+                                double* __restrict__ G)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 31, lk = lane >> 5;
@@ -43,7 +54,7 @@ __device__ inline void epilogue(const floatx16 (&acc)[2][2], int64_t rbase, int6
             for (int r = 0; r < 16; ++r) {
                 const int64_t i = rbase + 32 * mi + 8 * (r >> 2) + 4 * lk + (r & 3);
                 const int64_t j = cbase + 32 * nj + li;
-                if (i < W && j < W) G[i * W + j] += (double)acc[mi][nj][r];
+                if (i < W && j < W) G[i * W + j] = (accumulate ? G[i * W + j] : 0.0) + (double)acc[mi][nj][r];
             }
 }
 
@@ -60,7 +71,7 @@ __device__ inline int work_index(int nwork)
 
 __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, int64_t ld, int W, int64_t n_all,
                                                   const int* __restrict__ work, int nwork, int64_t kchunk,
-                                                  double* __restrict__ G, int64_t gstride)
+                                                  double* __restrict__ G, int64_t gstride, int accumulate)
 {
     const int wi = work_index(nwork);
     if (wi >= nwork) return;
@@ -70,8 +81,11 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
     const int64_t cbase = (int64_t)work[3 * wi + 1] * 128 + 64 * (wave & 1);
     const int64_t kb = (int64_t)work[3 * wi + 2] * kchunk;
     const int64_t n = kb + kchunk < n_all ? kb + kchunk : n_all;
-    if (kb >= n) return;
     G += (int64_t)work[3 * wi + 2] * gstride;
+    if (kb >= n) {
+        if (!accumulate) zero_tile(G, (int64_t)work[3 * wi] * 128, (int64_t)work[3 * wi + 1] * 128, 128, W);
+        return;
+    }
     floatx16 acc[2][2];
     for (int mi = 0; mi < 2; ++mi)
         for (int nj = 0; nj < 2; ++nj)
@@ -99,7 +113,7 @@ __global__ void __launch_bounds__(256) k_gram_f32(const float* __restrict__ X, i
                 for (int nj = 0; nj < 2; ++nj)
                     acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi][s], b[nj][s], acc[mi][nj], 0, 0, 0);
     }
-    epilogue(acc, rbase, cbase, W, G);
+    epilogue(acc, rbase, cbase, W, accumulate, G);
 }
 
 // Split-bfloat16 Gram with LDS staging: a block of 8 wavefronts owns a 256x256
@@ -125,7 +139,7 @@ __device__ inline int g2_lds(int r, int c)   // element offset of chunk c of row
 __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl,
                                                          int W, int n_all, const int* __restrict__ work,
                                                          int nwork, int kchunk, double* __restrict__ G,
-                                                         int64_t gstride)
+                                                         int64_t gstride, int accumulate)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sm0[4][G2_T * G2_BK];   // [A hi, A lo, B hi, B lo]
     __shared__ __attribute__((aligned(16))) uint16_t sm1[4][G2_T * G2_BK];
@@ -139,8 +153,11 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
     // samples [kb, n) of this entry's part; partial Gram of the part
     const int kb = work[3 * wi + 2] * kchunk;
     const int n = kb + kchunk < n_all ? kb + kchunk : n_all;
-    if (kb >= n) return;                                   // part beyond a ragged last tile
     G += (int64_t)work[3 * wi + 2] * gstride;
+    if (kb >= n) {                                         // part beyond a ragged last tile
+        if (!accumulate) zero_tile(G, row0, col0, G2_T, W);
+        return;
+    }
     const int wr = wave >> 1, wc = wave & 1;
     const int W32 = W << 5;    // elements per 32-sample block of the tile
     // direct loads: this wavefront fills row blocks wave and wave + 8 (16 rows each) of each slab;
@@ -242,8 +259,9 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
 #undef G2_STEP
 #undef G2_ORDER
 #undef G2_MULTIPLY
-    // epilogue: G += acc.  A tile inside the matrix reads its 16 values of an MFMA tile in one batch
-    // (one wait instead of 16); tiles at the matrix edge go element by element.
+    // epilogue: G += acc (G = acc for the first sample tile).  A tile inside the matrix reads its 16
+    // values of an MFMA tile in one batch (one wait instead of 16); tiles at the matrix edge go
+    // element by element.
     const bool inside = row0 + G2_T <= W && col0 + G2_T <= W;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -255,14 +273,15 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
                 double* g = G + (int64_t)ib * W + j;
                 double v[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[r] = g[(int64_t)(8 * (r >> 2) + (r & 3)) * W];
+                for (int r = 0; r < 16; ++r) v[r] = accumulate ? g[(int64_t)(8 * (r >> 2) + (r & 3)) * W] : 0.0;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) g[(int64_t)(8 * (r >> 2) + (r & 3)) * W] = v[r] + (double)acc[mi][nj][r];
             } else {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int i = ib + 8 * (r >> 2) + (r & 3);
-                    if (i < W && j < W) G[(int64_t)i * W + j] += (double)acc[mi][nj][r];
+                    if (i < W && j < W)
+                        G[(int64_t)i * W + j] = (accumulate ? G[(int64_t)i * W + j] : 0.0) + (double)acc[mi][nj][r];
                 }
             }
         }
@@ -345,9 +364,11 @@ __global__ void k_xr_finish(const double* __restrict__ Rp, int W, int groups, do
 }  // namespace
 
 // G[part] += X X^T over the work entries (row tile, column tile, part): part p covers
-// samples [p * kchunk, (p + 1) * kchunk) of the tile and adds into G + p * gstride.
+// samples [p * kchunk, (p + 1) * kchunk) of the tile and adds into G + p * gstride (accumulate = 0:
+// writes, for the first sample tile; entries outside the work list are not touched).
 int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-                     const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, hipStream_t s)
+                     const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, bool accumulate,
+                     hipStream_t s)
 {
     if (n <= 0 || nwork <= 0) return BEM_OK;
     const int grid = 8 * ((nwork + 7) / 8);
@@ -357,13 +378,13 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
             // blocked tile (ld unused); element offsets inside one operand array are 32-bit
             // (W * tile rows < 2^31 is checked by the caller)
             hipLaunchKernelGGL(k_gram_bf16x3_lds, dim3(grid), dim3(512), 0, s, (const uint16_t*)Xhi, Xlo, W, (int)n,
-                               work, nwork, (int)kchunk, G, gstride);
+                               work, nwork, (int)kchunk, G, gstride, accumulate ? 1 : 0);
         }
     else
         {
             ProfScope ps_(ctx, PT_GRAM_MFMA, s);
             hipLaunchKernelGGL(k_gram_f32, dim3(grid), dim3(256), 0, s, (const float*)Xhi, ld, W, n, work, nwork, kchunk,
-                               G, gstride);
+                               G, gstride, accumulate ? 1 : 0);
         }
     return check_launch(ctx, "gram_mfma");
 }

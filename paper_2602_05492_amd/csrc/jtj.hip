@@ -711,13 +711,19 @@ static std::vector<int> gram_work(const std::vector<int>& tiles, int parts)
 }
 
 namespace {
-// G[0] += G[1] + ... + G[parts - 1] (fixed order)
-__global__ void k_sum_parts(double* __restrict__ G, int parts, int64_t len)
+// G[0] += G[1] + ... + G[parts - 1] (fixed order) over the ts x ts output tile of work entry
+// blockIdx.x (blockDim.x = ts, a thread per column)
+__global__ void __launch_bounds__(256) k_sum_parts(double* __restrict__ G, int parts, int64_t W,
+                                                   const int* __restrict__ work, int ts)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
-        double v = G[i];
-        for (int p = 1; p < parts; ++p) v += G[(size_t)p * len + i];
-        G[i] = v;
+    const int64_t r0 = (int64_t)work[3 * blockIdx.x] * ts, c0 = (int64_t)work[3 * blockIdx.x + 1] * ts;
+    const int64_t c = c0 + threadIdx.x % ts;
+    for (int64_t r = r0 + threadIdx.x / ts; r < r0 + ts; r += blockDim.x / ts) {
+        if (r >= W || c >= W) continue;
+        const size_t e = (size_t)r * W + c;
+        double v = G[e];
+        for (int p = 1; p < parts; ++p) v += G[(size_t)p * W * W + e];
+        G[e] = v;
     }
 }
 }  // namespace
@@ -787,7 +793,9 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     double* G = R + (size_t)W * 3;
     double* Rp = G + (size_t)parts * W * W;
     double* r64 = (double*)ctx->tmp2.ptr;
-    if ((rc = fill_f64(ctx, R, (int64_t)parts * W * W + W * 3, 0.0, s))) return rc;
+    // the first sample tile's Gram writes G (every entry of its tile list, in every part), so only
+    // J^T r's partials (and G itself without samples) start from zero
+    if ((rc = fill_f64(ctx, R, N > 0 ? W * 3 : (int64_t)parts * W * W + W * 3, 0.0, s))) return rc;
     // Jtr == nullptr: J^T J only (the LM step takes its gradient from the adjoint)
     const bool want_r = Jtr != nullptr;
     if (N > 0 && want_r) {
@@ -840,7 +848,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
-                rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, 1.0, G, W, s, dtiles, ntiles);
+                rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, it > 0 ? 1.0 : 0.0, G, W, s,
+                              dtiles, ntiles);
             }
             if (rc) return rc;
             if (want_r &&
@@ -851,7 +860,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
-            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, sg)))
+            if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, it > 0, sg)))
                 return rc;
             if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
         } else {
@@ -863,7 +872,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
-            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, sg)))
+            if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, it > 0, sg)))
                 return rc;
             if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
         }
@@ -873,8 +882,9 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         if (hipEventRecord(ctx->ev[5], sg) != hipSuccess || hipStreamWaitEvent(s, ctx->ev[5], 0) != hipSuccess)
             return set_error(ctx, BEM_EHIP, "stream join");
     }
-    if (parts > 1) {
-        hipLaunchKernelGGL(k_sum_parts, dim3(4096), dim3(256), 0, s, G, parts, W * W);
+    if (parts > 1 && N > 0) {
+        // the first ntiles / parts work entries are part 0's, one per tile of the list
+        hipLaunchKernelGGL(k_sum_parts, dim3(ntiles / parts), dim3(256), 0, s, G, parts, W, dtiles, ts);
         if ((rc = check_launch(ctx, "gram parts"))) return rc;
     }
     // contraction per channel

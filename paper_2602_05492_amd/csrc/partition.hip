@@ -10,7 +10,7 @@ namespace bem {
 
 namespace {
 
-constexpr int kChunk = 4096;        // samples per block
+constexpr int kChunk = 1024;        // samples per block
 constexpr int kMaxLabels = 1024;
 
 __global__ void __launch_bounds__(256) k_part_hist(const int32_t* __restrict__ labels, int64_t N, int D, int nb,

@@ -77,6 +77,26 @@ def test_jtj_default_tiles_absorb_short_tail():
     assert eh < 1e-4 and eg < 1e-3
 
 
+@pytest.mark.parametrize("gram", ["bf16x3_mfma", "fp32_mfma"])
+def test_jtj_tiny_sample_counts(gram):
+    """N = 2,000 then 1, 40, 64 and 65 samples on one context: the first (here only) sample tile's
+    Gram writes its partial Grams, the parts that hold no samples are zeroed, and nothing of the
+    previous, larger call survives; N = 0 gives zeros.  Against the oracle, bars as above."""
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S)
+    th = dev(wl.theta_true)
+    for N in (2000, 1, 40, 64, 65):
+        x = W.random_points(60 + N, N)
+        r = W.random_vector(61 + N, (N, 3))
+        Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
+        JtJ, Jtr = ctx.jtj(th, dev(x), dev(r, torch.float32), gram, "mixed")
+        eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+        log(f"jtj {gram} N={N}: rel err JtJ {eh:.3e} Jtr {eg:.3e}")
+        assert eh < 1e-4 and eg < 1e-3
+    JtJ, Jtr = ctx.jtj(th, dev(np.zeros((0, 2))), dev(np.zeros((0, 3)), torch.float32), gram, "mixed")
+    assert not host(JtJ).any() and not host(Jtr).any()
+
+
 def test_jtj_medium_fp64_matches_oracle():
     wl = W.make_config(2)
     ctx = ctx_for(wl.S)
