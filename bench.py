@@ -254,8 +254,8 @@ def main() -> int:
         return lm_curve(args.lm_curve, args.gram, args.prec, args.workload, args.compat)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built "
-              "(every GPU box here has a single MI355X); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built; "
+              "run with --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np
