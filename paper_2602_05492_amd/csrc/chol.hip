@@ -218,13 +218,14 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* __restrict__ A, int6
 // Linv pointing at block kb's inverse [64][64].
 // 256 threads; the block stages its 64 rows and Linv_kk in LDS with coalesced loads and
 // thread (w, t) forms column t of rows w, w + 4, ...
+// skip: row blocks below the diagonal block left out (the first one may come from k_next_diag).
 __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P, int kb,
-                                               const double* __restrict__ Linv)
+                                               const double* __restrict__ Linv, int skip)
 {
     __shared__ double R[NB][NB];        // rows (read by broadcast)
     __shared__ double LiT[NB][NB];      // LiT[k][j] = Linv[j][k]
     const int64_t o = (int64_t)kb * NB;
-    const int64_t r0 = o + NB + (int64_t)blockIdx.x * NB;
+    const int64_t r0 = o + NB + (int64_t)(blockIdx.x + skip) * NB;
     const int nr = (int)(P - r0 < NB ? P - r0 : NB);
     const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
     // loads first (all in flight; rows past the matrix read row r0 and are then zeroed)
@@ -266,8 +267,7 @@ __global__ void __launch_bounds__(256) k_panel(double* __restrict__ A, int64_t P
 // Accumulator element q of lane l is row 4 q + l / 16, column l mod 16 of its 16 x 16 tile.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kSyrkLd = 72;              // LDS row stride (doubles) of the transposed slices
-// mode 0: every tile; 1: the first tile column only (J = 0: the next diagonal block and panel);
-// 2: the other tiles (J >= 1).
+// mode 0: every tile; 1: every tile but the first diagonal one (I = J = 0, updated by k_next_diag).
 __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t P, int kb, int nt, int mode)
 {
     __shared__ double SI[NB][kSyrkLd];   // [k][row] of the panel rows of tile row I
@@ -276,17 +276,11 @@ __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t 
     const int64_t rem = P - o2;
     // tile (I, J), I >= J, from the linear index b = I (I + 1) / 2 + J
     const int b = blockIdx.x;
-    int I, J;
-    if (mode == 1) {
-        I = b;
-        J = 0;
-    } else {
-        I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-        while ((I + 1) * (I + 2) / 2 <= b) ++I;
-        while (I * (I + 1) / 2 > b) --I;
-        J = b - I * (I + 1) / 2;
-        if (mode == 2 && J == 0) return;
-    }
+    if (mode == 1 && b == 0) return;
+    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    while (I * (I + 1) / 2 > b) --I;
+    const int J = b - I * (I + 1) / 2;
     if (I >= nt) return;
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -345,6 +339,101 @@ __global__ void __launch_bounds__(256) k_syrk64(double* __restrict__ A, int64_t 
                 const int64_t gr = rI + 32 * wr + 16 * i + 4 * q + (l >> 4);
                 const int64_t gc = rJ + 32 * wc + 16 * j + (l & 15);
                 if (gr < rem && gc <= gr) A[(o2 + gr) * P + o2 + gc] = c[i][j][q] - acc[i][j][q];
+            }
+}
+
+// Look-ahead of step kb (one block): the first row block of the panel,
+// L1 = A[o2:o2+64, o:o+64] Linv_kb^T, written in place, and the next diagonal block's update
+// A[o2:o2+64, o2:o2+64] -= L1 L1^T on its lower triangle, o2 = 64 (kb + 1).  Both products on
+// float64 MFMA with the operand and accumulator layout of k_syrk64; the rows of L1 past the
+// matrix are zero (their rows of A are neither read nor written).  Requires P > o2.
+__global__ void __launch_bounds__(256) k_next_diag(double* __restrict__ A, int64_t P, int kb,
+                                                   const double* __restrict__ Linv)
+{
+    __shared__ double SI[NB][kSyrkLd];   // [k][row]: A's row block, then L1
+    __shared__ double SJ[NB][kSyrkLd];   // [k][j] = Linv_kb[j][k]
+    const int64_t o = (int64_t)kb * NB, o2 = o + NB;
+    const int nr = (int)(P - o2 < NB ? P - o2 : NB);
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    // every global load first (entries past the matrix or above the diagonal read an in-bounds
+    // one and are then replaced): this thread's 16 entries of the diagonal block, the row block
+    // and the inverse
+    double c[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gr = 32 * wr + 16 * i + 4 * q + (l >> 4), gc = 32 * wc + 16 * j + (l & 15);
+                const bool in = gr < nr && gc <= gr;
+                c[i][j][q] = A[(o2 + (in ? gr : 0)) * P + o2 + (in ? gc : 0)];
+            }
+    double va[NB * NB / 256], vl[NB * NB / 256];
+#pragma unroll
+    for (int m = 0; m < NB * NB / 256; ++m) {
+        const int e = tid + 256 * m, r = e >> 6, k = e & 63;
+        va[m] = A[(o2 + (r < nr ? r : 0)) * P + o + k];
+        vl[m] = Linv[(size_t)r * NB + k];
+    }
+#pragma unroll
+    for (int m = 0; m < NB * NB / 256; ++m) {
+        const int e = tid + 256 * m, r = e >> 6, k = e & 63;
+        SI[k][r] = r < nr ? va[m] : 0.0;
+        SJ[k][r] = vl[m];
+    }
+    __syncthreads();
+    d4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NB; ks += 4) {
+        const int kk = ks + (l >> 4), rr = l & 15;
+        const double a0 = SI[kk][32 * wr + rr], a1 = SI[kk][32 * wr + 16 + rr];
+        const double b0 = SJ[kk][32 * wc + rr], b1 = SJ[kk][32 * wc + 16 + rr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();                    // every wave is done reading SI
+    // L1 to A and, transposed ([k = column][row]), back into SI
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gr = 32 * wr + 16 * i + 4 * q + (l >> 4), gc = 32 * wc + 16 * j + (l & 15);
+                SI[gc][gr] = acc[i][j][q];
+                if (gr < nr) A[(o2 + gr) * P + o + gc] = acc[i][j][q];
+            }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NB; ks += 4) {
+        const int kk = ks + (l >> 4), rr = l & 15;
+        const double a0 = SI[kk][32 * wr + rr], a1 = SI[kk][32 * wr + 16 + rr];
+        const double b0 = SI[kk][32 * wc + rr], b1 = SI[kk][32 * wc + 16 + rr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int gr = 32 * wr + 16 * i + 4 * q + (l >> 4), gc = 32 * wc + 16 * j + (l & 15);
+                if (gr < nr && gc <= gr) A[(o2 + gr) * P + o2 + gc] = c[i][j][q] - acc[i][j][q];
             }
 }
 
@@ -515,37 +604,43 @@ int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A,
     hipLaunchKernelGGL(k_damp, dim3(blocks_for(P, 256), P), dim3(256), 0, s, H, P, lam, dscal, A);
     if ((rc = fill_i32(ctx, dflag, 1, 0, s))) return rc;
     ProfScope ps_(ctx, PT_CHOLESKY, s);
-    // Look-ahead: after step kb's panel, the first tile column of the trailing update (the next
-    // diagonal block and panel) runs on the caller's stream and the next step's diagonal block
-    // and panel follow it there, while the rest of the trailing update runs on the second
-    // stream; the next step's first-column update waits for that rest.
+    // Look-ahead: only the next diagonal block's inputs stay on the caller's stream (k_next_diag:
+    // the panel's first row block and that block's update, then its factor); the rest of the
+    // panel and the trailing update run on the second stream.  Step kb's trailing update waits
+    // for k_next_diag(kb) (it reads the first row block), and k_next_diag(kb + 1) waits for that
+    // update (it reads the tiles it wrote).  The two streams touch disjoint tiles meanwhile.
     hipStream_t s2 = s;
     const bool ahead = nblk > 2;
     if (ahead && (rc = aux_stream(ctx, &s2))) return rc;
-    hipEvent_t evA = ctx->ev[0], evB = ctx->ev[1];
-    if (ahead && (hipEventRecord(evB, s) != hipSuccess || hipStreamWaitEvent(s2, evB, 0) != hipSuccess))
-        return set_error(ctx, BEM_EHIP, "cholesky fork");
+    hipEvent_t evP = ctx->ev[0], evN = ctx->ev[1], evS = ctx->ev[6];
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, 0, dflag, linv);
     for (int kb = 0; kb < nblk; ++kb) {
         double* Li = linv + (size_t)kb * NB * NB;
         const int64_t rem = P - (int64_t)(kb + 1) * NB;
         if (rem <= 0) break;
         const int nt = blocks_for(rem, NB);
-        hipLaunchKernelGGL(k_panel, dim3(nt), dim3(256), 0, s, A, P, kb, (const double*)Li);
         if (!ahead) {
+            hipLaunchKernelGGL(k_panel, dim3(nt), dim3(256), 0, s, A, P, kb, (const double*)Li, 0);
             hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, P, kb, nt, 0);
             hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
             continue;
         }
-        if (kb > 0 && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky wait");
-        hipLaunchKernelGGL(k_syrk64, dim3(nt), dim3(256), 0, s, A, P, kb, nt, 1);
-        if (hipEventRecord(evA, s) != hipSuccess || hipStreamWaitEvent(s2, evA, 0) != hipSuccess)
+        // second stream: the panel below the next diagonal block, once block kb is factored
+        if (hipEventRecord(evP, s) != hipSuccess || hipStreamWaitEvent(s2, evP, 0) != hipSuccess)
             return set_error(ctx, BEM_EHIP, "cholesky event");
-        if (nt > 1) hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s2, A, P, kb, nt, 2);
-        if (hipEventRecord(evB, s2) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky event");
+        if (nt > 1) hipLaunchKernelGGL(k_panel, dim3(nt - 1), dim3(256), 0, s2, A, P, kb, (const double*)Li, 1);
+        // caller's stream: the next diagonal block, once the previous trailing update is done
+        if (kb > 0 && hipStreamWaitEvent(s, evS, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky wait");
+        hipLaunchKernelGGL(k_next_diag, dim3(1), dim3(256), 0, s, A, P, kb, (const double*)Li);
+        if (nt > 1) {
+            if (hipEventRecord(evN, s) != hipSuccess || hipStreamWaitEvent(s2, evN, 0) != hipSuccess)
+                return set_error(ctx, BEM_EHIP, "cholesky event");
+            hipLaunchKernelGGL(k_syrk64, dim3(nt * (nt + 1) / 2), dim3(256), 0, s2, A, P, kb, nt, 1);
+            if (hipEventRecord(evS, s2) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky event");
+        }
         hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, P, kb + 1, dflag, Li + NB * NB);
     }
-    if (ahead && hipStreamWaitEvent(s, evB, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky join");
+    if (ahead && hipStreamWaitEvent(s, evS, 0) != hipSuccess) return set_error(ctx, BEM_EHIP, "cholesky join");
     if ((rc = check_launch(ctx, "cholesky"))) return rc;
     ctx->chol_P = P;
     int hflag = 0;

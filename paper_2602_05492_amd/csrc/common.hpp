@@ -85,10 +85,11 @@ struct bem_ctx {
     bem_reg reg{};           // regularisation terms of lm_step (all off by default)
     void* blas = nullptr;    // rocBLAS handle (plain FP64 GEMMs), created on first use
     int64_t chol_P = -1;     // order of the last Cholesky factor (its inverted diagonal blocks are in cholw)
-    // second stream of the normal equations (the Gram of a sample tile runs on it while the next
-    // tile's feature rows are formed on the caller's stream) and its events, created on first use
+    // second stream (the Gram of a sample tile runs on it while the next tile's feature rows are
+    // formed on the caller's stream; the Cholesky's panel and trailing update run on it beside the
+    // diagonal blocks) and its events, created on first use
     hipStream_t s2 = nullptr;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[7] = {};
     // near-pair slots per wavefront of the mixed-precision sweeps (a multiple of 256, raised by
     // lm_step when a wavefront's near pairs overflow it), and the device word in which the last
     // mixed forward sweep left its largest overflowing count (0: none overflowed)
