@@ -496,16 +496,55 @@ __device__ inline int64_t param_col(int a, Layout L, int c)
     return (int64_t)L.params() * (b / L.C) + L.G + 3 * (b % L.C) + c;
 }
 
-// JtJ[col(a)][col(b)] += s * (Gc[a][b] + S[a][b] + S[b][a]): exactly symmetric
-__global__ void k_scatter_h(const double* __restrict__ Gc, int Wc, const double* __restrict__ S, Layout L, int c,
-                            double s, double* __restrict__ JtJ, int64_t P)
+// Every entry of J^T J from the three channels' blocks v_c(a, b) = Gc_c[a][b] + (S_c[a][b] +
+// S_c[b][a]) (compact indices a, b < n12), written once (no fill, no read-modify-write):
+// geometry x geometry entries are shared by the channels and take v_0 + v_1 + v_2; an entry
+// with a colour parameter of channel c takes v_c; colour entries of two different channels
+// are zero.  A block owns a 32 x 32 tile of (a, b) and reads S_c[b][a] through LDS, so both
+// reads of S are coalesced; v_c(a, b) = v_c(b, a) bit for bit, so J^T J is exactly symmetric.
+__global__ void __launch_bounds__(256) k_scatter_jtj(const double* __restrict__ Gc, int64_t gcs, int Wc,
+                                                     const double* __restrict__ S, int64_t ss, Layout L, double s,
+                                                     double* __restrict__ JtJ, int64_t P)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = blockIdx.y;
+    __shared__ double T[3][32][33];
     const int n = L.compact();
+    const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int bb = b0 + ty + 8 * k, aa = a0 + tx;   // S_c[bb][aa], aa contiguous
+            T[c][ty + 8 * k][tx] = (bb < n && aa < n) ? S[c * ss + (size_t)bb * n + aa] : 0.0;
+        }
+    __syncthreads();
+    const int b = b0 + tx;
     if (b >= n) return;
-    const double v = Gc[(size_t)a * Wc + b] + S[(size_t)a * n + b] + S[(size_t)b * n + a];
-    JtJ[param_col(a, L, c) * P + param_col(b, L, c)] += s * v;
+    const int64_t geo = L.geo();
+    const int Q = L.params();
+    const bool gb = b < geo;
+    const int64_t cb = gb ? (int64_t)Q * (b / L.G) + b % L.G
+                          : (int64_t)Q * ((b - geo) / L.C) + L.G + 3 * ((b - geo) % L.C);   // + channel
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int a = a0 + ty + 8 * k;
+        if (a >= n) break;
+        double v[3];
+        for (int c = 0; c < 3; ++c)
+            v[c] = Gc[c * gcs + (size_t)a * Wc + b] + (S[c * ss + (size_t)a * n + b] + T[c][tx][ty + 8 * k]);
+        const bool ga = a < geo;
+        const int64_t ca = ga ? (int64_t)Q * (a / L.G) + a % L.G
+                              : (int64_t)Q * ((a - geo) / L.C) + L.G + 3 * ((a - geo) % L.C);
+        if (ga && gb) {
+            JtJ[ca * P + cb] = s * ((v[0] + v[1]) + v[2]);
+        } else if (ga) {
+            for (int c = 0; c < 3; ++c) JtJ[ca * P + cb + c] = s * v[c];
+        } else if (gb) {
+            for (int c = 0; c < 3; ++c) JtJ[(ca + c) * P + cb] = s * v[c];
+        } else {
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) JtJ[(ca + c) * P + cb + d] = c == d ? s * v[c] : 0.0;
+        }
+    }
 }
 
 // Jtr[col(a)] += s * (R[row(a)][c] + sum_i Zc[i][a] R[beta row i][c])
@@ -887,18 +926,20 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         hipLaunchKernelGGL(k_sum_parts, dim3(ntiles / parts), dim3(256), 0, s, G, parts, W, dtiles, ts);
         if ((rc = check_launch(ctx, "gram parts"))) return rc;
     }
-    // contraction per channel
+    // contraction: per channel the compact Gram and S, then every entry of J^T J in one pass
     const double sc = N > 0 ? 1.0 / (double)N : 0.0;
-    if ((rc = fill_f64(ctx, JtJ, P * P, 0.0, s))) return rc;
     if (want_r && (rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
     const size_t wc2 = (size_t)Wc * Wc;
     const size_t szc = (size_t)M * n12;
-    if ((rc = ensure(ctx, ctx->tmp2, (wc2 + szc + (size_t)n12 * n12 + (size_t)(N > 0 ? N : 1) * 3) * sizeof(double), s)))
+    const size_t sn = (size_t)n12 * n12;
+    if ((rc = ensure(ctx, ctx->tmp2, (3 * wc2 + szc + 3 * sn + (size_t)(N > 0 ? N : 1) * 3) * sizeof(double), s)))
         return rc;
-    double* Gc = (double*)ctx->tmp2.ptr + (size_t)(N > 0 ? N : 1) * 3;   // keep r64 (not needed anymore, but harmless)
-    double* Zc = Gc + wc2;
-    double* S1 = Zc + szc;
+    double* Gc3 = (double*)ctx->tmp2.ptr + (size_t)(N > 0 ? N : 1) * 3;   // after r64 (no longer needed)
+    double* Zc = Gc3 + 3 * wc2;
+    double* S3 = Zc + szc;
     for (int c = 0; c < 3; ++c) {
+        double* Gc = Gc3 + c * wc2;
+        double* S1 = S3 + c * sn;
         hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, L, c, Wc, Gc);
         hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, L, M, c, Zc);
         if ((rc = check_launch(ctx, "gather"))) return rc;
@@ -909,9 +950,14 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                            nullptr, 0)))
             return rc;
         if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, S1, n12, s, nullptr, 0))) return rc;
-        hipLaunchKernelGGL(k_scatter_h, dim3(blocks_for(n12, 256), n12), dim3(256), 0, s, Gc, Wc, S1, L, c, sc, JtJ, P);
-        if (want_r)
+        if (want_r) {
             hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, L, M, c, sc, Jtr);
+            if ((rc = check_launch(ctx, "scatter"))) return rc;
+        }
+    }
+    if (n12 > 0) {
+        hipLaunchKernelGGL(k_scatter_jtj, dim3(blocks_for(n12, 32), blocks_for(n12, 32)), dim3(256), 0, s, Gc3,
+                           (int64_t)wc2, Wc, S3, (int64_t)sn, L, sc, JtJ, P);
         if ((rc = check_launch(ctx, "scatter"))) return rc;
     }
     return BEM_OK;
