@@ -464,17 +464,41 @@ struct Layout {
 };
 
 // Channel-c augmented Gram in compact order [g_c (GH) | e (CH) | beta (M)],
-// symmetric fill from the upper triangle of G.
-__global__ void k_gather_gram(const double* __restrict__ G, int64_t W, Layout L, int c, int Wc, double* __restrict__ Gc)
+// symmetric fill from the upper triangle of G.  The compact-to-row map is increasing, so
+// entry (a, b) comes from G[row(a)][row(b)] for a <= b and from G[row(b)][row(a)] below the
+// diagonal.  A block owns a 32 x 32 tile of (a, b); a tile below the diagonal reads its
+// mirror tile along a (coalesced) and transposes it through LDS.
+__global__ void __launch_bounds__(256) k_gather_gram(const double* __restrict__ G, int64_t W, Layout L, int c, int Wc,
+                                                     double* __restrict__ Gc)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = blockIdx.y;
+    __shared__ double T[32][33];
+    const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    if (b0 + 31 < a0) {                  // wholly below the diagonal: T[b][a] = G[row(b)][row(a)]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int bb = b0 + ty + 8 * k, aa = a0 + tx;
+            if (aa < Wc) T[ty + 8 * k][tx] = G[(size_t)L.row(bb, c) * W + L.row(aa, c)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int a = a0 + ty + 8 * k, b = b0 + tx;
+            if (a < Wc) Gc[(size_t)a * Wc + b] = T[tx][ty + 8 * k];
+        }
+        return;
+    }
+    const int b = b0 + tx;
     if (b >= Wc) return;
-    const int64_t ia = L.row(a, c);
     const int64_t ib = L.row(b, c);
-    // the upper triangle holds every needed entry (diagonal tiles are computed whole); reading
-    // it on both sides makes the gathered block exactly symmetric
-    Gc[(size_t)a * Wc + b] = ia <= ib ? G[(size_t)ia * W + ib] : G[(size_t)ib * W + ia];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int a = a0 + ty + 8 * k;
+        if (a >= Wc) break;
+        const int64_t ia = L.row(a, c);
+        // the upper triangle holds every needed entry (diagonal tiles are computed whole)
+        Gc[(size_t)a * Wc + b] = ia <= ib ? G[(size_t)ia * W + ib] : G[(size_t)ib * W + ia];
+    }
 }
 
 // Zc[i][a] = Z[i][row(a)] for the handle part of the compact order (a < (G + C)H)
@@ -751,13 +775,17 @@ static std::vector<int> gram_work(const std::vector<int>& tiles, int parts)
 
 namespace {
 // G[0] += G[1] + ... + G[parts - 1] (fixed order) over the ts x ts output tile of work entry
-// blockIdx.x (blockDim.x = ts, a thread per column)
+// blockIdx.x, rows split over gridDim.y blocks (blockDim.x = ts, a thread per column)
 __global__ void __launch_bounds__(256) k_sum_parts(double* __restrict__ G, int parts, int64_t W,
                                                    const int* __restrict__ work, int ts)
 {
-    const int64_t r0 = (int64_t)work[3 * blockIdx.x] * ts, c0 = (int64_t)work[3 * blockIdx.x + 1] * ts;
+    const int64_t c0 = (int64_t)work[3 * blockIdx.x + 1] * ts;
+    const int64_t rt = (int64_t)work[3 * blockIdx.x] * ts;   // the tile's first row
+    const int rows = (ts + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = rt + (int64_t)blockIdx.y * rows;
+    const int64_t r1 = rt + ts < r0 + rows ? rt + ts : r0 + rows;
     const int64_t c = c0 + threadIdx.x % ts;
-    for (int64_t r = r0 + threadIdx.x / ts; r < r0 + ts; r += blockDim.x / ts) {
+    for (int64_t r = r0 + threadIdx.x / ts; r < r1; r += blockDim.x / ts) {
         if (r >= W || c >= W) continue;
         const size_t e = (size_t)r * W + c;
         double v = G[e];
@@ -923,7 +951,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     }
     if (parts > 1 && N > 0) {
         // the first ntiles / parts work entries are part 0's, one per tile of the list
-        hipLaunchKernelGGL(k_sum_parts, dim3(ntiles / parts), dim3(256), 0, s, G, parts, W, dtiles, ts);
+        hipLaunchKernelGGL(k_sum_parts, dim3(ntiles / parts, 8), dim3(256), 0, s, G, parts, W, dtiles, ts);
         if ((rc = check_launch(ctx, "gram parts"))) return rc;
     }
     // contraction: per channel the compact Gram and S, then every entry of J^T J in one pass
@@ -940,7 +968,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     for (int c = 0; c < 3; ++c) {
         double* Gc = Gc3 + c * wc2;
         double* S1 = S3 + c * sn;
-        hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 256), Wc), dim3(256), 0, s, G, W, L, c, Wc, Gc);
+        hipLaunchKernelGGL(k_gather_gram, dim3(blocks_for(Wc, 32), blocks_for(Wc, 32)), dim3(256), 0, s, G, W, L, c,
+                           Wc, Gc);
         hipLaunchKernelGGL(k_gather_z, dim3(blocks_for(n12, 256), M), dim3(256), 0, s, Z, L, M, c, Zc);
         if ((rc = check_launch(ctx, "gather"))) return rc;
         // The channel's block of J^T J is G + B Zc + (B Zc)^T + Zc^T D Zc with B = Gc[0:n12, n12:Wc]
