@@ -96,6 +96,22 @@ def test_normal_equations_small(gram, prec, tol):
     assert eh < tol and eg < max(tol, 1e-10 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("n", [37, 200, 1001])
+def test_normal_equations_ragged_tiles(n):
+    """Split-BF16 J^T J with one-segment handles on sample counts whose last tile ends inside a
+    32-sample block of the blocked tile (37; 1001: tiles of 256 and a last one of 233) or on a
+    multiple of 8 that is not one of 32 (200)."""
+    th = _handles(14, 8)
+    x = _points(15, th, n)
+    ctx = ctx_for(1, tile_rows=256, handle_model="straight")
+    r = W.random_vector(16, (n, 3))
+    Ho, go = ST.normal_equations(th, x, r, 1, 1e-2)
+    JtJ, Jtr = ctx.jtj(dev(th), dev(x), dev(r, torch.float32), "bf16x3_mfma", "mixed")
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"straight jtj N={n}: JtJ {eh:.3e} Jtr {eg:.3e}")
+    assert eh < 1e-4 and eg < 1e-3
+
+
 @pytest.mark.parametrize("compat", [0, 1])
 @pytest.mark.parametrize("gram,prec,tol", [("fp64", "fp64", 1e-8), ("bf16x3_mfma", "mixed", 1e-2)])
 def test_lm_step_small(compat, gram, prec, tol):
