@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(256) k_bwd_step(const double* __restrict__ A, 
 
 // Damp, factor and check: returns BEM_ENOTPD when a pivot fails (host sync).  Blocked
 // right-looking with 64-column panels: the diagonal block and its inverse by k_potrf_diag,
-// the panel as A21 Linv^T (one GEMM into a scratch panel, copied back), the trailing
+// the panel as A21 Linv^T (in place; its first row block by k_next_diag), the trailing
 // lower triangle by a rank-64 update.  The inverted diagonal blocks stay in the context
 // for chol_solve.
 int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,
