@@ -833,11 +833,6 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             (gram != BEM_GRAM_BF16X3_MFMA || W * T2 < ((int64_t)1 << 31)))
             T = T2;
     }
-    // split-BF16 Gram: the sample tile is split into 3 parts with partial Grams of their own,
-    // so that a launch has 3x the blocks (fewer idle CUs in its last round) and stays
-    // deterministic (no atomics)
-    const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 3 : 1;
-    const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
     // MFMA Grams with several sample tiles: the Gram of tile t runs on a second stream while tile t+1's
     // feature rows are formed on the caller's stream (two tile buffers), so the VALU-bound feature
     // kernels and the MFMA-bound Gram share the chip.  Sharing slows a Gram launch by about a third
@@ -845,8 +840,26 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // (handle segment pairs per sample, H S) is a sizeable share of the Gram's (its distinct output
     // area): from about a third of the Gram's time, H S >= area / 8000.
     const int64_t gram_area = (int64_t)(gram_tiles(L, (int)W, 256).size() / 2) * 256 * 256;
-    const bool overlap = gram != BEM_GRAM_FP64 && N > T &&
-                         (int64_t)H * ctx->opts.segs_per_handle * 8000 >= gram_area;
+    const bool shares = gram != BEM_GRAM_FP64 && (int64_t)H * ctx->opts.segs_per_handle * 8000 >= gram_area;
+    // default split-BF16 tile when the Gram runs alone: the fewest tiles the tile buffer holds,
+    // balanced (fewer Gram launches and partial-Gram read-modify-writes: paper-native step -0.2 ms
+    // with 2 tiles of 50,048 samples against 3 of 33,344)
+    if (ctx->opts.tile_rows <= 0 && gram == BEM_GRAM_BF16X3_MFMA && !shares && N > T) {
+        int64_t Tmax = (int64_t)(((size_t)3 << 30) / ((size_t)W * elem)) / 64 * 64;
+        const int64_t Toff = (((int64_t)1 << 31) - 1) / W / 64 * 64;          // 32-bit offsets in the Gram
+        if (Toff < Tmax) Tmax = Toff;
+        if (Tmax > T) {
+            const int64_t nt = (N + Tmax - 1) / Tmax;
+            const int64_t T2 = ((N + nt - 1) / nt + 63) / 64 * 64;
+            if (T2 > T) T = T2;
+        }
+    }
+    // split-BF16 Gram: the sample tile is split into 3 parts with partial Grams of their own,
+    // so that a launch has 3x the blocks (fewer idle CUs in its last round) and stays
+    // deterministic (no atomics)
+    const int parts = gram == BEM_GRAM_BF16X3_MFMA ? 3 : 1;
+    const int64_t kchunk = ((T + parts - 1) / parts + 31) / 32 * 32;
+    const bool overlap = shares && N > T;
     const size_t tile_bytes = ((size_t)W * T * elem + 255) / 256 * 256;
     hipStream_t sg = s;
     if (overlap && (rc = aux_stream(ctx, &sg))) return rc;
