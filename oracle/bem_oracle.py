@@ -28,9 +28,12 @@ through those same expressions.
 Pins (tests/test_oracle_*.py): adaptive quadrature of single segment
 integrals; the double-layer identity on closed polygons; Green's third
 identity reproducing u = x and u = x^2 - y^2; the single layer of a circle;
-matrix row sums and spectrum; jump relations across a handle; central finite
-differences of every derivative; exact colour recovery by one Gauss-Newton
-step; LM invariants.  The paper prints no worked numerical example, so no pin
+matrix row sums and spectrum; jump relations across a handle; the
+alpha = 1/2 jump of the outer boundary (the interior formula's limit on each
+element equals the solved boundary value, which fixes the size of the
+right-hand side against the matrix); the zero-Neumann condition converging
+under refinement for compatible handles; central finite differences of every
+derivative; exact colour recovery by one Gauss-Newton step; LM invariants.  The paper prints no worked numerical example, so no pin
 is a value printed in the paper.
 """
 from __future__ import annotations
