@@ -40,7 +40,8 @@
  *    which it grows with hipMalloc on first use of a size and frees in
  *    bem_destroy.
  *  - Calls enqueue on `stream` and return without a host synchronisation,
- *    except where stated (lm_step; growth of a workspace).
+ *    except where stated (lm_step; growth of a workspace; the first bem_jtj
+ *    of a context for a given H, which uploads its Gram work list).
  *  - Every call returns a bem_status; nothing throws across the ABI.  On an
  *    error, outputs are unspecified and bem_last_error() describes it.
  *  - A context is not thread-safe; use one context per stream.
@@ -70,8 +71,9 @@ typedef enum {
 /* Arithmetic of the sample x segment sweeps.
  * FP64 : every pair in float64; u and cotangents are float64.
  * MIXED: pairs in float32 except near-singular pairs (both segment end points
- *        within 2*near_factor*L of the sample, which contains every sample
- *        closer than near_factor*L to the segment), which are evaluated in
+ *        within max(2 nf, nf + 1)*L of the sample, nf = near_factor, which
+ *        contains every sample closer than nf*L to the segment), which are
+ *        evaluated in
  *        float64 from the float64 inputs; u and cotangents are float32; every
  *        reduction over samples is finished in float64.  The float64 sums of
  *        near pairs in bem_eval and bem_vjp are accumulated with atomics, so
@@ -128,6 +130,8 @@ typedef struct {
     double compat_violation;  /* out: max_c |a_c . theta'| / sum |a_c theta'| (compat) */
     double reg_value;         /* out: regularisation terms at theta (in loss_before)  */
     int32_t snap_pairs;       /* out: end point pairs snapped in this step            */
+    int64_t data_count;       /* in: M_H, samples drawn over the whole image, which
+                                 divides the data terms (0: the step's own N; else >= N) */
 } bem_lm_state;
 
 /* Regularisation terms of the LM step (Sec. 4.4).  Each enters the step with its
@@ -222,16 +226,18 @@ int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  *   JtJ = (1/N) sum_x sum_c J_c(x)^T J_c(x)   [P,P] float64 (full, symmetric)
  *   Jtr = (1/N) sum_x sum_c J_c(x)^T r_c(x)   [P]   float64
  * with J_c(x) = du_c(x)/dtheta.  resid [N,3] (float64 for FP64, float32 for
- * MIXED).  The Gram contraction runs in `gram` arithmetic.
+ * MIXED).  The Gram contraction runs in `gram` arithmetic.  The Gram's work
+ * list is uploaded (with a host synchronisation) on the first call for a given
+ * H, handle model and `gram` and kept on the device; later calls only enqueue.
  * Errors: as bem_eval. */
 int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
             const void* resid, double* JtJ, double* Jtr, bem_gram gram, bem_prec prec,
             hipStream_t stream);
 
 /* One Levenberg-Marquardt step (Eq. optimstep, Sec. 4.3) on the samples x
- * with targets T [N,3] float64:
- *   cbar update (state->mean_rule), u = u(theta), r = u - T, loss L0 = (1/2N) sum r^2,
- *   g = (1/N) sum J^T r by the adjoint (bem_vjp), H = (1/N) sum J^T J (bem_jtj's
+ * with targets T [N,3] float64, m = state->data_count (0: m = N):
+ *   cbar update (state->mean_rule), u = u(theta), r = u - T, loss L0 = (1/2m) sum r^2,
+ *   g = (1/m) sum J^T r by the adjoint (bem_vjp), H = (1/m) sum J^T J (bem_jtj's
  *   Gram; J^T r itself is not formed again),
  *   delta = (lambda diag(H) + H)^{-1} g by float64 Cholesky,
  *   theta' = theta - delta, L1 = loss at theta' on the same samples with cbar fixed;
@@ -247,6 +253,11 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * With regularisation terms set (bem_set_regularization) their gradient and
  * Hessian are added to g and H, and their value to L0 and L1 (snapping pairs
  * chosen at theta); state->reg_value and state->snap_pairs report them.
+ * The data terms are Monte Carlo estimates over the m samples drawn for the
+ * whole image (Eq. losshessian, Eq. lossjacobian divide by M_H): the step of one
+ * subdomain (Sec. 4.3, block-diagonal Hessian) sums its own N samples and sets
+ * data_count to the image's total, so that its data terms keep their weight
+ * against the regularisation terms.
  * MIXED: the step works on a copy of x and target reordered cell by cell (a
  * 32 x 32 grid of Morton-ordered cells over the outer boundary's bounding box),
  * so that neighbouring samples share wavefronts; x and target themselves are
@@ -256,7 +267,8 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.
- * Errors: as bem_eval, ENOTPD, ENUMERIC (non-finite loss or step). */
+ * Errors: as bem_eval, EINVAL (data_count < 0 or 0 < data_count < N), ENOTPD,
+ * ENUMERIC (non-finite loss or step). */
 int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N,
             const double* target, bem_lm_state* state, bem_gram gram, bem_prec prec,
             hipStream_t stream);

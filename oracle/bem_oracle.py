@@ -448,6 +448,7 @@ class LMState:
     cbar: np.ndarray = None
     compat: bool = False        # enforce the compatibility condition (Sec. 4.3)
     chol_retries: int = 0       # damping raises after a failed Cholesky in the last step
+    data_count: int = 0         # M_H, the samples drawn over the whole image (0: the step's own)
 
     def __post_init__(self):
         if self.cbar_sum is None:
@@ -571,8 +572,15 @@ def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256
         cbar = (T - u0).mean(axis=0)
     state.cbar = cbar
     u = u0 + cbar[None, :]
-    L0 = loss(u, T)
+    # the data terms are Monte Carlo estimates over the M_H samples drawn for the whole image
+    # (Eq. losshessian, Eq. lossjacobian): a subdomain's step sums its own samples and divides by
+    # M_H, so its data terms keep their weight against the regularisers (Sec. 4.4)
+    if state.data_count and state.data_count < len(T):
+        raise ValueError("data_count must be 0 or at least the number of samples")
+    wdat = len(T) / state.data_count if state.data_count else 1.0
+    L0 = wdat * loss(u, T)
     JtJ, Jtr = normal_equations(theta, x, u - T, S, eps, per_side)
+    JtJ, Jtr = wdat * JtJ, wdat * Jtr
     pairs = None
     if reg is not None and reg.active():
         R0, gR, HR, pairs = rg.terms(theta, reg)
@@ -594,7 +602,7 @@ def lm_step(theta, x, T, state: LMState, S: int, eps: float, per_side: int = 256
     theta_new = theta - delta.reshape(theta.shape)
     if state.compat:
         theta_new = reproject(theta_new, S)
-    L1 = loss(evaluate(theta_new, x, cbar, S, eps, per_side), T)
+    L1 = wdat * loss(evaluate(theta_new, x, cbar, S, eps, per_side), T)
     if pairs is not None:
         L1 += rg.value(theta_new, reg, pairs)
     state.loss_before, state.loss_after = L0, L1

@@ -43,7 +43,7 @@ class LMState(ctypes.Structure):
                 ("cbar_count", ctypes.c_int64), ("mean_rule", ctypes.c_int32), ("accepted", ctypes.c_int32),
                 ("loss_before", ctypes.c_double), ("loss_after", ctypes.c_double), ("chol_retries", ctypes.c_int32),
                 ("compat", ctypes.c_int32), ("compat_violation", ctypes.c_double), ("reg_value", ctypes.c_double),
-                ("snap_pairs", ctypes.c_int32)]
+                ("snap_pairs", ctypes.c_int32), ("data_count", ctypes.c_int64)]
 
 
 class Reg(ctypes.Structure):
@@ -330,9 +330,14 @@ class Context:
 def lm_step_subdomains(contexts, thetas, x, target, labels, states, gram: str = "fp64", prec: str = "fp64"):
     """One LM step in every subdomain (Sec. 4.1, Sec. 4.3): the samples are grouped by label on
     the GPU, then subdomain d takes its own step (its own handles, mean colour, normal equations,
-    Cholesky and damping) on its own samples.  contexts, thetas and states are per subdomain."""
+    Cholesky and damping) on its own samples.  contexts, thetas and states are per subdomain.
+    Every subdomain's data terms are divided by the number of samples drawn over the whole image
+    (all N rows, including those outside every subdomain), as the Monte Carlo estimates of
+    Eq. losshessian and Eq. lossjacobian do."""
     xs, Ts, off = contexts[0].partition(labels, x, target, len(contexts))
+    N = x.shape[0]
     for d, (ctx, th, st) in enumerate(zip(contexts, thetas, states)):
+        st.data_count = N
         ctx.lm_step(th, xs[off[d]:off[d + 1]], Ts[off[d]:off[d + 1]], st, gram, prec)
     return states
 

@@ -103,6 +103,10 @@ struct bem_ctx {
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal, egeo;   // egeo: outer elements [M][4] (a, b)
     // per-call workspaces
     bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw, sortw;
+    // Gram work list of the normal equations on the device, uploaded once per (W, H, handle
+    // model, Gram arithmetic) and kept, so that later calls enqueue without a host synchronisation
+    bem::DevBuf tilew;
+    int64_t tiles_key[4] = {-1, -1, -1, -1};
 };
 
 namespace bem {
@@ -167,7 +171,7 @@ int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, i
 // jtj.hip
 int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s);
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
-            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre = nullptr);
+            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre = nullptr, double norm = 0.0);
 int run_jacobian(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, double* J, hipStream_t s);
 // gram_mfma.hip
 int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,

@@ -241,7 +241,7 @@ int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, bool mixed, hipStream_t 
     {
         ProfScope ps_(ctx, PT_BOUNDARY, s);
         if (mixed) {
-            const double nf = 2.0 * ctx->opts.near_factor;
+            const double nf = near_radius(ctx->opts.near_factor);
             hipLaunchKernelGGL(k_boundary_rhs_mixed, dim3(ctx->M), dim3(256), 0, s, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, K, (const double*)ctx->egeo.ptr, eps2, (float)(nf * nf), F);
         } else {

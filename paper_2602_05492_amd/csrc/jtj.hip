@@ -16,8 +16,11 @@
 //   J^T J += E_c^T A_c E_c + sym(E_c^T B_c Z_c') + Z_c'^T D Z_c'
 // with A_c, B_c, D the channel's blocks of G, and J^T r likewise.
 #include <algorithm>
+#include <cstring>
 #include <tuple>
 #include <vector>
+
+#include <cstring>
 
 #include "common.hpp"
 #include "sweep_common.hpp"
@@ -643,7 +646,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const int S = ctx->opts.segs_per_handle;
     const int model = ctx->model;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
-    const double nf = 2.0 * ctx->opts.near_factor;
+    const double nf = near_radius(ctx->opts.near_factor);
     const float near2 = (float)(nf * nf);
     const Layout L = layout_of(ctx, H);
     const int64_t beta_row0 = L.handle_rows();
@@ -796,7 +799,7 @@ __global__ void __launch_bounds__(256) k_sum_parts(double* __restrict__ G, int p
 }  // namespace
 
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,
-            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre)
+            int gram, double* JtJ, double* Jtr, hipStream_t s, const NearList* pre, double norm)
 {
     int rc;
     const int M = ctx->M;
@@ -888,9 +891,21 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(L, (int)W, ts)
                                                          : gram_work(gram_tiles(L, (int)W, ts), parts);
     const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
-    // tmp5: tile list, the vertex table, then the near-pair corrections and run table of one sample tile
+    // the work list lives on the device (tilew); it is uploaded when its configuration changes, the
+    // only host synchronisation of this call apart from workspace growth
+    const int64_t key[4] = {W, H, ctx->model, gram};
+    if (std::memcmp(key, ctx->tiles_key, sizeof(key)) != 0) {
+        ctx->tiles_key[0] = -1;
+        if ((rc = ensure(ctx, ctx->tilew, tiles.size() * sizeof(int), s))) return rc;
+        if (hipMemcpyAsync(ctx->tilew.ptr, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)       // the host copy goes out of scope below
+            return set_error(ctx, BEM_EHIP, "tile list upload");
+        std::memcpy(ctx->tiles_key, key, sizeof(key));
+    }
+    const int* dtiles = (const int*)ctx->tilew.ptr;
+    // tmp5: the vertex table, then the near-pair corrections and run table of one sample tile
     const int S = ctx->opts.segs_per_handle;
-    const size_t tiles_bytes = (tiles.size() * sizeof(int) + 255) / 256 * 256;
     const size_t vtab_bytes = ((size_t)(S + 1) * 8 * sizeof(float) + 255) / 256 * 256;
     NearList nl{};
     if (mixed && N > 0) {
@@ -899,16 +914,11 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     }
     const size_t corr_bytes = mixed ? ((size_t)((T + 63) / 64) * nl.slots * kFeatVals * sizeof(float) + 255) / 256 * 256 : 0;
     const size_t runs_bytes = mixed ? (size_t)((T + 63) / 64) * H * sizeof(int2) : 0;
-    if ((rc = ensure(ctx, ctx->tmp5, tiles_bytes + vtab_bytes + corr_bytes + runs_bytes + 256, s))) return rc;
-    float* vtab = (float*)((char*)ctx->tmp5.ptr + tiles_bytes);
-    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes) : nullptr;
-    int2* runs = mixed ? (int2*)((char*)ctx->tmp5.ptr + tiles_bytes + vtab_bytes + corr_bytes) : nullptr;
+    if ((rc = ensure(ctx, ctx->tmp5, vtab_bytes + corr_bytes + runs_bytes + 256, s))) return rc;
+    float* vtab = (float*)ctx->tmp5.ptr;
+    float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes) : nullptr;
+    int2* runs = mixed ? (int2*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes) : nullptr;
     hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
-    if (hipMemcpyAsync(ctx->tmp5.ptr, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
-        return set_error(ctx, BEM_EHIP, "tile list upload");
-    // the tile list is read by every tile's Gram; keep the host copy alive until queued work is done
-    if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, BEM_EHIP, "tile list sync");
-    const int* dtiles = (const int*)ctx->tmp5.ptr;
     hipEvent_t* evF = ctx->ev;          // features of the tile in buffer b done
     hipEvent_t* evG = ctx->ev + 2;      // Gram of the tile in buffer b done
     if (overlap) {                      // the Gram stream starts after everything queued so far
@@ -968,7 +978,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         if ((rc = check_launch(ctx, "gram parts"))) return rc;
     }
     // contraction: per channel the compact Gram and S, then every entry of J^T J in one pass
-    const double sc = N > 0 ? 1.0 / (double)N : 0.0;
+    // (1/N) sum over the samples, or (1/norm): the samples drawn over the whole image
+    const double sc = N > 0 ? 1.0 / (norm > 0.0 ? norm : (double)N) : 0.0;
     if (want_r && (rc = fill_f64(ctx, Jtr, P, 0.0, s))) return rc;
     const size_t wc2 = (size_t)Wc * Wc;
     const size_t szc = (size_t)M * n12;

@@ -337,6 +337,12 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     double* cA = dpart + 3 * kRedBlocks + 8;
     double* cX = cA + 3 * (size_t)P;          // [P][4]: gradient and the three a_c, solved in place
     double* cviol = cX + 4 * (size_t)P;
+    if (st->data_count < 0 || (st->data_count > 0 && st->data_count < N))
+        return set_error(ctx, BEM_EINVAL, "data_count %lld must be 0 or at least N = %lld", (long long)st->data_count,
+                         (long long)N);
+    // the data terms divide by the samples drawn over the whole image (a subdomain's step sums
+    // only its own)
+    const double nd = st->data_count > 0 ? (double)st->data_count : (double)N;
     st->compat_violation = 0.0;
     st->reg_value = 0.0;
     st->snap_pairs = 0;
@@ -402,16 +408,16 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
         if ((rc = bem_eval(ctx, theta, H, x, N, st->cbar, u, prec, s))) return rc;
         if ((rc = row_sums(ctx, u, mixed, T, N, 0, r, sums, dpart, s))) return rc;
     }
-    const double L0 = N > 0 ? 0.5 * sums[0] / (double)N : 0.0;
+    const double L0 = N > 0 ? 0.5 * sums[0] / nd : 0.0;
     st->loss_before = L0;
     st->loss_after = L0;
     if (!std::isfinite(L0)) return set_error(ctx, BEM_ENUMERIC, "non-finite loss at the current parameters");
     if (H == 0 || N == 0) return BEM_OK;
     // gradient by the adjoint, Hessian by the normal equations
     if ((rc = run_vjp(ctx, theta, H, x, N, r, mixed, g, s, mixed ? &nl : nullptr))) return rc;
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / (double)N);
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / nd);
     // the step's right-hand side is the adjoint gradient above, so J^T r is not formed
-    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr))) return rc;
+    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr, nd))) return rc;
     // regularisation terms (Sec. 4.4): gradient and Hessian into g and J^T J, value into the loss;
     // the snapping pairs chosen here are kept for the trial point
     const bool reg = reg_active(ctx);
@@ -484,7 +490,7 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     int hflag = 0;
     if (hipMemcpy(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "flag readback");
-    double L1 = 0.5 * sums[0] / (double)N;
+    double L1 = 0.5 * sums[0] / nd;
     if (reg) {
         double R1 = 0.0;
         if ((rc = reg_terms(ctx, th1, H, false, nullptr, nullptr, &R1, nullptr, s))) return rc;

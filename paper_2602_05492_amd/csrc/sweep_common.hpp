@@ -35,10 +35,14 @@ __device__ inline void load_element(const double* eg, int i, double& ax, double&
 }
 
 // ---- near-singular pairs of the mixed-precision sweeps ---------------------------
-// A pair is near when both end points of the segment lie within 2*near_factor*L
-// of the sample (this contains every sample closer than near_factor*L to the
-// segment).  The test is written with explicit roundings so that every kernel
-// that classifies a pair takes the same decision.
+// A pair is near when both end points of the segment lie within rho*L of the
+// sample, rho = near_radius(near_factor).  A sample at distance d < nf*L from the
+// segment is within d + L < (nf + 1)*L of either end point, so rho = max(2 nf,
+// nf + 1) makes the near set contain every sample closer than nf*L to the
+// segment (for nf >= 1 the radius is 2 nf*L).  The test is written with explicit
+// roundings so that every kernel that classifies a pair takes the same decision.
+inline double near_radius(double nf) { return nf >= 1.0 ? 2.0 * nf : nf + 1.0; }
+
 __device__ inline bool near_segment(float ax, float ay, float bx, float by, float L2, float X, float Y, float near2)
 {
     const float dx = __fsub_rn(ax, X), dy = __fsub_rn(ay, Y), ex = __fsub_rn(bx, X), ey = __fsub_rn(by, Y);

@@ -2,9 +2,9 @@
 // u(x) at every sample).
 //
 // Far pairs run in float32 from the float32 copies of the segment and element
-// tables.  A pair whose two end points both lie within 2*near_factor*L of the
-// sample (a set containing every sample closer than near_factor*L to the
-// segment) is not evaluated there: the wavefront appends (sample, segment) to its
+// tables.  A pair whose two end points both lie within max(2 nf, nf + 1)*L of the
+// sample, nf = near_factor (a set containing every sample closer than nf*L to
+// the segment) is not evaluated there: the wavefront appends (sample, segment) to its
 // own slice of a list, and a second kernel evaluates the listed
 // pairs in float64 from the float64 tables and the float64 sample, adding into
 // float64 per-sample sums.  Keeping float64 code out of the float32 sweep keeps
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) k_sweep_inline(const double* __restrict__
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s)
 {
     int rc;
-    const double nf = 2.0 * ctx->opts.near_factor;
+    const double nf = near_radius(ctx->opts.near_factor);
     const int64_t nwaves = N > 0 ? (int64_t)blocks_for(N, 256) * 4 : 0;
     const int slots = near_slots_for(ctx->near_slots, nwaves);
     // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N]
@@ -258,7 +258,7 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     if (N == 0) return BEM_OK;
     int rc;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
-    const double nf = 2.0 * ctx->opts.near_factor;
+    const double nf = near_radius(ctx->opts.near_factor);
     const float near2 = (float)(nf * nf);
     // per-wavefront near-pair slices, their counts, float64 sums, overflow flags
     const int64_t nwaves = (int64_t)blocks_for(N, 256) * 4;     // every launched wavefront, idle tail ones too

@@ -380,7 +380,7 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int K = H * S;
     const int M = ctx->M;
     const double eps2 = ctx->opts.eps * ctx->opts.eps;
-    const double nf = 2.0 * ctx->opts.near_factor;
+    const double nf = near_radius(ctx->opts.near_factor);
     const float near2 = (float)(nf * nf);
     if (H == 0) return BEM_OK;
     if ((rc = launch_expand(ctx, theta, H, s))) return rc;

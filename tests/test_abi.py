@@ -43,13 +43,34 @@ def test_build_rejects_bad_options(bad):
     assert L.bem_last_error(None)
 
 
-def test_opts_struct_matches_header():
-    """bem_opts: the binding's field order and sizes are the header's."""
+def _header_struct(name):
+    """(field name, C type) of the typedef'd struct `name` in the header, in order."""
     src = open(B.HEADER).read()
-    body = src[src.index("typedef struct {\n    int32_t elems_per_side"):]
-    body = body[:body.index("} bem_opts;")]
-    fields = [ln.split(";")[0].split()[-1] for ln in body.splitlines()[1:] if ";" in ln]
-    assert fields == [f[0] for f in B.Opts._fields_]
+    end = src.index("} %s;" % name)
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    out = []
+    for ln in body.splitlines():
+        decl = ln.split("/*")[0].strip()
+        if not decl.endswith(";"):
+            continue
+        parts = decl[:-1].split()
+        out.append((parts[-1].split("[")[0], parts[0], "[" in parts[-1]))
+    return out
+
+
+_CTYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+
+
+@pytest.mark.parametrize("name,cls", [("bem_opts", "Opts"), ("bem_lm_state", "LMState"), ("bem_reg", "Reg")])
+def test_structs_match_header(name, cls):
+    """The binding's ctypes structs have the header's fields, in order, with the same C types."""
+    fields = _header_struct(name)
+    ct = getattr(B, cls)._fields_
+    alias = {"lambda": "lam"}                      # a Python keyword
+    assert [alias.get(f[0], f[0]) for f in fields] == [f[0] for f in ct]
+    for (fname, ctype, is_arr), (_, cty) in zip(fields, ct):
+        base = cty._type_ if is_arr else cty
+        assert base is _CTYPES[ctype], (fname, ctype, cty)
 
 
 def test_null_arguments():

@@ -232,3 +232,38 @@ def test_lm_step_rejects_non_finite_parameters():
     with pytest.raises(B.BemError) as e:
         ctx.lm_step(dev(th), x, T, st, "fp64", "fp64")
     assert e.value.status == -6
+
+
+def test_jtj_enqueues_without_host_sync():
+    """bem_jtj through the raw C ABI: after the first call of a configuration (work-list upload,
+    workspace growth) a call only enqueues.  An event recorded right after it returns is still
+    pending (the call did not wait for its ~0.1 s of kernels), and the results, once the stream
+    drains, equal the first call's bit for bit (FP64 Gram, reproducible)."""
+    import ctypes
+    wl = W.make_config(2)
+    ctx = ctx_for(wl.S)
+    x = dev(wl.samples(0))
+    th = dev(wl.theta_true)
+    r = dev(W.random_vector(53, (wl.N, 3)))
+    P = wl.P
+    out = [(torch.empty((P, P), dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.float64, device="cuda"))
+           for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p(stream.cuda_stream)
+    L = B.lib()
+
+    def call(o):
+        return L.bem_jtj(ctx._h, ctypes.c_void_p(th.data_ptr()), wl.H, ctypes.c_void_p(x.data_ptr()), wl.N,
+                         ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(o[0].data_ptr()),
+                         ctypes.c_void_p(o[1].data_ptr()), 0, 0, h)
+
+    assert call(out[0]) == 0
+    torch.cuda.synchronize()
+    ev = torch.cuda.Event()
+    assert call(out[1]) == 0
+    ev.record(stream)
+    pending = not ev.query()
+    torch.cuda.synchronize()
+    log(f"bem_jtj returned with its work pending: {pending}")
+    assert pending
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

@@ -3,7 +3,9 @@ wavefronts whose list slice overflows (their samples are flagged and redone
 with the near pairs inline).
 
 The mixed path evaluates a pair in float64 when both segment end points lie
-within 2 * near_factor * L of the sample.  near_factor = 1.5 overflows the
+within max(2 nf, nf + 1) * L of the sample, nf = near_factor (2 nf * L for the
+factors >= 1 used here; a factor of 0.5 takes the radius 1.5 L, which still
+contains every sample within 0.5 L of the segment).  near_factor = 1.5 overflows the
 slices of most wavefronts of the medium workload (within such a wavefront some
 samples' pairs are listed, the rest flagged); near_factor = 60 makes every
 pair near, so every slice overflows and every sample takes the flagged path.
@@ -115,3 +117,18 @@ def test_lm_step_mixed_near_lists(nf):
     e = float(np.abs(d - d_o).max() / np.abs(d_o).max()) if st_o.accepted else float(np.abs(d).max())
     log(f"near_factor {nf}: lm step rel err {e:.3e}, accepted {st.accepted}")
     assert e < 1e-2
+
+
+def test_eval_mixed_small_near_factor():
+    """near_factor = 0.5 on the near-singular stress samples (10% within 1e-3 of a segment): the
+    radius max(2 nf, nf + 1) L = 1.5 L still sends every pair closer than 0.5 L to the float64
+    evaluation; colour within the mixed-precision bar of the oracle."""
+    wl = W.make_config(3)
+    x = wl.samples(0, n=4096)                          # 410 of them within 1e-3 of a segment
+    th = wl.theta_true
+    ctx = ctx_for(wl.S, near_factor=0.5)
+    got = host(ctx.eval(dev(th), dev(x), wl.cbar_true, "mixed"))
+    ref = O.evaluate(th, x, wl.cbar_true, wl.S, wl.eps)
+    err = float(np.abs(got - ref).max())
+    log(f"near_factor 0.5: mixed eval max abs err {err:.3e}")
+    assert err < 1e-4

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 import oracle as O
+from oracle import regularizers as RG
 from paper_2602_05492_amd import bem as B
 from paper_2602_05492_amd import workload as W
 from helpers import dev, host, log
@@ -138,9 +139,12 @@ def test_partition_matches_stable_sort(N):
     assert np.array_equal(host(To)[: off[D]], T[order])
 
 
-def test_two_subdomains_lm_step():
+@pytest.mark.parametrize("with_reg", [False, True])
+def test_two_subdomains_lm_step(with_reg):
     """Left and right halves of the unit square as subdomains with their own handles: one
-    partitioned call equals the oracle's independent step in each half."""
+    partitioned call equals the oracle's independent step in each half, whose data terms are
+    divided by all samples drawn over the image (10% of them in no subdomain), also with the
+    regularisation terms of Sec. 4.4 on, where that normalisation sets their relative weight."""
     halves = [np.array([[0.0, 0.0], [0.5, 0.0], [0.5, 1.0], [0.0, 1.0]]),
               np.array([[0.5, 0.0], [1.0, 0.0], [1.0, 1.0], [0.5, 1.0]])]
     bnds, ctxs, ths, ths0 = [], [], [], []
@@ -155,6 +159,12 @@ def test_two_subdomains_lm_step():
         ths0.append(th + 0.01 * W.random_vector(60 + d, th.shape))
     x = W.random_points(70, 5000, 0.001, 0.999)
     labels = (x[:, 0] >= 0.5).astype(np.int32)
+    labels[::10] = -1                                   # samples outside both subdomains
+    reg = RG.Reg(length_weight=2.0, length_max=0.05, snap_weight=0.0, snap_dist=0.1, snap_mix=0.5,
+                 sparse_wd=0.01, sparse_wc=0.005, sparse_t=0.1, sparse_eps=1e-2) if with_reg else None
+    if with_reg:
+        for c in ctxs:
+            c.set_regularization(**{f: getattr(reg, f) for f in reg.__dataclass_fields__})
     T = np.zeros((len(x), 3))
     for d in range(2):
         m = labels == d
@@ -164,8 +174,9 @@ def test_two_subdomains_lm_step():
     B.lm_step_subdomains(ctxs, dth, dev(x), dev(T), dev(labels), sts, "fp64", "fp64")
     for d in range(2):
         m = labels == d
-        st_o = O.LMState(lam=1e-1, mean_rule=0)
-        th_o, st_o = O.lm_step(ths0[d], x[m], T[m], st_o, 8, 1e-2, bnds[d])
+        st_o = O.LMState(lam=1e-1, mean_rule=0, data_count=len(x))
+        th_o, st_o = O.lm_step(ths0[d], x[m], T[m], st_o, 8, 1e-2, bnds[d], reg=reg)
+        assert sts[d].loss_before == pytest.approx(st_o.loss_before, rel=1e-10)
         e = _rel(host(dth[d]) - ths0[d], th_o - ths0[d]) if st_o.accepted else float(np.abs(host(dth[d]) - ths0[d]).max())
         log(f"subdomain {d}: {m.sum()} samples, accepted {sts[d].accepted}/{st_o.accepted}, cbar {sts[d].cbar[:]} / "
             f"{st_o.cbar}, step rel err {e:.3e}")

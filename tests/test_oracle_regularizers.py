@@ -160,3 +160,39 @@ def test_prune():
     cub[2, 8:20] = 0.0
     cub[2, 11] = 5e-4
     assert np.array_equal(RG.prune(cub, 1e-3), cub[:2])
+
+
+@pytest.mark.parametrize("compat", [False, True])
+def test_data_count_scales_only_the_data_terms(compat):
+    """A subdomain's step divides its data terms by the samples drawn over the whole image, M_H
+    (Eq. losshessian, Eq. lossjacobian), and leaves the regularisers (Sec. 4.4) as they are.
+    Dividing the whole objective by a constant does not change the LM step or its accept test
+    (the step is invariant to a rescaled loss), so the step with data_count = m and weights w
+    equals the step with the subdomain's own count and weights w N / m, and its losses are the
+    latter's times N / m. A slip that scaled only some of the data terms (loss, gradient or
+    Hessian) or also the regularisers breaks the equality."""
+    ST = O.straight
+    th = _straight(3, 4)
+    S, eps, ps = 1, 1e-2, 16
+    x = W.random_points(4, 96)
+    T = ST.evaluate(_straight(5, 4), x, np.full(3, 0.4), S, eps, ps)
+    m = 96 * 7
+    k = 96 / m
+    scaled = RG.Reg(**{f: (getattr(REG, f) / k if f in ("length_weight", "snap_weight", "sparse_wd", "sparse_wc")
+                          else getattr(REG, f)) for f in REG.__dataclass_fields__})
+    st_a = O.LMState(lam=1e-1, mean_rule=1, compat=compat, data_count=m)
+    th_a, st_a = ST.lm_step(th, x, T, st_a, S, eps, ps, reg=REG)
+    st_b = O.LMState(lam=1e-1, mean_rule=1, compat=compat)
+    th_b, st_b = ST.lm_step(th, x, T, st_b, S, eps, ps, reg=scaled)
+    assert st_a.accepted == st_b.accepted
+    assert np.allclose(th_a, th_b, rtol=1e-9, atol=1e-12)
+    assert st_a.loss_before == pytest.approx(k * st_b.loss_before, rel=1e-12)
+    assert st_a.loss_after == pytest.approx(k * st_b.loss_after, rel=1e-9)
+    # without regularisers the step does not depend on data_count at all
+    st_c = O.LMState(lam=1e-1, mean_rule=1, compat=compat, data_count=m)
+    th_c, _ = ST.lm_step(th, x, T, st_c, S, eps, ps)
+    st_d = O.LMState(lam=1e-1, mean_rule=1, compat=compat)
+    th_d, _ = ST.lm_step(th, x, T, st_d, S, eps, ps)
+    assert np.allclose(th_c, th_d, rtol=1e-9, atol=1e-12)
+    with pytest.raises(ValueError):
+        ST.lm_step(th, x, T, O.LMState(lam=1e-1, data_count=95), S, eps, ps)
