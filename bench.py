@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sample×segment pairs/s and LM steps/s, FP32-mixed vs FP64 at 1e-4 color err"
-PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15}
+PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12,
+         "bf16_mfma": 2.5e15}
 # HBM byte counters of the split-BF16 Gram kernel, taken with rocprofv3 --pmc on the
 # --pmc-probe run (two sample tiles of the LM workload plus a 256 MiB copy for calibration)
 PMC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_lm_workload_pmc.json")
@@ -186,47 +187,248 @@ def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int) -> in
     return 0
 
 
-def cpu_baseline(wl, x_host, budget_note: str) -> dict:
-    """Time the FP64 oracle on bounded pieces of one LM step and extrapolate to the full step
-    (BLAS held to one thread, so the figure is one host core's)."""
+# ---- CPU baseline: the FP64 oracle on the host's cores ----------------------------------------
+# Worker processes are started (spawn) before this process touches the GPU; each runs the oracle
+# single-threaded on its own chunk of the same workload, so the per-sample times below are
+# measured with every worker busy.  The one-time boundary factor is not part of a step.
+def _cpu_worker_init():
+    import numpy  # noqa: F401  (load BLAS before limiting its threads)
+    import scipy.linalg  # noqa: F401
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        return _cpu_baseline(wl, x_host, budget_note)
+    global _CPU_LIMIT
+    _CPU_LIMIT = threadpool_limits(limits=1)
 
 
-def _cpu_baseline(wl, x_host, budget_note: str) -> dict:
+def _cpu_chunk(job):
+    """(kind, config, lo, hi) -> seconds the oracle takes for that piece on one core."""
     import numpy as np
     import oracle as O
+    from paper_2602_05492_amd import workload as W
+    kind, config, lo, hi = job
+    wl = W.make_config(config)
     S, eps = wl.S, wl.eps
-    # straight handles are evaluated by the oracle as the equivalent cubic handles
     th = wl.theta0 if wl.spec.model == "cubic" else O.straight.embed(wl.theta0)
-    bnd = O.boundary(wl.elems_per_side)                 # one-time factor, not part of a step
-    gp = bnd.gp.reshape(-1, 2)
-    n_eval, n_jac, n_gp = 256, 64, 192
-    xs = x_host[:n_eval]
+    bnd = O.boundary(wl.elems_per_side)
+    if kind in ("rhs", "dF"):
+        pts = bnd.gp.reshape(-1, 2)[lo:hi]
+        t = time.perf_counter()
+        if kind == "rhs":
+            O.handle_term(pts, th, S, eps)
+        else:
+            O.handle_term_jacobian(pts, th, S, eps)
+        return time.perf_counter() - t
+    x = wl.samples(0, n=max(hi, 1))[lo:hi]
     t = time.perf_counter()
-    O.handle_term(xs, th, S, eps)
-    O.element_weights(xs, bnd)
-    t_eval = (time.perf_counter() - t) / n_eval          # per sample, forward
-    t = time.perf_counter()
-    O.handle_term(gp[:n_gp], th, S, eps)
-    t_rhs = (time.perf_counter() - t) / n_gp * len(gp)   # boundary right-hand side, per evaluation
-    t = time.perf_counter()
-    O.handle_term_jacobian(gp[:n_gp], th, S, eps)
-    t_z = (time.perf_counter() - t) / n_gp * len(gp)     # dF/dtheta at the Gauss points, per step
-    Z = np.zeros((bnd.M, 3, th.size))
-    t = time.perf_counter()
-    xj = x_host[:n_jac]
-    J = O.handle_term_jacobian(xj, th, S, eps) + np.einsum("nj,jcp->ncp", O.element_weights(xj, bnd), Z)
-    Jr = J.reshape(-1, th.size)
-    _ = Jr.T @ Jr
-    t_jac = (time.perf_counter() - t) / n_jac            # per sample: J rows + Gram update
+    if kind == "forward":
+        O.handle_term(x, th, S, eps)
+        O.element_weights(x, bnd)
+    else:                                    # J rows (Z given) and their Gram update
+        Z = np.zeros((bnd.M, 3, th.size))
+        J = O.handle_term_jacobian(x, th, S, eps) + np.einsum("nj,jcp->ncp", O.element_weights(x, bnd), Z)
+        Jr = J.reshape(-1, th.size)
+        _ = Jr.T @ Jr
+    return time.perf_counter() - t
+
+
+def cpu_cores() -> int:
+    """Host cores the baseline uses: every core this process may run on, at most 16 (the host
+    share of one GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(config: int) -> dict:
+    """The FP64 oracle timed on bounded pieces of one LM step of the workload, on all host
+    cores, extrapolated linearly in the sample count to one step."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from scipy.linalg import cho_factor
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(config)
+    C = cpu_cores()
+    n_fwd, n_jac, n_gp = 256, 32, 48        # samples and boundary Gauss points per worker
+    bnd = O.boundary(wl.elems_per_side)      # one-time factor (SVD), outside the timed pieces
+    ng = bnd.gp.reshape(-1, 2).shape[0]
+    P = wl.P
+    with mp.get_context("spawn").Pool(C, initializer=_cpu_worker_init) as pool:
+        pool.map(_cpu_chunk, [("forward", config, i, i + 1) for i in range(C)])          # warm the workers
+
+        def timed(jobs):
+            t = time.perf_counter()
+            pool.map(_cpu_chunk, jobs)
+            return time.perf_counter() - t
+
+        t_fwd = timed([("forward", config, i * n_fwd, (i + 1) * n_fwd) for i in range(C)]) / (C * n_fwd)
+        t_jac = timed([("jac", config, i * n_jac, (i + 1) * n_jac) for i in range(C)]) / (C * n_jac)
+        # the boundary right-hand side and dF/dtheta on n_gp Gauss points per worker, scaled to all ng
+        t_rhs = timed([("rhs", config, i * n_gp, (i + 1) * n_gp) for i in range(C)]) * ng / (C * n_gp)
+        t_dF = timed([("dF", config, i * n_gp, (i + 1) * n_gp) for i in range(C)]) * ng / (C * n_gp)
+    th = wl.theta0 if wl.spec.model == "cubic" else O.straight.embed(wl.theta0)
+    rng = np.random.default_rng(0)
+    with threadpool_limits(limits=C):
+        dF = rng.standard_normal((bnd.M, 3 * th.size))
+        t = time.perf_counter()
+        _ = bnd.Apinv @ dF                   # Z = A+ dF/dtheta (boundary_derivative_values)
+        t_z = time.perf_counter() - t
+        B = rng.standard_normal((P, P // 4))
+        Hd = B @ B.T + P * np.eye(P)
+        t = time.perf_counter()
+        cho_factor(Hd, lower=True)           # damped_step's Cholesky of the P x P system
+        t_chol = time.perf_counter() - t
     N = wl.N
-    step = 2 * (N * t_eval + t_rhs) + t_z + N * t_jac
-    return {"value": 1.0 / step, "unit": "LM steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle (numpy FP64, one process) timed on {n_eval} samples (forward), {n_jac} samples "
-                       f"(Jacobian rows + Gram) and {n_gp} of {len(gp)} boundary Gauss points of the workload, "
-                       f"extrapolated linearly to one step of {N:,} samples: {step:.3e} s/step. {budget_note}")}
+    step = 2 * (N * t_fwd + t_rhs) + t_dF + t_z + N * t_jac + t_chol
+    return {"value": 1.0 / step, "unit": "LM steps/s", "cores": C, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"oracle (numpy FP64) on {C} host cores ({cpu_model()}), {C} single-threaded worker processes: "
+                       f"forward on {C * n_fwd} samples, J rows + Gram update on {C * n_jac} samples, the boundary "
+                       f"right-hand side and dF/dtheta at {C * n_gp} of the {ng} Gauss points, then with {C} BLAS threads "
+                       f"Z = A+ dF/dtheta ({bnd.M} x {bnd.M} by {bnd.M} x {3 * th.size}) and the Cholesky of a "
+                       f"{P} x {P} system; extrapolated linearly to one step of {N:,} samples (2 forwards, "
+                       f"2 right-hand sides, dF/dtheta, Z, J^T J, Cholesky): {step:.3e} s/step "
+                       f"(per sample: forward {t_fwd * C:.3e} s, J rows + Gram {t_jac * C:.3e} s on one core).")}
+
+
+def forward_mode(steps: int, warmup: int, do_cpu: bool) -> int:
+    """Near-singular forward (128 cubic handles x 32 segments, 1,048,576 samples of which 10% lie
+    within 1e-3 of a segment): mixed bem_eval throughput, its float64 near-pair share, and the
+    colour error against the float64 GPU path (validated against the oracle by the GPU tests),
+    split into the near and the uniform samples."""
+    config = 3
+    cpu = cpu_forward_baseline(config) if do_cpu else None
+    import torch
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(config)
+    ctx = make_context(wl)
+    N, K, M = wl.N, wl.H * wl.S, ctx.M
+    th = torch.from_numpy(wl.theta_true).cuda()
+    x = torch.from_numpy(wl.samples(0)).cuda()
+    for _ in range(warmup):
+        ctx.eval(th, x, wl.cbar_true, "mixed")
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = ctx.eval(th, x, wl.cbar_true, "mixed")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    t0 = time.perf_counter()
+    u64 = ctx.eval(th, x, wl.cbar_true, "fp64")
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3
+    err = (u.double() - u64).abs().amax(dim=1)
+    n_near = int(round(wl.spec.near_frac * N))
+    pairs = N * (K + M)
+    out = {"metric": "sample x segment pairs/s (mixed forward, near-singular samples)", "value": pairs / (ms * 1e-3),
+           "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": W.SPECS[config].name, "handles": wl.H, "segs_per_handle": wl.S, "samples": N,
+                      "outer_elements": M, "near_samples": n_near},
+           "fp64_gpu_ms": ms64, "fp64_pairs_per_s": pairs / (ms64 * 1e-3), "speedup_vs_fp64_gpu": ms64 / ms,
+           "color_err_vs_fp64": {"max_abs_all": float(err.max()), "max_abs_uniform": float(err[: N - n_near].max()),
+                                 "max_abs_near": float(err[N - n_near:].max()) if n_near else None, "bar": 1e-4},
+           "kernel_ms_per_eval": {k: v[0] / steps for k, v in prof.items() if v[1] > 0},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def adjoint_mode(steps: int, warmup: int, do_cpu: bool) -> int:
+    """Differentiation workload (256 cubic handles x 32 segments, 4,194,304 samples): bem_vjp
+    throughput of the mean-squared-error gradient, mixed and float64, and the gradient's error."""
+    config = 4
+    cpu = cpu_adjoint_baseline(config) if do_cpu else None
+    import torch
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(config)
+    ctx = make_context(wl)
+    N, K, M = wl.N, wl.H * wl.S, ctx.M
+    tht = torch.from_numpy(wl.theta_true).cuda()
+    th = torch.from_numpy(wl.theta0).cuda()
+    x = torch.from_numpy(wl.samples(0)).cuda()
+    T = make_target(ctx, wl, tht, x, 0)
+    g64 = (2.0 / (3 * N)) * (ctx.eval(th, x, wl.cbar_true, "fp64") - T)       # d(mean squared error)/du
+    g32 = g64.float()
+    for _ in range(warmup):
+        ctx.vjp(th, x, g32, "mixed")
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gm = ctx.vjp(th, x, g32, "mixed")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.vjp(th, x, g64, "fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gd = ctx.vjp(th, x, g64, "fp64")
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3
+    rel = float((gm - gd).abs().max() / gd.abs().max())
+    pairs = N * (K + M)
+    out = {"metric": "sample x segment pairs/s (mixed adjoint, bem_vjp)", "value": pairs / (ms * 1e-3),
+           "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": W.SPECS[config].name, "handles": wl.H, "segs_per_handle": wl.S, "samples": N,
+                      "params": wl.P, "outer_elements": M},
+           "handle_pairs_per_s": N * K / (ms * 1e-3), "fp64_gpu_ms": ms64, "fp64_pairs_per_s": pairs / (ms64 * 1e-3),
+           "speedup_vs_fp64_gpu": ms64 / ms,
+           "grad_rel_err_vs_fp64": {"max_abs_over_max": rel, "bar": 1e-3},
+           "kernel_ms_per_vjp": {k: v[0] / steps for k, v in prof.items() if v[1] > 0},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_forward_baseline(config: int) -> dict:
+    import multiprocessing as mp
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(config)
+    C, n = cpu_cores(), 256
+    with mp.get_context("spawn").Pool(C, initializer=_cpu_worker_init) as pool:
+        pool.map(_cpu_chunk, [("forward", config, i, i + 1) for i in range(C)])
+        t = time.perf_counter()
+        pool.map(_cpu_chunk, [("forward", config, i * n, (i + 1) * n) for i in range(C)])
+        t = (time.perf_counter() - t) / (C * n)
+    K, M = wl.H * wl.S, 4 * wl.elems_per_side
+    return {"value": (K + M) / t, "unit": "pairs/s", "cores": C, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"oracle (numpy FP64) forward on {C * n} samples of the workload, {C} single-threaded worker "
+                      f"processes on {C} host cores ({cpu_model()}); the boundary solve (per evaluation, "
+                      f"independent of N) is not included."}
+
+
+def cpu_adjoint_baseline(config: int) -> dict:
+    import multiprocessing as mp
+    from paper_2602_05492_amd import workload as W
+    wl = W.make_config(config)
+    C, n = cpu_cores(), 16
+    with mp.get_context("spawn").Pool(C, initializer=_cpu_worker_init) as pool:
+        pool.map(_cpu_chunk, [("forward", config, i, i + 1) for i in range(C)])
+        t = time.perf_counter()
+        pool.map(_cpu_chunk, [("jac", config, i * n, (i + 1) * n) for i in range(C)])
+        t = (time.perf_counter() - t) / (C * n)
+    K, M = wl.H * wl.S, 4 * wl.elems_per_side
+    return {"value": (K + M) / t, "unit": "pairs/s", "cores": C, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"oracle (numpy FP64) gradient by explicit Jacobian rows on {C * n} samples of the workload "
+                      f"(the oracle's vjp forms J), {C} single-threaded worker processes on {C} host cores "
+                      f"({cpu_model()})."}
 
 
 def main() -> int:
@@ -235,14 +437,16 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--gram", default="bf16x3_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma"])
-    ap.add_argument("--fp64-ref", type=int, default=1, help="also time one plain FP64 GPU step (speedup)")
+    ap.add_argument("--gram", default="bf16x3_mfma", choices=["fp64", "fp32_mfma", "bf16x3_mfma", "fp64_valu"])
+    ap.add_argument("--fp64-ref", type=int, default=1,
+                    help="also time the plain FP64 GPU step (one warm-up, median of 3) for the speedup")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--compat", type=int, default=0,
                     help="enforce the compatibility condition in every LM step (constrained step + re-projection)")
-    ap.add_argument("--workload", default="lm", choices=sorted(WORKLOADS),
-                    help="lm: 256 cubic handles x 32 segments, 2,097,152 samples; paper: 500 straight handles, "
-                         "100,000 samples")
+    ap.add_argument("--workload", default="lm", choices=sorted(WORKLOADS) + ["near", "adjoint"],
+                    help="lm: 256 cubic handles x 32 segments, 2,097,152 samples (LM steps/s); paper: 500 straight "
+                         "handles, 100,000 samples (LM steps/s); near: mixed forward with near-singular samples, "
+                         "1,048,576 samples (pairs/s); adjoint: bem_vjp at 4,194,304 samples (pairs/s)")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
     ap.add_argument("--lm-curve", type=int, default=0,
                     help="instead of timing: run this many LM steps (fresh samples each) and print loss, lambda and "
@@ -257,6 +461,15 @@ def main() -> int:
         print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built; "
               "run with --gpus 1", file=sys.stderr)
         return 2
+    if args.workload == "near":
+        return forward_mode(args.steps, args.warmup, bool(args.cpu_baseline))
+    if args.workload == "adjoint":
+        return adjoint_mode(args.steps, args.warmup, bool(args.cpu_baseline))
+
+    # the CPU baseline's worker processes run before this process initialises the GPU
+    cpu = cpu_baseline(WORKLOADS[args.workload]) if args.cpu_baseline else None
+    if cpu:
+        print(f"cpu baseline: {cpu['value']:.3e} LM steps/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     import numpy as np
     import torch
@@ -270,12 +483,8 @@ def main() -> int:
     nb = args.warmup + args.steps
     tht = torch.from_numpy(wl.theta_true).cuda()
     batches = []
-    x0_host = None
     for i in range(nb):
-        xh = wl.samples(i)
-        if x0_host is None:
-            x0_host = xh
-        x = torch.from_numpy(xh).cuda()
+        x = torch.from_numpy(wl.samples(i)).cuda()
         batches.append((x, make_target(ctx, wl, tht, x, i)))
     theta = torch.from_numpy(wl.theta0).cuda()
     st = B.new_lm_state(wl.lam0, 0, compat=args.compat)
@@ -315,7 +524,7 @@ def main() -> int:
                "vjp_elements": ("alu", PEAKS["fp32_vector"]),
                "features": ("alu", PEAKS["fp32_vector"] if args.prec == "mixed" else PEAKS["fp64_vector"]),
                "gram_mfma": ("mfma", PEAKS["bf16_mfma"] if args.gram == "bf16x3_mfma" else PEAKS["fp32_mfma"]),
-               "gram_f64": ("alu", PEAKS["fp64_vector"])}
+               "gram_f64": ("mfma", PEAKS["fp64_mfma"]) if args.gram == "fp64" else ("alu", PEAKS["fp64_vector"])}
     timed = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max((k for k in timed if k in work), key=lambda k: timed[k][0])
     tot_ms, launches = timed[dom]
@@ -362,20 +571,44 @@ def main() -> int:
                       "hbm_bytes_per_sample": bytes_per_sample,
                       "hbm_gbps": bytes_per_sample * samples_per_s / 1e9, "hbm_frac": bytes_per_sample * samples_per_s / 8e12}
 
+    # colour error of the mixed forward against the float64 path at the start parameters, over
+    # every sample of the first batch (the metric's "at 1e-4 color err")
+    x0 = batches[0][0]
+    th0 = torch.from_numpy(wl.theta0).cuda()
+    cbar0 = tuple(float(v) for v in batches[0][1].mean(0))
+    u_mixed = ctx.eval(th0, x0, cbar0, "mixed")
+    u_f64 = ctx.eval(th0, x0, cbar0, "fp64")
+    color_err = {"max_abs": float((u_mixed.double() - u_f64).abs().max()), "samples": N, "bar": 1e-4,
+                 "against": "float64 GPU path (oracle-validated) at the start parameters, every sample of batch 0"}
+    del u_mixed, u_f64
+
     speedup = None
-    fp64_ms = None
+    fp64 = None
     step_err = None
     if args.fp64_ref and args.prec == "mixed":
-        th64 = torch.from_numpy(wl.theta0).cuda()
-        st64 = B.new_lm_state(wl.lam0, 0, compat=args.compat)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ctx.lm_step(th64, batches[0][0], batches[0][1], st64, "fp64", "fp64")
-        torch.cuda.synchronize()
-        fp64_ms = (time.perf_counter() - t) * 1e3
+        # the plain float64 GPU step (float64 sweeps, float64 Gram on float64 MFMA): one warm-up,
+        # then the median of 3, each from the start parameters on batch 0
+        times, gram_ms = [], []
+        for rep in range(4):
+            th64 = torch.from_numpy(wl.theta0).cuda()
+            st64 = B.new_lm_state(wl.lam0, 0, compat=args.compat)
+            torch.cuda.synchronize()
+            ctx.profile(rep > 0)
+            t = time.perf_counter()
+            ctx.lm_step(th64, batches[0][0], batches[0][1], st64, "fp64", "fp64")
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append((time.perf_counter() - t) * 1e3)
+                gram_ms.append(ctx.profile_read()["gram_f64"][0])
+            ctx.profile(False)
+        fp64_ms = float(np.median(times))
+        g_ms = float(np.median(gram_ms))
+        fp64 = {"ms_per_step": fp64_ms, "runs_ms": times, "gram": "fp64 (float64 MFMA)",
+                "gram_ms": g_ms, "gram_tflops": 2.0 * N * gram_entries(H, M, wl.spec.model) / (g_ms * 1e-3) / 1e12,
+                "gram_peak_tflops": PEAKS["fp64_mfma"] / 1e12}
         speedup = fp64_ms / ms
-        print(f"fp64 reference step: {fp64_ms:.1f} ms (loss {st64.loss_before:.6e} -> {st64.loss_after:.6e})",
-              file=sys.stderr, flush=True)
+        print(f"fp64 reference step: {fp64_ms:.1f} ms (median of {times}), Gram {g_ms:.1f} ms", file=sys.stderr,
+              flush=True)
         # step direction of the reduced-precision Grams against the FP64 step (same batch, same start)
         step_err = {}
         d64 = (th64 - torch.from_numpy(wl.theta0).cuda()).flatten()
@@ -388,11 +621,6 @@ def main() -> int:
                             if (st64.accepted and stg.accepted) else None)
         print(f"step direction vs fp64: {step_err}", file=sys.stderr, flush=True)
 
-    cpu = None
-    if args.cpu_baseline:
-        cpu = cpu_baseline(wl, x0_host, "")
-        cpu["sample"] = cpu["sample"].strip()
-
     out = {
         "metric": METRIC, "value": value, "unit": "LM steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -400,8 +628,8 @@ def main() -> int:
         "config": {"workload": WORKLOAD_TEXT[args.workload], "handle_model": wl.spec.model,
                    "handles": H, "segs_per_handle": S, "samples": N, "params": wl.P, "outer_elements": M,
                    "prec": args.prec, "gram": args.gram, "compat": args.compat, "parallelism": "single GPU"},
-        "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp,
-        "fp64_gpu_ms_per_step": fp64_ms, "speedup_vs_fp64_gpu": speedup,
+        "pairs_per_s_forward": pairs_fwd, "pairs_per_s_adjoint": pairs_vjp, "color_err_vs_fp64": color_err,
+        "fp64_gpu": fp64, "speedup_vs_fp64_gpu": speedup,
         "step_direction_rel_err_vs_fp64": step_err,
         "kernel_ms_per_step": {k: v[0] / steps for k, v in timed.items()},
         "sweep_valu": sweep_valu, "roofline": roofline, "cpu_baseline": cpu,

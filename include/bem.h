@@ -91,13 +91,17 @@ typedef enum {
 typedef enum { BEM_PREC_FP64 = 0, BEM_PREC_MIXED = 1 } bem_prec;
 
 /* Arithmetic of the Gram contraction that forms J^T J and J^T r.
- * FP64         : float64 tiles, float64 accumulation (VALU).
+ * FP64         : float64 tiles, float64 products and accumulation on float64
+ *                MFMA (v_mfma_f64_16x16x4f64).
  * FP32_MFMA    : float32 J tiles, float32 MFMA, float32 accumulation within
  *                a sample tile, float64 across tiles.
  * BF16X3_MFMA  : J split as hi + lo bfloat16, hi*hi + hi*lo + lo*hi on bf16
  *                MFMA with float32 accumulation within a third of a sample
- *                tile, float64 across thirds and tiles (fixed order). */
-typedef enum { BEM_GRAM_FP64 = 0, BEM_GRAM_FP32_MFMA = 1, BEM_GRAM_BF16X3_MFMA = 2 } bem_gram;
+ *                tile, float64 across thirds and tiles (fixed order).
+ * FP64_VALU    : as FP64, with the products on the float64 vector ALUs.
+ * Every float64 product of the library (the Gram's contraction to J^T J, the
+ * boundary derivatives Z = A+ dF/dtheta) runs on float64 MFMA in all modes. */
+typedef enum { BEM_GRAM_FP64 = 0, BEM_GRAM_FP32_MFMA = 1, BEM_GRAM_BF16X3_MFMA = 2, BEM_GRAM_FP64_VALU = 3 } bem_gram;
 
 /* Handle parametrisation (see the conventions above). */
 typedef enum { BEM_HANDLE_CUBIC = 0, BEM_HANDLE_STRAIGHT = 1 } bem_handle_model;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbem.so")
 HEADER = os.path.join(HERE, "..", "include", "bem.h")
 
 PREC = {"fp64": 0, "mixed": 1}
-GRAM = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2}
+GRAM = {"fp64": 0, "fp32_mfma": 1, "bf16x3_mfma": 2, "fp64_valu": 3}
 HANDLE_MODELS = {"cubic": 0, "straight": 1}
 PARAMS_PER_HANDLE = {"cubic": 20, "straight": 10}
 STATUS = {0: "BEM_OK", -1: "BEM_EINVAL", -2: "BEM_ENOMEM", -3: "BEM_ESTATE", -4: "BEM_ENOTPD",

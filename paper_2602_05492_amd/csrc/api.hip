@@ -1,6 +1,5 @@
 // api.hip - the C ABI of include/bem.h: argument checks, call order,
 // workspaces and the orchestration of the kernels of each entry point.
-#include <rocblas/rocblas.h>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -310,7 +309,7 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
     if (N > 0 && !resid) return set_error(ctx, BEM_EINVAL, "resid is null");
     if (H > 0 && (!JtJ || !Jtr)) return set_error(ctx, BEM_EINVAL, "JtJ / Jtr is null");
     if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
-    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA)
+    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA && gram != BEM_GRAM_FP64_VALU)
         return set_error(ctx, BEM_EINVAL, "bad gram mode %d", (int)gram);
     return run_jtj(ctx, theta, H, x, N, resid, prec == BEM_PREC_MIXED, (int)gram, JtJ, Jtr, stream);
 }
@@ -323,7 +322,7 @@ int lm_step(bem_ctx* ctx, double* theta, int32_t H, const double* x, int64_t N, 
     if (!state) return set_error(ctx, BEM_EINVAL, "state is null");
     if (N > 0 && !target) return set_error(ctx, BEM_EINVAL, "target is null");
     if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
-    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA)
+    if (gram != BEM_GRAM_FP64 && gram != BEM_GRAM_FP32_MFMA && gram != BEM_GRAM_BF16X3_MFMA && gram != BEM_GRAM_FP64_VALU)
         return set_error(ctx, BEM_EINVAL, "bad gram mode %d", (int)gram);
     if (state->mean_rule != 0 && state->mean_rule != 1) return set_error(ctx, BEM_EINVAL, "bad mean_rule");
     if (state->compat != 0 && state->compat != 1) return set_error(ctx, BEM_EINVAL, "bad compat flag");
@@ -478,7 +477,6 @@ void bem_destroy(bem_ctx* ctx)
                       &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw, &ctx->sortw,
                       &ctx->tilew};
     for (DevBuf* b : bufs) release(*b);
-    if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
     for (hipEvent_t e : ctx->ev)
         if (e) hipEventDestroy(e);
     if (ctx->s2) hipStreamDestroy(ctx->s2);

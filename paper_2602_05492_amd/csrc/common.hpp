@@ -83,7 +83,6 @@ struct bem_ctx {
     // normal equations the geometry columns of one channel and the channel-shared colour columns
     int model = 0, npar = 20, ngeo = 8, ncol = 4;
     bem_reg reg{};           // regularisation terms of lm_step (all off by default)
-    void* blas = nullptr;    // rocBLAS handle (plain FP64 GEMMs), created on first use
     int64_t chol_P = -1;     // order of the last Cholesky factor (its inverted diagonal blocks are in cholw)
     // second stream (the Gram of a sample tile runs on it while the next tile's feature rows are
     // formed on the caller's stream; the Cholesky's panel and trailing update run on it beside the
@@ -166,8 +165,10 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
 int prepare_forward_tables(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
 int prepare_forward(bem_ctx* ctx, const double* theta, int H, bool mixed, hipStream_t s);
 // gemm.hip
+// plain products and the float64 Gram on float64 MFMA; valu selects the VALU kernel (Gram mode FP64_VALU)
 int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, int64_t lda, bool ta, const double* B,
-             int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles);
+             int64_t ldb, bool tb, double beta, double* C, int64_t ldc, hipStream_t s, const int* tiles, int ntiles,
+             bool valu = false);
 // jtj.hip
 int fill_f64(bem_ctx* ctx, double* p, int64_t n, double v, hipStream_t s);
 int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* resid, bool mixed,

@@ -818,9 +818,11 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // output tile re-reads it
     // sample tile: 32,768 for the split-BF16 Gram (1 GB of blocked bf16 pairs at the LM workload; 3
     // parts of 10,944 samples per launch)
+    // float64 Gram on MFMA (BEM_GRAM_FP64) or on the VALU (BEM_GRAM_FP64_VALU): float64 tiles
+    const bool f64 = gram == BEM_GRAM_FP64 || gram == BEM_GRAM_FP64_VALU;
     int64_t T = ctx->opts.tile_rows > 0 ? ctx->opts.tile_rows
-                                        : (gram == BEM_GRAM_FP32_MFMA ? 8192 : (gram == BEM_GRAM_FP64 ? 16384 : 32768));
-    const size_t elem = gram == BEM_GRAM_FP64 ? 8 : 4;
+                                        : (gram == BEM_GRAM_FP32_MFMA ? 8192 : (f64 ? 16384 : 32768));
+    const size_t elem = f64 ? 8 : 4;
     while (T > 1024 && (size_t)W * T * elem > ((size_t)3 << 30)) T /= 2;
     if (T > N) T = N > 0 ? N : 1;
     T = (T + 63) / 64 * 64;
@@ -843,7 +845,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // (handle segment pairs per sample, H S) is a sizeable share of the Gram's (its distinct output
     // area): from about a third of the Gram's time, H S >= area / 8000.
     const int64_t gram_area = (int64_t)(gram_tiles(L, (int)W, 256).size() / 2) * 256 * 256;
-    const bool shares = gram != BEM_GRAM_FP64 && (int64_t)H * ctx->opts.segs_per_handle * 8000 >= gram_area;
+    const bool shares = !f64 && (int64_t)H * ctx->opts.segs_per_handle * 8000 >= gram_area;
     // default split-BF16 tile when the Gram runs alone: the fewest tiles the tile buffer holds,
     // balanced (fewer Gram launches and partial-Gram read-modify-writes: paper-native step -0.2 ms
     // with 2 tiles of 50,048 samples against 3 of 33,344)
@@ -887,10 +889,9 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         else
             hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)resid, 3 * N, r64);
     }
-    const int ts = gram == BEM_GRAM_FP64 ? 64 : (gram == BEM_GRAM_FP32_MFMA ? 128 : 256);
-    const std::vector<int> tiles = gram == BEM_GRAM_FP64 ? gram_tiles(L, (int)W, ts)
-                                                         : gram_work(gram_tiles(L, (int)W, ts), parts);
-    const int ntiles = gram == BEM_GRAM_FP64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
+    const int ts = gram == BEM_GRAM_FP64_VALU ? 64 : (gram == BEM_GRAM_BF16X3_MFMA ? 256 : 128);
+    const std::vector<int> tiles = f64 ? gram_tiles(L, (int)W, ts) : gram_work(gram_tiles(L, (int)W, ts), parts);
+    const int ntiles = f64 ? (int)tiles.size() / 2 : (int)tiles.size() / 3;
     // the work list lives on the device (tilew); it is uploaded when its configuration changes, the
     // only host synchronisation of this call apart from workspace growth
     const int64_t key[4] = {W, H, ctx->model, gram};
@@ -933,13 +934,13 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         void* tile = (char*)ctx->tmp0.ptr + (size_t)buf * tile_bytes;
         if (overlap && it >= 2 && hipStreamWaitEvent(s, evG[buf], 0) != hipSuccess)
             return set_error(ctx, BEM_EHIP, "stream wait");
-        if (gram == BEM_GRAM_FP64) {
+        if (f64) {
             double* Xt = (double*)tile;
             if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, it > 0 ? 1.0 : 0.0, G, W, s,
-                              dtiles, ntiles);
+                              dtiles, ntiles, gram == BEM_GRAM_FP64_VALU);
             }
             if (rc) return rc;
             if (want_r &&

@@ -31,14 +31,16 @@ def test_jacobian_tiny_matches_oracle():
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("gram", ["fp64", "fp64_valu"])
 @pytest.mark.parametrize("tile_rows", [0, 320])
-def test_jtj_fp64_tiny_matches_oracle(tile_rows):
-    """Several sample tiles and a ragged tail (N = 2085) when tile_rows = 320."""
+def test_jtj_fp64_tiny_matches_oracle(tile_rows, gram):
+    """Several sample tiles and a ragged tail (N = 2085) when tile_rows = 320; the float64 Gram
+    on float64 MFMA and on the VALU."""
     wl = W.make_config(1)
     ctx = ctx_for(wl.S, tile_rows=tile_rows)
     x = wl.samples(0)[:2085]
     r = W.random_vector(51, (len(x), 3))
-    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r), "fp64", "fp64")
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r), gram, "fp64")
     Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps)
     eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
     log("jtj fp64 rel err", eh, "jtr", eg)
@@ -132,6 +134,27 @@ def test_jtj_full_size_properties():
     log(f"full-size jtj: additivity rel err {e_add:.3e}; Jtr vs fp64 adjoint {e_g:.3e}")
     assert e_add < 1e-6
     assert e_g < 1e-3
+
+
+def test_jtj_full_size_matches_fp64_gram():
+    """LM workload at full size (2,097,152 samples in 64 sample tiles, the split-BF16 Gram on the
+    second stream beside the next tile's feature kernels, two tile buffers, partial Grams): J^T J
+    of the split-BF16 and FP32-MFMA Grams on mixed tiles against the FP64 Gram on FP64 tiles of
+    the same batch, element by element, within 1e-4 of the largest entry (the FP64 path matches
+    the oracle to 1e-10 in the tests above)."""
+    wl = W.make_config(5)
+    ctx = ctx_for(wl.S)
+    x = dev(wl.samples(0))
+    th = dev(wl.theta0)
+    r = 0.2 * wl.noise(0)
+    H64, _ = ctx.jtj(th, x, dev(r), "fp64", "fp64")
+    H64 = host(H64)
+    scale = np.abs(H64).max()
+    for gram in ("bf16x3_mfma", "fp32_mfma"):
+        Hm, _ = ctx.jtj(th, x, dev(r, torch.float32), gram, "mixed")
+        e = float(np.abs(host(Hm) - H64).max() / scale)
+        log(f"full-size J^T J {gram}/mixed vs fp64: max abs err / max {e:.3e}")
+        assert e < 1e-4
 
 
 def _lm_compare(wl, x, T, theta, lam, mean_rule, gram, prec, tol_theta):

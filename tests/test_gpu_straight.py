@@ -168,6 +168,39 @@ def test_paper_workload_full_size_sampled():
     assert r64 < 1e-10 and r32 < 1e-3
 
 
+def test_paper_workload_full_size_normal_equations_and_step():
+    """The paper-native workload at full size (500 straight handles, 100,000 samples in two
+    balanced sample tiles): J^T J of the split-BF16 / mixed path element by element against the
+    FP64 Gram's J^T J on the same batch (within 1e-4 of the largest entry), and the mixed LM step
+    (split-BF16 and FP32 MFMA) from the same start within 1.5e-3 (relative, 2-norm) of the FP64
+    step."""
+    wl = W.make_config(W.PAPER_CONFIG)
+    ctx = ctx_for(wl.S, handle_model="straight")
+    x = dev(wl.samples(0))
+    th0 = dev(wl.theta0)
+    T = ctx.eval(dev(wl.theta_true), x, wl.cbar_true, "fp64") + wl.spec.sigma * dev(wl.noise(0))
+    T = T.clamp_(max=wl.spec.target_max)
+    r = 0.1 * wl.noise(0)
+    H64 = host(ctx.jtj(th0, x, dev(r), "fp64", "fp64")[0])
+    scale = np.abs(H64).max()
+    for gram in ("bf16x3_mfma", "fp32_mfma"):
+        e = float(np.abs(host(ctx.jtj(th0, x, dev(r, torch.float32), gram, "mixed")[0]) - H64).max() / scale)
+        log(f"paper workload J^T J {gram}/mixed vs fp64: {e:.3e}")
+        assert e < 1e-4
+    d = {}
+    acc = {}
+    for gram, prec in (("fp64", "fp64"), ("bf16x3_mfma", "mixed"), ("fp32_mfma", "mixed")):
+        th = th0.clone()
+        st = B.new_lm_state(wl.lam0, 0)
+        ctx.lm_step(th, x, T, st, gram, prec)
+        d[gram] = (th - th0).flatten()
+        acc[gram] = st.accepted
+    assert acc["fp64"] and acc["bf16x3_mfma"] and acc["fp32_mfma"]
+    e = {g: float(torch.linalg.norm(d[g] - d["fp64"]) / torch.linalg.norm(d["fp64"])) for g in ("bf16x3_mfma", "fp32_mfma")}
+    log(f"paper workload LM step direction vs FP64: {e}")
+    assert e["bf16x3_mfma"] < 1.5e-3 and e["fp32_mfma"] < 1.5e-3
+
+
 def test_handle_model_validated():
     with pytest.raises(ValueError):
         B.Context(segs_per_handle=1, handle_model="quadratic")
