@@ -413,11 +413,18 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     st->loss_after = L0;
     if (!std::isfinite(L0)) return set_error(ctx, BEM_ENUMERIC, "non-finite loss at the current parameters");
     if (H == 0 || N == 0) return BEM_OK;
-    // gradient by the adjoint, Hessian by the normal equations
-    if ((rc = run_vjp(ctx, theta, H, x, N, r, mixed, g, s, mixed ? &nl : nullptr))) return rc;
-    hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / nd);
-    // the step's right-hand side is the adjoint gradient above, so J^T r is not formed
-    if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr, nd))) return rc;
+    // gradient g = (1/m) J^T r and Hessian H = (1/m) J^T J.  Mixed precision with an MFMA Gram: g is
+    // contracted from the same feature tiles as H (J^T r of each tile, read once more beside its
+    // Gram), so no separate adjoint sweep runs.  Otherwise g comes from the adjoint (bem_vjp's
+    // kernels) and the normal equations form J^T J only.
+    const bool g_from_tiles = mixed && (gram == BEM_GRAM_FP32_MFMA || gram == BEM_GRAM_BF16X3_MFMA);
+    if (g_from_tiles) {
+        if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, g, s, &nl, nd))) return rc;
+    } else {
+        if ((rc = run_vjp(ctx, theta, H, x, N, r, mixed, g, s, mixed ? &nl : nullptr))) return rc;
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(P, 256)), dim3(256), 0, s, g, P, 1.0 / nd);
+        if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, nullptr, s, mixed ? &nl : nullptr, nd))) return rc;
+    }
     // regularisation terms (Sec. 4.4): gradient and Hessian into g and J^T J, value into the loss;
     // the snapping pairs chosen here are kept for the trial point
     const bool reg = reg_active(ctx);

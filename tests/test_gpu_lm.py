@@ -11,7 +11,7 @@ import torch
 import oracle as O
 from paper_2602_05492_amd import bem as B
 from paper_2602_05492_amd import workload as W
-from helpers import ctx_for, dev, host, log
+from helpers import ctx_for, dev, host, log, mixed_step_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -191,7 +191,9 @@ def test_lm_step_tiny_least_squares_mean_and_mixed():
     x = wl.samples(0)[:8192]
     T = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps) + wl.spec.sigma * wl.noise(0)[:8192]
     _lm_compare(wl, x, T, wl.theta0, 1e-3, 1, "fp64", "fp64", 1e-8)
-    _lm_compare(wl, x, T, wl.theta0, 1e-3, 1, "bf16x3_mfma", "mixed", 1e-2)
+    tol = mixed_step_tol(O.normal_equations(wl.theta0, x, np.zeros_like(T), wl.S, wl.eps)[0], 1e-3)
+    log(f"mixed step bar (10 u kappa) {tol:.3e}")
+    _lm_compare(wl, x, T, wl.theta0, 1e-3, 1, "bf16x3_mfma", "mixed", tol)
 
 
 def test_lm_step_medium_matches_oracle():
