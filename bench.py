@@ -133,9 +133,9 @@ def sweep_flops_per_pair():
 
 
 def pmc_probe() -> int:
-    """Small run for byte counters: mixed forward sweep and J^T J on two 32,768-sample tiles (the
-    bench's tile) of the LM workload, then a plain 256 MiB device copy whose counters calibrate
-    FETCH_SIZE / WRITE_SIZE."""
+    """Small run for counters: mixed forward sweep, J^T J on two 32,768-sample tiles (the bench's
+    tile) and the mixed adjoint on the same 65,536 samples of the LM workload, then a plain 256 MiB
+    device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
@@ -144,8 +144,10 @@ def pmc_probe() -> int:
     n = 2 * GRAM_TILE
     x = torch.from_numpy(wl.samples(0)[:n]).cuda()
     r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
-    ctx.eval(torch.from_numpy(wl.theta0).cuda(), x, wl.cbar_true, "mixed")
-    ctx.jtj(torch.from_numpy(wl.theta0).cuda(), x, r, "bf16x3_mfma", "mixed")
+    th = torch.from_numpy(wl.theta0).cuda()
+    ctx.eval(th, x, wl.cbar_true, "mixed")
+    ctx.jtj(th, x, r, "bf16x3_mfma", "mixed")
+    ctx.vjp(th, x, r, "mixed")
     a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)

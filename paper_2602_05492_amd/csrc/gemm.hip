@@ -105,7 +105,7 @@ __device__ inline double slab_load(const double* __restrict__ X, int64_t ldx, in
     return in ? v : 0.0;
 }
 
-__global__ void __launch_bounds__(256) k_gemm_f64_mfma(int m, int n, int k, double alpha, const double* __restrict__ A,
+__global__ void __launch_bounds__(256, 2) k_gemm_f64_mfma(int m, int n, int k, double alpha, const double* __restrict__ A,
                                                        int64_t lda, int ta, const double* __restrict__ B, int64_t ldb,
                                                        int tb, double beta, double* __restrict__ C, int64_t ldc,
                                                        const int* __restrict__ tiles)
