@@ -179,7 +179,7 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
                      const int* work, int nwork, int64_t kchunk, double* G, int64_t gstride, bool accumulate,
                      hipStream_t s);
 int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-              const double* r, double* R, double* Rp, hipStream_t s);
+              const double* r, double* R, double* Rp, hipStream_t s, int f0 = 0);
 constexpr int kXrPartials = 32;   // sample-block groups of the split-BF16 X r (workspace kXrPartials * W * 3)
 // chol.hip
 int chol_factor(bem_ctx* ctx, const double* H, int64_t P, double lam, double* A, int* dflag, double* dscal,

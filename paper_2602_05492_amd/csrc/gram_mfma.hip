@@ -289,10 +289,10 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
 
 // R[f][c] += sum_t X[f][t] r[t][c]  (float64 sums; float rows of stride ld)
 __global__ void __launch_bounds__(256) k_xr_f32(const float* __restrict__ X, int64_t ld, int64_t n,
-                                                const double* __restrict__ r, double* __restrict__ R)
+                                                const double* __restrict__ r, double* __restrict__ R, int f0)
 {
     __shared__ double red[3][256];
-    const int64_t f = blockIdx.x;
+    const int64_t f = f0 + (int64_t)blockIdx.x;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
         const double v = (double)X[f * ld + t];
@@ -317,10 +317,10 @@ constexpr int kXrGroups = kXrPartials;
 
 __global__ void __launch_bounds__(256) k_xr_bf16(const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl, int W,
                                                  int64_t n, int64_t blocks_per_group, const double* __restrict__ r,
-                                                 double* __restrict__ Rp)
+                                                 double* __restrict__ Rp, int f0)
 {
     const int lane = threadIdx.x & 63;
-    const int f = blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + (lane >> 2);
+    const int f = f0 + blockIdx.x * 64 + (threadIdx.x >> 6) * 16 + (lane >> 2);
     const int cq = lane & 3;
     const int64_t nb = (n + 31) / 32;
     const int64_t b0 = (int64_t)blockIdx.y * blocks_per_group;
@@ -351,10 +351,10 @@ __global__ void __launch_bounds__(256) k_xr_bf16(const uint16_t* __restrict__ Xh
     }
 }
 
-// R[f][c] += sum_g Rp[g][f][c] (fixed order)
-__global__ void k_xr_finish(const double* __restrict__ Rp, int W, int groups, double* __restrict__ R)
+// R[f][c] += sum_g Rp[g][f][c] (fixed order), rows f >= f0
+__global__ void k_xr_finish(const double* __restrict__ Rp, int W, int groups, double* __restrict__ R, int f0)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = 3 * f0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 3 * W) return;
     double v = 0.0;
     for (int g = 0; g < groups; ++g) v += Rp[(size_t)g * 3 * W + i];
@@ -389,20 +389,23 @@ int launch_gram_mfma(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xl
     return check_launch(ctx, "gram_mfma");
 }
 
-// R += X r over one sample tile; Rp is a workspace of kXrGroups * W * 3 doubles (split-BF16 only).
+// R += X r over one sample tile for the rows [f0, W); Rp is a workspace of kXrGroups * W * 3 doubles
+// (split-BF16 only).
 int launch_xr(bem_ctx* ctx, int gram, const void* Xhi, const uint16_t* Xlo, int64_t ld, int W, int64_t n,
-              const double* r, double* R, double* Rp, hipStream_t s)
+              const double* r, double* R, double* Rp, hipStream_t s, int f0)
 {
-    if (n <= 0) return BEM_OK;
+    if (n <= 0 || f0 >= W) return BEM_OK;
     ProfScope ps_(ctx, PT_XR, s);
+    const int rows = W - f0;
     if (gram == BEM_GRAM_BF16X3_MFMA) {
         const int64_t nb = (n + 31) / 32;
         const int64_t per = (nb + kXrGroups - 1) / kXrGroups;
-        hipLaunchKernelGGL(k_xr_bf16, dim3((W + 63) / 64, kXrGroups), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, W, n,
-                           per, r, Rp);
-        hipLaunchKernelGGL(k_xr_finish, dim3((3 * W + 255) / 256), dim3(256), 0, s, (const double*)Rp, W, kXrGroups, R);
+        hipLaunchKernelGGL(k_xr_bf16, dim3((rows + 63) / 64, kXrGroups), dim3(256), 0, s, (const uint16_t*)Xhi, Xlo, W,
+                           n, per, r, Rp, f0);
+        hipLaunchKernelGGL(k_xr_finish, dim3((3 * rows + 255) / 256), dim3(256), 0, s, (const double*)Rp, W, kXrGroups,
+                           R, f0);
     } else {
-        hipLaunchKernelGGL(k_xr_f32, dim3(W), dim3(256), 0, s, (const float*)Xhi, ld, n, r, R);
+        hipLaunchKernelGGL(k_xr_f32, dim3(rows), dim3(256), 0, s, (const float*)Xhi, ld, n, r, R, f0);
     }
     return check_launch(ctx, "xr");
 }

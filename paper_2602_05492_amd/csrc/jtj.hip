@@ -104,6 +104,119 @@ __global__ void k_zero_pad(OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, in
     Store<OutT>::put(Xt, Xlo, (r / pad) * gp + gh + r % pad, t, ld, 0.0);
 }
 
+// ---- J^T r of the handle rows, formed with the features -------------------------------
+// Per (sample, handle) the products of its feature rows with the sample's residuals:
+// v[8 c + q] = geo[c][q] r_c (the channel-c geometry rows), v[24 + 3 m + c] = col[m] r_c (the
+// channel-shared colour rows against each channel's residual): 36 values, summed over the 256
+// samples of a block in float32 (wavefront reduction, then the 4 wavefronts through LDS) and
+// stored per block; k_jtr_handles adds the blocks in float64.
+constexpr int kJtrVals = 36;
+
+// Sum of v over the 64 lanes of a wavefront for v[0..31] by recursive halving (after the steps
+// with offsets 32, 16, 8, 4, 2 lane l holds the sum over its half-wavefront of v[(l >> 1) & 31],
+// the offset-1 step completes it), and for v[32..35] by butterflies; the 4 wavefronts' sums are
+// then added through LDS and written to out[0..35].
+template <class A>
+__device__ inline void handle_jtr_block(const A (&geo)[3][8], const A (&col)[4], float r0, float r1, float r2,
+                                        float (*red)[kJtrVals], float* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float v[32];
+    float e[4];
+    const float r[3] = {r0, r1, r2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[8 * c + q] = (float)geo[c][q] * r[c];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = 24 + 3 * m + c;
+            const float p = (float)col[m] * r[c];
+            if (i < 32) v[i] = p;
+            else e[i - 32] = p;
+        }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int half = 16 >> k, o = 32 >> k;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < half) {
+                const float keep = up ? v[i + half] : v[i];
+                const float send = up ? v[i] : v[i + half];
+                v[i] = keep + __shfl_xor(send, o, 64);
+            }
+        }
+    }
+    v[0] += __shfl_xor(v[0], 1, 64);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[i] += __shfl_xor(e[i], 32 >> k, 64);
+    if ((lane & 1) == 0) red[wave][(lane >> 1) & 31] = v[0];
+    if (lane < 4) red[wave][32 + lane] = e[lane];
+    __syncthreads();
+    if (threadIdx.x < kJtrVals)
+        out[threadIdx.x] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// Feature row of product v of handle h (cubic: rows as store_handle_rows; straight: geometry q < 4,
+// the colour products of m = 0, 1 (wd) and m = 2, 3 (wc) go to the one constant-jump row) and its
+// channel; -1 for a product that has no row (straight geometry q >= 4).
+__host__ __device__ inline int64_t jtr_row(int model, int v, int h, int64_t gp, int* c)
+{
+    if (v < 24) {
+        const int cc = v / 8, q = v % 8;
+        *c = cc;
+        if (model == 1) return q < 4 ? (int64_t)cc * gp + 4 * h + q : -1;
+        return (int64_t)cc * gp + 8 * h + q;
+    }
+    const int m = (v - 24) / 3;
+    *c = (v - 24) % 3;
+    if (model == 1) return 3 * gp + 2 * h + (m >> 1);
+    return 3 * gp + 4 * h + m;
+}
+
+// R[row][c] += sum over the tile's blocks of rpart[block][h][v] (float64, fixed order): thread per
+// (h, v) pair.  For straight handles the two products that share a row are added by the thread of
+// the first (m even) of them.
+__global__ void __launch_bounds__(256) k_jtr_handles(const float* __restrict__ rpart, int nblocks, int H, int model,
+                                                     int64_t gp, double* __restrict__ R)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H * kJtrVals) return;
+    const int h = i / kJtrVals, v = i % kJtrVals;
+    int c;
+    const int64_t row = jtr_row(model, v, h, gp, &c);
+    if (row < 0) return;
+    const bool pair = model == 1 && v >= 24 && (((v - 24) / 3) & 1) == 0;   // m even: also take m + 1
+    if (model == 1 && v >= 24 && !pair) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const float* pb = rpart + ((size_t)b * H + h) * kJtrVals;
+        acc += (double)pb[v];
+        if (pair) acc += (double)pb[v + 3];
+    }
+    R[row * 3 + c] += acc;
+}
+
+// J^T r of one flagged sample's handle rows (the inline kernel): float64 atomics into R.
+template <class A>
+__device__ inline void handle_jtr_atomic(int model, int h, int64_t gp, const A (&geo)[3][8], const A (&col)[4],
+                                         const float* rr, double* __restrict__ R)
+{
+#pragma unroll
+    for (int v = 0; v < kJtrVals; ++v) {
+        int c;
+        const int64_t row = jtr_row(model, v, h, gp, &c);
+        if (row < 0) continue;
+        const double f = v < 24 ? (double)geo[v / 8][v % 8] : (double)col[(v - 24) / 3];
+        atomicAdd(R + row * 3 + c, f * (double)rr[c]);
+    }
+}
+
 // Handle features of one point and one handle (thread per (point, handle)):
 //   rows c*8H + 8h + 2j + d : d f_c / d P_{h,j,d}      (c = 0..2, j = 0..3, d = x, y)
 //   rows 24H + 4h + m       : coefficient of wd0, wd1, wc0, wc1 of handle h (any channel)
@@ -118,7 +231,8 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
                                                   const double* __restrict__ seg64, const float* __restrict__ seg32,
                                                   int H, int S, int model, int64_t gp, double eps2, float eps2f,
                                                   float near2, const uint8_t* __restrict__ only,
-                                                  OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld)
+                                                  OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld,
+                                                  const float* __restrict__ rr = nullptr, double* __restrict__ R = nullptr)
 {
     using A = typename std::conditional<Mixed, float, double>::type;
     const int h = blockIdx.y;
@@ -192,6 +306,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
             }
         }
         store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
+        if (rr) handle_jtr_atomic(model, h, gp, geo, col, rr + 3 * t, R);     // J^T r of a flagged sample
     }
 }
 
@@ -212,69 +327,85 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
                                                       const int2* __restrict__ runs,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
                                                       const float* __restrict__ vtab, OutT* __restrict__ Xt,
-                                                      uint16_t* __restrict__ Xlo, int64_t ld)
+                                                      uint16_t* __restrict__ Xlo, int64_t ld,
+                                                      const float* __restrict__ rr, float* __restrict__ rpart)
 {
+    __shared__ float jtr_red[4][kJtrVals];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = blockIdx.y;
-    if (t >= npts) return;
-    const float Xf = (float)x[2 * t], Yf = (float)x[2 * t + 1];
+    const bool valid = t < npts;
     float geo[3][8];
     float col[4] = {0.f, 0.f, 0.f, 0.f};
-    float pv[3][2];
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c)
         for (int q = 0; q < 8; ++q) geo[c][q] = 0.f;
-        pv[c][0] = pv[c][1] = 0.f;
-    }
-    for (int j = 0; j <= S; ++j) {
-        float va[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-        float vb[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-        if (j < S) {
-            const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
-            const SegGeom<float> gf = load_geom(s32);
-            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
-            if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
-                const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-                const Moments<float> m = pair_moments(gf, st);
-                for (int c = 0; c < 3; ++c) {
-                    const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
-                                                          s32[kWcA + c], s32[kWcB + c]);
-                    va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
+    bool take = false;
+    if (valid) {
+        const float Xf = (float)x[2 * t], Yf = (float)x[2 * t + 1];
+        float pv[3][2];
+        for (int c = 0; c < 3; ++c) pv[c][0] = pv[c][1] = 0.f;
+        for (int j = 0; j <= S; ++j) {
+            float va[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+            float vb[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+            if (j < S) {
+                const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
+                const SegGeom<float> gf = load_geom(s32);
+                // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
+                if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
+                    const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                    const Moments<float> m = pair_moments(gf, st);
+                    for (int c = 0; c < 3; ++c) {
+                        const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
+                                                              s32[kWcA + c], s32[kWcB + c]);
+                        va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
+                    }
+                    const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
+                    const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
+                    col[0] += m.da * sa_ + m.db * sb_;
+                    col[1] += m.da * ta + m.db * tb;
+                    col[2] += m.sa * sa_ + m.sb * sb_;
+                    col[3] += m.sa * ta + m.sb * tb;
                 }
-                const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
-                const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
-                col[0] += m.da * sa_ + m.db * sb_;
-                col[1] += m.da * ta + m.db * tb;
-                col[2] += m.sa * sa_ + m.sb * sb_;
-                col[3] += m.sa * ta + m.sb * tb;
+            }
+            const float* B = vtab + 8 * j;
+            for (int c = 0; c < 3; ++c) {
+                const float gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
+                for (int q = 0; q < 4; ++q) {
+                    geo[c][2 * q] += B[q] * gx;
+                    geo[c][2 * q + 1] += B[q] * gy;
+                }
+                pv[c][0] = vb[c][0];
+                pv[c][1] = vb[c][1];
             }
         }
-        const float* B = vtab + 8 * j;
-        for (int c = 0; c < 3; ++c) {
-            const float gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
-            for (int q = 0; q < 4; ++q) {
-                geo[c][2 * q] += B[q] * gx;
-                geo[c][2 * q + 1] += B[q] * gy;
-            }
-            pv[c][0] = vb[c][0];
-            pv[c][1] = vb[c][1];
+        const int64_t i = t0 + t;
+        take = !flag[i];
+        // the wavefront's index within the tile (the same for all its lanes, as t0 is a multiple of 64)
+        const int wl = __builtin_amdgcn_readfirstlane((int)(t >> 6));
+        const int2 run = runs[(size_t)wl * H + h];
+        const NearPair* sl = list + ((t0 >> 6) + wl) * (int64_t)slots;
+        const float* cw = corr + (size_t)wl * slots * kFeatVals;
+        for (int e = run.x; e < run.y; ++e) {
+            const NearPair p = sl[e];
+            if (!take || p.sample != (int32_t)i) continue;
+            const float* cr = cw + (size_t)e * kFeatVals;
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 8; ++q) geo[c][q] += cr[8 * c + q];
+            for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
         }
+        store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
     }
-    const int64_t i = t0 + t;
-    const bool take = !flag[i];
-    // the wavefront's index within the tile (the same for all its lanes, as t0 is a multiple of 64)
-    const int wl = __builtin_amdgcn_readfirstlane((int)(t >> 6));
-    const int2 run = runs[(size_t)wl * H + h];
-    const NearPair* sl = list + ((t0 >> 6) + wl) * (int64_t)slots;
-    const float* cw = corr + (size_t)wl * slots * kFeatVals;
-    for (int e = run.x; e < run.y; ++e) {
-        const NearPair p = sl[e];
-        if (!take || p.sample != (int32_t)i) continue;
-        const float* cr = cw + (size_t)e * kFeatVals;
-        for (int c = 0; c < 3; ++c)
-            for (int q = 0; q < 8; ++q) geo[c][q] += cr[8 * c + q];
-        for (int q = 0; q < 4; ++q) col[q] += cr[24 + q];
+    // with rr (the tile's residuals) the block also forms its part of J^T r over its samples and
+    // this handle's rows; every thread joins the reduction (samples past the tile and flagged
+    // samples, whose rows and J^T r the inline kernel rewrites, with zero residual)
+    if (rr) {
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+        if (valid && take) {
+            r0 = rr[3 * t];
+            r1 = rr[3 * t + 1];
+            r2 = rr[3 * t + 2];
+        }
+        handle_jtr_block(geo, col, r0, r1, r2, jtr_red, rpart + ((size_t)blockIdx.x * H + h) * kJtrVals);
     }
-    store_handle_rows(model, Xt, Xlo, H, h, t, ld, gp, geo, col);
 }
 
 // Ranges of each handle's entries in the near-pair slices of a tile's wavefronts
@@ -636,11 +767,13 @@ static Layout layout_of(const bem_ctx* ctx, int H)
 // first global sample index t0 (a multiple of 64), the global samples xg and a
 // correction buffer of ceil(npts / 64) * nl->slots * 28 floats and a run table of
 // ceil(npts / 64) * H entries.
+// With rr (float residuals of the npts samples, mixed only) J^T r of the handle rows is added into
+// R [W][3] as the features are formed (block partial sums in rpart, ceil(npts / 256) * H * 36 floats).
 template <class OutT>
 static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
                            uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
                            const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr,
-                           int2* runs = nullptr)
+                           int2* runs = nullptr, const float* rr = nullptr, float* rpart = nullptr, double* R = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -667,12 +800,15 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
                                H, S, model, gp, (float)eps2, near2, nl->list, nl->slots, (const int2*)runs, nl->flag, corr,
-                               vtab, Xt, Xlo, ld);
+                               vtab, Xt, Xlo, ld, rr, rpart);
+            if (rr)
+                hipLaunchKernelGGL(k_jtr_handles, dim3(blocks_for((int64_t)H * kJtrVals, 256)), dim3(256), 0, s,
+                                   (const float*)rpart, (int)grid.x, H, model, gp, R);
             const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
             if (nl->overflowed)
                 hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
                                (const float*)ctx->seg32.ptr, H, S, model, gp, eps2, (float)eps2, near2, nl->flag + t0,
-                               Xt, Xlo, ld);
+                               Xt, Xlo, ld, rr, R);
         } else {
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features<false, OutT>), grid, dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
@@ -914,11 +1050,18 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         else if ((rc = near_classify(ctx, ctx->nearf, x, N, H * ctx->opts.segs_per_handle, 0, &nl, s))) return rc;
     }
     const size_t corr_bytes = mixed ? ((size_t)((T + 63) / 64) * nl.slots * kFeatVals * sizeof(float) + 255) / 256 * 256 : 0;
-    const size_t runs_bytes = mixed ? (size_t)((T + 63) / 64) * H * sizeof(int2) : 0;
-    if ((rc = ensure(ctx, ctx->tmp5, vtab_bytes + corr_bytes + runs_bytes + 256, s))) return rc;
+    const size_t runs_bytes = mixed ? ((size_t)((T + 63) / 64) * H * sizeof(int2) + 255) / 256 * 256 : 0;
+    // mixed tiles for an MFMA Gram: J^T r of the handle rows is summed as the features are formed
+    // (float32 per 256-sample block, float64 across blocks); only the beta rows are read back
+    const bool fused_r = want_r && mixed && !f64;
+    const size_t rpart_bytes = fused_r ? (size_t)blocks_for(T, 256) * H * kJtrVals * sizeof(float) : 0;
+    if ((rc = ensure(ctx, ctx->tmp5, vtab_bytes + corr_bytes + runs_bytes + rpart_bytes + 256, s))) return rc;
     float* vtab = (float*)ctx->tmp5.ptr;
     float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes) : nullptr;
     int2* runs = mixed ? (int2*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes) : nullptr;
+    float* rpart = fused_r ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes + runs_bytes) : nullptr;
+    const float* rr = fused_r ? (const float*)resid : nullptr;
+    const int xr_row0 = fused_r ? (int)L.handle_rows() : 0;
     hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
     hipEvent_t* evF = ctx->ev;          // features of the tile in buffer b done
     hipEvent_t* evG = ctx->ev + 2;      // Gram of the tile in buffer b done
@@ -948,24 +1091,30 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 return rc;
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)tile;
-            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
+            if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs,
+                                             rr ? rr + 3 * t0 : nullptr, rpart, R)))
+                return rc;
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
             if ((rc = launch_gram_mfma(ctx, gram, Xt, nullptr, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, it > 0, sg)))
                 return rc;
-            if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xt, nullptr, T, (int)W, n, r64 + 3 * t0, R, Rp, sg, xr_row0)))
+                return rc;
         } else {
             uint16_t* Xh = (uint16_t*)tile;
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
-            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab, runs))) return rc;
+            if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab, runs,
+                                                rr ? rr + 3 * t0 : nullptr, rpart, R)))
+                return rc;
             if (n & 31)
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, it > 0, sg)))
                 return rc;
-            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg))) return rc;
+            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg, xr_row0)))
+                return rc;
         }
         if (overlap && hipEventRecord(evG[buf], sg) != hipSuccess) return set_error(ctx, BEM_EHIP, "stream event");
     }
