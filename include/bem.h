@@ -225,6 +225,24 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
 int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
             const void* gbar, double* grad, bem_prec prec, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bem_vjp in FP64 that
+ * calls no hipMalloc / hipFree and no allocating library routine.  Same
+ * arguments and result as bem_vjp(..., BEM_PREC_FP64, ...) (gbar float64), to
+ * rounding: every workspace of the call (segment and element tables, partial
+ * sums, psi, mu, the boundary Gauss points) is carved from a static 64 MiB
+ * device array of the library, one per device, held until the process ends
+ * (its address is looked up once per device on the first call there).  The
+ * context must be built and factored (those calls allocate).  Sizes whose
+ * workspace exceeds the array fail with BEM_EINVAL and a message: with
+ * M = 1024 outer elements every K = H*S <= 13,376 segments fits for any N
+ * (the LM workload's 8,192 take 53.5 MiB); nothing needs to start at zero.  Every call on a device shares that device's array, so calls that
+ * overlap on one device (two streams, two threads, two contexts) race: the
+ * caller must serialise them.  No profiling events are recorded for the call.
+ * Errors: as bem_vjp. */
+int bem_vjp_noalloc(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+                    const double* gbar, double* grad, hipStream_t stream);
+
 /* Monte Carlo normal equations with uniform samples (p = 1 on the unit
  * square; Eq. losshessian, Eq. lossjacobian):
  *   JtJ = (1/N) sum_x sum_c J_c(x)^T J_c(x)   [P,P] float64 (full, symmetric)

@@ -65,6 +65,7 @@ _SIGS = {
     "bem_factor": (ctypes.c_int, [P, P]),
     "bem_eval": (ctypes.c_int, [P, P, I32, P, I64, ctypes.POINTER(ctypes.c_double), P, ctypes.c_int, P]),
     "bem_vjp": (ctypes.c_int, [P, P, I32, P, I64, P, P, ctypes.c_int, P]),
+    "bem_vjp_noalloc": (ctypes.c_int, [P, P, I32, P, I64, P, P, P]),
     "bem_jtj": (ctypes.c_int, [P, P, I32, P, I64, P, P, P, ctypes.c_int, ctypes.c_int, P]),
     "lm_step": (ctypes.c_int, [P, P, I32, P, I64, P, ctypes.POINTER(LMState), ctypes.c_int, ctypes.c_int, P]),
     "bem_jacobian": (ctypes.c_int, [P, P, I32, P, I64, P, P]),
@@ -253,6 +254,14 @@ class Context:
         else:
             _check_dev("out", out, torch.float64, (H, self.Q))
         self._check(lib().bem_vjp(self._h, _ptr(theta), H, _ptr(x), N, _ptr(gbar), _ptr(out), PREC[prec], _stream()))
+        return out
+
+    def vjp_noalloc(self, theta, x, gbar, out) -> torch.Tensor:
+        """bem_vjp_noalloc: the float64 adjoint into a caller-allocated out [H, Q], allocating nothing."""
+        H, N = self._theta_x(theta, x)
+        _check_dev("gbar", gbar, torch.float64, (N, 3))
+        _check_dev("out", out, torch.float64, (H, self.Q))
+        self._check(lib().bem_vjp_noalloc(self._h, _ptr(theta), H, _ptr(x), N, _ptr(gbar), _ptr(out), _stream()))
         return out
 
     def jtj(self, theta, x, resid, gram: str = "fp64", prec: str = "fp64"):

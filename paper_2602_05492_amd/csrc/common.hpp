@@ -124,6 +124,8 @@ struct ProfScope {
     ~ProfScope() { prof_end(ctx, tag, s, start); }
 };
 int ensure(bem_ctx* ctx, DevBuf& b, size_t bytes, hipStream_t stream);
+// argument checks shared by the per-call entry points; makes the context's device current
+int check_common(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N);
 int aux_stream(bem_ctx* ctx, hipStream_t* out);
 int check_launch(bem_ctx* ctx, const char* what);
 
@@ -136,9 +138,11 @@ int launch_assemble(bem_ctx* ctx, hipStream_t s);
 int launch_factor(bem_ctx* ctx, hipStream_t s);
 // forward.hip
 int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s);
+int launch_expand_into(bem_ctx* ctx, const double* theta, int H, double* seg64, float* seg32, hipStream_t s);
 int launch_boundary_rhs(bem_ctx* ctx, int K, double* F, bool mixed, hipStream_t s);
 int launch_boundary_solve(bem_ctx* ctx, const double* F, double* U, bool transpose, hipStream_t s);
 int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s);
+int launch_pack_elements_into(bem_ctx* ctx, const double* U, double* el64, float* el32, hipStream_t s);
 int launch_sweep_f64(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, double* u, hipStream_t s);
 // The mixed sweeps share one near-pair list layout (sweep_common.hpp).  The
 // forward sweep returns the list it built (valid until the next mixed sweep);
@@ -158,8 +162,14 @@ int reg_terms(bem_ctx* ctx, const double* theta, int H, bool choose, double* g, 
               hipStream_t s);
 int run_prune(bem_ctx* ctx, double* theta, int H, double thr, int* H_out, hipStream_t s);
 // vjp.hip
+// Device memory the float64 adjoint may carve every workspace from instead of allocating (the
+// allocation-free entry point's static array); null: the context's workspaces.
+struct Carve {
+    char* base;
+    size_t bytes;
+};
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
-            double* grad, hipStream_t s, const NearList* pre = nullptr);
+            double* grad, hipStream_t s, const NearList* pre = nullptr, const Carve* carve = nullptr);
 // api.hip: expand + element tables (no boundary solve); and the whole forward set-up
 // (expand, boundary right-hand side (float32 far pairs when mixed), boundary solve, element tables)
 int prepare_forward_tables(bem_ctx* ctx, const double* theta, int H, hipStream_t s);

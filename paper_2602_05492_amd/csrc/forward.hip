@@ -223,15 +223,20 @@ __global__ void __launch_bounds__(256) k_sweep_f64(const double* __restrict__ x,
 
 int launch_expand(bem_ctx* ctx, const double* theta, int H, hipStream_t s)
 {
-    const int S = ctx->opts.segs_per_handle;
-    const int K = H * S;
+    const int K = H * ctx->opts.segs_per_handle;
     int rc;
     const size_t n = (size_t)(K > 0 ? K : 1) * kSegStride;
     if ((rc = ensure(ctx, ctx->seg64, n * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->seg32, n * sizeof(float), s))) return rc;
+    return launch_expand_into(ctx, theta, H, (double*)ctx->seg64.ptr, (float*)ctx->seg32.ptr, s);
+}
+
+int launch_expand_into(bem_ctx* ctx, const double* theta, int H, double* seg64, float* seg32, hipStream_t s)
+{
+    const int S = ctx->opts.segs_per_handle;
+    const int K = H * S;
     if (K == 0) return BEM_OK;
-    hipLaunchKernelGGL(k_expand, dim3(blocks_for(K, 256)), dim3(256), 0, s, theta, H, S, ctx->model,
-                       (double*)ctx->seg64.ptr, (float*)ctx->seg32.ptr);
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(K, 256)), dim3(256), 0, s, theta, H, S, ctx->model, seg64, seg32);
     return check_launch(ctx, "expand");
 }
 
@@ -264,8 +269,13 @@ int launch_pack_elements(bem_ctx* ctx, const double* U, hipStream_t s)
     int rc;
     if ((rc = ensure(ctx, ctx->elem64, (size_t)ctx->M * kElemStride * sizeof(double), s))) return rc;
     if ((rc = ensure(ctx, ctx->elem32, (size_t)ctx->M * kElemStride * sizeof(float), s))) return rc;
+    return launch_pack_elements_into(ctx, U, (double*)ctx->elem64.ptr, (float*)ctx->elem32.ptr, s);
+}
+
+int launch_pack_elements_into(bem_ctx* ctx, const double* U, double* el64, float* el32, hipStream_t s)
+{
     hipLaunchKernelGGL(k_pack_elements, dim3(blocks_for(ctx->M, 256)), dim3(256), 0, s, U, ctx->M, (const double*)ctx->egeo.ptr,
-                       (double*)ctx->elem64.ptr, (float*)ctx->elem32.ptr);
+                       el64, el32);
     return check_launch(ctx, "pack_elements");
 }
 

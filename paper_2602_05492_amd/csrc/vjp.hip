@@ -16,6 +16,8 @@
 // loads).  Four wavefronts of a block split the chunk and are summed through
 // LDS; chunks are summed by a separate fixed-order pass, so results do not
 // depend on scheduling.
+#include <mutex>
+
 #include "common.hpp"
 #include "sweep_common.hpp"
 
@@ -372,8 +374,27 @@ int chunks_for(int64_t N, int groups, int64_t& chunk)
 
 }  // namespace
 
+// Bytes of device workspace the float64 adjoint carves for K segments, M elements and N samples
+// (tables, partial sums, psi, mu, boundary Gauss points, segment sums), each piece 256-aligned.
+static size_t carve_round(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t vjp_f64_workspace_bytes(int K, int M, int64_t N)
+{
+    const int kgroups = (K + 63) / 64, mgroups = (M + 63) / 64;
+    int64_t c = 1;
+    const int ns = N > 0 ? chunks_for(N, kgroups, c) : 0;
+    const int ng = chunks_for(3 * (int64_t)M, kgroups, c);
+    const int ne = N > 0 ? chunks_for(N, mgroups, c) : 0;
+    const size_t k1 = (size_t)(K > 0 ? K : 1);
+    return carve_round(k1 * kSegStride * sizeof(double)) + carve_round(k1 * kSegStride * sizeof(float)) +
+           carve_round((size_t)M * kElemStride * sizeof(double)) + carve_round((size_t)M * kElemStride * sizeof(float)) +
+           carve_round((size_t)M * 3 * sizeof(double)) + carve_round((size_t)(ns + ng) * k1 * kV * sizeof(double)) +
+           carve_round(((size_t)(ne > 0 ? ne : 1) * M * 3 + 2 * (size_t)M * 3) * sizeof(double)) +
+           carve_round((size_t)3 * M * 5 * sizeof(double)) + carve_round(k1 * kV * sizeof(double));
+}
+
 int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N, const void* gbar, bool mixed,
-            double* grad, hipStream_t s, const NearList* pre)
+            double* grad, hipStream_t s, const NearList* pre, const Carve* carve)
 {
     int rc;
     const int S = ctx->opts.segs_per_handle;
@@ -383,9 +404,7 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const double nf = near_radius(ctx->opts.near_factor);
     const float near2 = (float)(nf * nf);
     if (H == 0) return BEM_OK;
-    if ((rc = launch_expand(ctx, theta, H, s))) return rc;
-    if ((rc = ensure(ctx, ctx->U, (size_t)M * 3 * sizeof(double), s))) return rc;
-    if ((rc = launch_pack_elements(ctx, (const double*)ctx->U.ptr, s))) return rc;   // element geometry only
+    if (carve && mixed) return set_error(ctx, BEM_EINVAL, "the carved adjoint is float64 only (internal)");
     const int kgroups = (K + 63) / 64, mgroups = (M + 63) / 64;
     int64_t chunk_s = 1, chunk_g = 1, chunk_e = 1;
     const int ns = N > 0 ? chunks_for(N, kgroups, chunk_s) : 0;
@@ -394,21 +413,55 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const int extra = mixed && N > 0 ? kNearCopies : 0; // partial rows for the float64 near pairs
     const size_t seg_part = (size_t)(ns + ng + extra) * K * kV;
     const size_t el_rows = (size_t)(ne > 0 ? ne : 1) + extra;
-    // workspaces: tmp1 segment partials, tmp2 element partials + psi + mu, tmp3 Gauss points, red segment sums
-    if ((rc = ensure(ctx, ctx->tmp1, seg_part * sizeof(double), s))) return rc;
-    if ((rc = ensure(ctx, ctx->tmp2, (el_rows * M * 3 + 2 * (size_t)M * 3) * sizeof(double), s))) return rc;
-    if ((rc = ensure(ctx, ctx->tmp3, (size_t)3 * M * 5 * sizeof(double), s))) return rc;
-    if ((rc = ensure(ctx, ctx->red, (size_t)K * kV * sizeof(double), s))) return rc;
-    double* part = (double*)ctx->tmp1.ptr;
-    double* epart = (double*)ctx->tmp2.ptr;
+    const size_t seg_n = (size_t)(K > 0 ? K : 1) * kSegStride;
+    double *seg64w, *el64w, *Uw, *part, *epart, *gx, *redw;
+    float *seg32w, *el32w;
+    if (carve) {
+        // every workspace from the caller's device memory, in the order vjp_f64_workspace_bytes counts
+        if (vjp_f64_workspace_bytes(K, M, N) > carve->bytes)
+            return set_error(ctx, BEM_EINVAL, "%zu bytes of workspace for K = %d, M = %d, N = %lld exceed the %zu "
+                             "available", vjp_f64_workspace_bytes(K, M, N), K, M, (long long)N, carve->bytes);
+        char* p = carve->base;
+        auto take = [&](size_t b) { char* q = p; p += carve_round(b); return q; };
+        seg64w = (double*)take(seg_n * sizeof(double));
+        seg32w = (float*)take(seg_n * sizeof(float));
+        el64w = (double*)take((size_t)M * kElemStride * sizeof(double));
+        el32w = (float*)take((size_t)M * kElemStride * sizeof(float));
+        Uw = (double*)take((size_t)M * 3 * sizeof(double));
+        part = (double*)take(seg_part * sizeof(double));
+        epart = (double*)take((el_rows * M * 3 + 2 * (size_t)M * 3) * sizeof(double));
+        gx = (double*)take((size_t)3 * M * 5 * sizeof(double));
+        redw = (double*)take((size_t)K * kV * sizeof(double));
+    } else {
+        // workspaces: tmp1 segment partials, tmp2 element partials + psi + mu, tmp3 Gauss points, red segment sums
+        if ((rc = ensure(ctx, ctx->seg64, seg_n * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->seg32, seg_n * sizeof(float), s))) return rc;
+        if ((rc = ensure(ctx, ctx->U, (size_t)M * 3 * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->elem64, (size_t)M * kElemStride * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->elem32, (size_t)M * kElemStride * sizeof(float), s))) return rc;
+        if ((rc = ensure(ctx, ctx->tmp1, seg_part * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->tmp2, (el_rows * M * 3 + 2 * (size_t)M * 3) * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->tmp3, (size_t)3 * M * 5 * sizeof(double), s))) return rc;
+        if ((rc = ensure(ctx, ctx->red, (size_t)K * kV * sizeof(double), s))) return rc;
+        seg64w = (double*)ctx->seg64.ptr;
+        seg32w = (float*)ctx->seg32.ptr;
+        Uw = (double*)ctx->U.ptr;
+        el64w = (double*)ctx->elem64.ptr;
+        el32w = (float*)ctx->elem32.ptr;
+        part = (double*)ctx->tmp1.ptr;
+        epart = (double*)ctx->tmp2.ptr;
+        gx = (double*)ctx->tmp3.ptr;
+        redw = (double*)ctx->red.ptr;
+    }
+    if ((rc = launch_expand_into(ctx, theta, H, seg64w, seg32w, s))) return rc;
+    if ((rc = launch_pack_elements_into(ctx, Uw, el64w, el32w, s))) return rc;   // element geometry only
     double* psi = epart + el_rows * M * 3;
     double* mu = psi + (size_t)M * 3;
-    double* gx = (double*)ctx->tmp3.ptr;
     double* gc = gx + (size_t)3 * M * 2;
-    const double* seg64 = (const double*)ctx->seg64.ptr;
-    const float* seg32 = (const float*)ctx->seg32.ptr;
-    const double* el64 = (const double*)ctx->elem64.ptr;
-    const float* el32 = (const float*)ctx->elem32.ptr;
+    const double* seg64 = seg64w;
+    const float* seg32 = seg32w;
+    const double* el64 = el64w;
+    const float* el32 = el32w;
     if (N > 0) {
         if (!mixed) {
             {
@@ -461,14 +514,72 @@ int run_vjp(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                                part + (size_t)ns * K * kV);
         }
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part,
-                           ns + ng + extra, (int64_t)K * kV, (double*)ctx->red.ptr);
+                           ns + ng + extra, (int64_t)K * kV, redw);
     } else {
         hipLaunchKernelGGL(k_reduce_parts, dim3(blocks_for((int64_t)K * kV, 256)), dim3(256), 0, s, part, 0,
-                           (int64_t)K * kV, (double*)ctx->red.ptr);
+                           (int64_t)K * kV, redw);
     }
-    hipLaunchKernelGGL(k_chain_theta, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)ctx->red.ptr, H, S,
+    hipLaunchKernelGGL(k_chain_theta, dim3(blocks_for(H, 64)), dim3(64), 0, s, (const double*)redw, H, S,
                        ctx->model, grad);
     return check_launch(ctx, "vjp");
 }
 
 }  // namespace bem
+
+// ---- allocation-free float64 adjoint ----------------------------------------------------------
+// Every workspace of bem_vjp_noalloc (segment and element tables, partial sums, psi, mu, boundary
+// Gauss points, segment sums) is carved from this array; each device that runs the library holds
+// its own copy for the life of the process.  Host code never passes the array's name to a kernel:
+// its device address, found once per device with hipGetSymbolAddress, is kept in g_scratch.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices] = {};
+
+// device address of this device's scratch array (the context's device is current)
+int scratch_address(bem_ctx* ctx, char** out)
+{
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= kScratchDevices)
+        return bem::set_error(ctx, BEM_EINVAL, "device %d beyond the %d the scratch table covers", dev, kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return bem::set_error(ctx, BEM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                                  hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = (char*)g_scratch[dev];
+    return BEM_OK;
+}
+}  // namespace
+
+extern "C" int bem_vjp_noalloc(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
+                               const double* gbar, double* grad, hipStream_t stream)
+{
+    using namespace bem;
+    int rc = check_common(ctx, theta, H, x, N);
+    if (rc) return rc;
+    if (N > 0 && !gbar) return set_error(ctx, BEM_EINVAL, "gbar is null");
+    if (H > 0 && !grad) return set_error(ctx, BEM_EINVAL, "grad is null");
+    const int K = H * ctx->opts.segs_per_handle;
+    const size_t need = vjp_f64_workspace_bytes(K, ctx->M, N);
+    if (need > kScratchBytes)
+        return set_error(ctx, BEM_EINVAL, "bem_vjp_noalloc: %zu bytes of workspace for K = %d segments, M = %d "
+                         "elements, N = %lld samples exceed its %zu-byte scratch", need, K, ctx->M, (long long)N,
+                         kScratchBytes);
+    char* base = nullptr;
+    if ((rc = scratch_address(ctx, &base))) return rc;
+    // no profiling events for this call (recording them may allocate)
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    const Carve carve{base, kScratchBytes};
+    rc = run_vjp(ctx, theta, H, x, N, gbar, false, grad, stream, nullptr, &carve);
+    ctx->prof.on = prof;
+    return rc;
+}
+
