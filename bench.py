@@ -156,8 +156,10 @@ def pmc_probe() -> int:
     return 0
 
 
-def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int) -> int:
-    """LM iterations of a workload with fresh samples per step; one JSON line per step."""
+def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int, ref: bool = False) -> int:
+    """LM iterations of a workload with fresh samples per step; one JSON line per step.  With ref,
+    each step's direction is also compared with the plain float64 step (float64 sweeps and Gram)
+    taken from the same parameters, damping and batch."""
     import numpy as np
     import torch
     from paper_2602_05492_amd import bem as B
@@ -180,12 +182,27 @@ def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int) -> in
         T = make_target(ctx, wl, tht, x, i)
         if i == 0:   # the start, with the mean colour the first step will use
             print(json.dumps({"step": 0, "rmse": rmse(T.mean(0).tolist())}), flush=True)
+        dir_err = None
+        if ref:
+            th64 = theta.clone()
+            st64 = B.new_lm_state(st.lam, 0, compat=compat)
+            st64.cbar_sum[:] = st.cbar_sum[:]
+            st64.cbar_count = st.cbar_count
+            ctx.lm_step(th64, x, T, st64, "fp64", "fp64")
+        th_before = theta.clone()
         t = time.perf_counter()
         ctx.lm_step(theta, x, T, st, gram, prec)
         torch.cuda.synchronize()
-        print(json.dumps({"step": i + 1, "loss_before": st.loss_before, "loss_after": st.loss_after,
-                          "accepted": int(st.accepted), "lambda": st.lam, "ms": (time.perf_counter() - t) * 1e3,
-                          "rmse": rmse(st.cbar)}), flush=True)
+        ms = (time.perf_counter() - t) * 1e3
+        if ref and st.accepted and st64.accepted:
+            d, d64 = (theta - th_before).flatten(), (th64 - th_before).flatten()
+            dir_err = float(torch.linalg.vector_norm(d - d64) / torch.linalg.vector_norm(d64))
+        rec = {"step": i + 1, "loss_before": st.loss_before, "loss_after": st.loss_after,
+               "accepted": int(st.accepted), "lambda": st.lam, "ms": ms, "rmse": rmse(st.cbar)}
+        if ref:
+            rec["fp64_accepted"] = int(st64.accepted)
+            rec["step_dir_rel_err_vs_fp64"] = dir_err
+        print(json.dumps(rec), flush=True)
     return 0
 
 
@@ -450,6 +467,9 @@ def main() -> int:
                          "handles, 100,000 samples (LM steps/s); near: mixed forward with near-singular samples, "
                          "1,048,576 samples (pairs/s); adjoint: bem_vjp at 4,194,304 samples (pairs/s)")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
+    ap.add_argument("--lm-curve-ref", action="store_true",
+                    help="with --lm-curve: also take the float64 step from the same state each step and report the "
+                         "step direction's relative error")
     ap.add_argument("--lm-curve", type=int, default=0,
                     help="instead of timing: run this many LM steps (fresh samples each) and print loss, lambda and "
                          "RMSE against the noise-free truth on the 512 x 512 pixel-centre grid per step")
@@ -457,7 +477,7 @@ def main() -> int:
     if args.pmc_probe:
         return pmc_probe()
     if args.lm_curve:
-        return lm_curve(args.lm_curve, args.gram, args.prec, args.workload, args.compat)
+        return lm_curve(args.lm_curve, args.gram, args.prec, args.workload, args.compat, args.lm_curve_ref)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the sample-sharded multi-GPU path is not built; "

@@ -341,41 +341,53 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
     bool take = false;
     if (valid) {
         const float Xf = (float)x[2 * t], Yf = (float)x[2 * t + 1];
+        // pv[c]: the b-end gradient of segment j - 1, carried to vertex j; each channel's a-end
+        // gradient is chained into geo as soon as it is formed, so that only one channel's
+        // end-point gradients are live at a time
         float pv[3][2];
         for (int c = 0; c < 3; ++c) pv[c][0] = pv[c][1] = 0.f;
-        for (int j = 0; j <= S; ++j) {
-            float va[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-            float vb[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
-            if (j < S) {
-                const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
-                const SegGeom<float> gf = load_geom(s32);
-                // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
-                if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
-                    const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-                    const Moments<float> m = pair_moments(gf, st);
-                    for (int c = 0; c < 3; ++c) {
-                        const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
-                                                              s32[kWcA + c], s32[kWcB + c]);
-                        va[c][0] = gr.ax; va[c][1] = gr.ay; vb[c][0] = gr.bx; vb[c][1] = gr.by;
-                    }
-                    const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
-                    const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
-                    col[0] += m.da * sa_ + m.db * sb_;
-                    col[1] += m.da * ta + m.db * tb;
-                    col[2] += m.sa * sa_ + m.sb * sb_;
-                    col[3] += m.sa * ta + m.sb * tb;
-                }
-            }
+        for (int j = 0; j < S; ++j) {
+            const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
+            const SegGeom<float> gf = load_geom(s32);
             const float* B = vtab + 8 * j;
-            for (int c = 0; c < 3; ++c) {
-                const float gx = va[c][0] + pv[c][0], gy = va[c][1] + pv[c][1];
-                for (int q = 0; q < 4; ++q) {
-                    geo[c][2 * q] += B[q] * gx;
-                    geo[c][2 * q + 1] += B[q] * gy;
+            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
+            if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
+                const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+                const Moments<float> m = pair_moments(gf, st);
+                for (int c = 0; c < 3; ++c) {
+                    const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
+                                                          s32[kWcA + c], s32[kWcB + c]);
+                    const float gx = gr.ax + pv[c][0], gy = gr.ay + pv[c][1];
+                    for (int q = 0; q < 4; ++q) {
+                        geo[c][2 * q] += B[q] * gx;
+                        geo[c][2 * q + 1] += B[q] * gy;
+                    }
+                    pv[c][0] = gr.bx;
+                    pv[c][1] = gr.by;
                 }
-                pv[c][0] = vb[c][0];
-                pv[c][1] = vb[c][1];
+                const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
+                const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
+                col[0] += m.da * sa_ + m.db * sb_;
+                col[1] += m.da * ta + m.db * tb;
+                col[2] += m.sa * sa_ + m.sb * sb_;
+                col[3] += m.sa * ta + m.sb * tb;
+            } else {
+                for (int c = 0; c < 3; ++c) {
+                    for (int q = 0; q < 4; ++q) {
+                        geo[c][2 * q] += B[q] * pv[c][0];
+                        geo[c][2 * q + 1] += B[q] * pv[c][1];
+                    }
+                    pv[c][0] = pv[c][1] = 0.f;
+                }
             }
+        }
+        {
+            const float* B = vtab + 8 * S;                  // the last vertex takes the carried b end
+            for (int c = 0; c < 3; ++c)
+                for (int q = 0; q < 4; ++q) {
+                    geo[c][2 * q] += B[q] * pv[c][0];
+                    geo[c][2 * q + 1] += B[q] * pv[c][1];
+                }
         }
         const int64_t i = t0 + t;
         take = !flag[i];
