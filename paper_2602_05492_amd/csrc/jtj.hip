@@ -717,16 +717,25 @@ __global__ void __launch_bounds__(256) k_scatter_jtj(const double* __restrict__ 
     }
 }
 
-// Jtr[col(a)] += s * (R[row(a)][c] + sum_i Zc[i][a] R[beta row i][c])
-__global__ void k_scatter_g(const double* __restrict__ R, const double* __restrict__ Zc, Layout L, int M, int c,
-                            double s, double* __restrict__ Jtr)
+// Jtr[col(a)] += s * (R[row(a)][c] + sum_i Zc[i][a] R[beta row i][c]): a block per 64 compact
+// indices a, its 4 wavefronts splitting the M beta rows (coalesced reads of Zc along a), the four
+// partial sums added in a fixed order through LDS.
+__global__ void __launch_bounds__(256) k_scatter_g(const double* __restrict__ R, const double* __restrict__ Zc,
+                                                   Layout L, int M, int c, double s, double* __restrict__ Jtr)
 {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int a = blockIdx.x * 64 + lane;
     const int n = L.compact();
-    if (a >= n) return;
-    double v = R[(size_t)L.row(a, c) * 3 + c];
-    for (int i = 0; i < M; ++i) v += Zc[(size_t)i * n + a] * R[((size_t)L.handle_rows() + i) * 3 + c];
-    Jtr[param_col(a, L, c)] += s * v;
+    const int64_t rb = L.handle_rows();
+    double v = 0.0;
+    if (a < n)
+        for (int i = wave; i < M; i += 4) v += Zc[(size_t)i * n + a] * R[(rb + i) * 3 + c];
+    part[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && a < n)
+        Jtr[param_col(a, L, c)] += s * (R[(size_t)L.row(a, c) * 3 + c] + ((part[0][lane] + part[1][lane]) +
+                                                                            (part[2][lane] + part[3][lane])));
 }
 
 // J[n][c][p] assembly for the explicit Jacobian: features + beta . Z
@@ -1166,7 +1175,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             return rc;
         if ((rc = gemm_f64(ctx, n12, n12, M, 1.0, Gc + n12, Wc, false, Zc, n12, false, 0.0, S1, n12, s, nullptr, 0))) return rc;
         if (want_r) {
-            hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 256)), dim3(256), 0, s, R, Zc, L, M, c, sc, Jtr);
+            hipLaunchKernelGGL(k_scatter_g, dim3(blocks_for(n12, 64)), dim3(256), 0, s, R, Zc, L, M, c, sc, Jtr);
             if ((rc = check_launch(ctx, "scatter"))) return rc;
         }
     }

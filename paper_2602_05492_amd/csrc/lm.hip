@@ -413,11 +413,15 @@ int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, 
     st->loss_after = L0;
     if (!std::isfinite(L0)) return set_error(ctx, BEM_ENUMERIC, "non-finite loss at the current parameters");
     if (H == 0 || N == 0) return BEM_OK;
-    // gradient g = (1/m) J^T r and Hessian H = (1/m) J^T J.  Mixed precision with an MFMA Gram: g is
-    // contracted from the same feature tiles as H (J^T r of each tile, read once more beside its
-    // Gram), so no separate adjoint sweep runs.  Otherwise g comes from the adjoint (bem_vjp's
-    // kernels) and the normal equations form J^T J only.
-    const bool g_from_tiles = mixed && (gram == BEM_GRAM_FP32_MFMA || gram == BEM_GRAM_BF16X3_MFMA);
+    // gradient g = (1/m) J^T r and Hessian H = (1/m) J^T J.  Mixed precision with an MFMA Gram and
+    // handles of several segments: g is formed with the J tiles (the handle rows' J^T r summed in the
+    // feature kernel, the beta rows' read back from the tile), so no separate adjoint sweep runs
+    // (LM workload, S = 32: 512 -> 445 ms per step, A/B on one box).  With one segment per handle
+    // the in-kernel sums cost more than the adjoint (paper-native workload: 26.5 -> 26.0 ms with
+    // the adjoint), so there, and otherwise, g comes from the adjoint (bem_vjp's kernels) and the
+    // normal equations form J^T J only.
+    const bool g_from_tiles = mixed && (gram == BEM_GRAM_FP32_MFMA || gram == BEM_GRAM_BF16X3_MFMA) &&
+                              ctx->opts.segs_per_handle >= 2;
     if (g_from_tiles) {
         if ((rc = run_jtj(ctx, theta, H, x, N, r, mixed, gram, JtJ, g, s, &nl, nd))) return rc;
     } else {
