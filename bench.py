@@ -32,13 +32,11 @@ sys.path.insert(0, ROOT)
 METRIC = "sample×segment pairs/s and LM steps/s, FP32-mixed vs FP64 at 1e-4 color err"
 PEAKS = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12,
          "bf16_mfma": 2.5e15}
-# HBM byte counters of the split-BF16 Gram kernel, taken with rocprofv3 --pmc on the
-# --pmc-probe run (two sample tiles of the LM workload plus a 256 MiB copy for calibration)
-PMC_FILE = os.path.join(ROOT, "profiles", "gram_bf16x3_lm_workload_pmc.json")
+# Counters of the hot kernels (rocprofv3 --pmc passes over `bench.py --pmc-probe`: two 32,768-sample
+# tiles of the LM workload, kernels serialised), each with the SHA-256 of the sources it was taken from
+PMC_FILE = os.path.join(ROOT, "profiles", "lm_workload_counters.json")
 CSRC = os.path.join(ROOT, "paper_2602_05492_amd", "csrc")
 GRAM_TILE = 32768          # samples per split-BF16 Gram launch (the library's default tile)
-GRAM_SOURCES = ["gram_mfma.hip"]
-SWEEP_SOURCES = ["sweep_mixed.hip", "sweep_common.hpp", "seg_math.hpp"]
 
 
 def sources_sha(names) -> str:
@@ -112,24 +110,53 @@ def gram_entries(H: int, M: int, model: str = "cubic") -> int:
     return 3 * (g * (g + 1) // 2) + 3 * g * s + s * (s + 1) // 2
 
 
+def counters(kernel: str):
+    """The committed counter record of a kernel, or None when there is none or its sources have
+    changed since it was taken."""
+    rec = pmc_record()
+    k = rec.get("kernels", {}).get(kernel) if rec else None
+    if not k or k.get("source_sha256") != sources_sha(k.get("source_files", [])):
+        return None
+    return k
+
+
+def gram_alg_bytes(H: int, M: int, model: str) -> float:
+    """Algorithmic HBM bytes of one split-BF16 Gram launch: the feature tile read once (hi and lo
+    planes, W rows x the tile's samples) and the partial-Gram tiles of its work list read and
+    written once (8-byte entries, 3 parts)."""
+    fg, fc = FEATURE_ROWS[model]
+    W = 3 * (-(-fg * H // 256) * 256) + fc * H + M
+    return W * GRAM_TILE * 4.0 + 2 * 3 * gram_tile_pairs(H, M, model) * 256 * 256 * 8.0
+
+
 def gram_traffic(samples_per_launch: int):
-    """HBM bytes per Gram launch from the committed counter run, or None when there is none
-    or the kernel source has changed since it was taken."""
-    rec = pmc_record()
-    g = rec.get("gram") if rec else None
-    if not g or g.get("source_sha256") != sources_sha(GRAM_SOURCES) or g.get("samples_per_dispatch") != samples_per_launch:
+    """HBM bytes per Gram launch from the committed counter run (FETCH_SIZE and WRITE_SIZE scaled by
+    what they read for a plain copy), or None."""
+    g = counters("k_gram_bf16x3_lds")
+    if not g or samples_per_launch != GRAM_TILE:
         return None
-    return 1024.0 * (g["fetch_kib_per_dispatch"] * rec["fetch_scale"] + g["write_kib_per_dispatch"] * rec["write_scale"])
+    return g["hbm_bytes"]
 
 
-def sweep_flops_per_pair():
-    """float32 flops per sample x segment pair of the mixed forward sweep (VALU FLOPS counters of
-    the committed counter run), or None when the sweep source has changed since."""
-    rec = pmc_record()
-    sw = rec.get("sweep") if rec else None
-    if not sw or sw.get("source_sha256") != sources_sha(SWEEP_SOURCES):
+def valu_fraction(kernel: str, pairs_per_s_in_step):
+    """float32 VALU rate of a sweep-type kernel: the counter flops per pair (FMA = 2) times its pair
+    rate, in the timed step (shared with other kernels) and alone (the counter run), against the
+    float32 vector peak (packed) and the non-packed FMA ceiling (half of it)."""
+    k = counters(kernel)
+    if not k or "fp32_flops_per_pair" not in k:
         return None
-    return sw["fp32_flops_per_pair"]
+    fpp = k["fp32_flops_per_pair"]
+    out = {"kernel": kernel, "fp32_flops_per_pair": fpp, "valu_insts_per_pair": k["valu_insts_per_pair"],
+           "vgpr": k["vgpr"], "scratch_bytes_per_lane": k["scratch_bytes_per_lane"],
+           "alone": {"pairs_per_s": k["pairs_per_s_alone"], "tflops": k["tflops_alone"],
+                     "frac": k["tflops_alone"] / (PEAKS["fp32_vector"] / 1e12),
+                     "frac_of_unpacked_peak": k["tflops_alone"] / (PEAKS["fp32_vector"] / 2e12),
+                     "clock_ghz": k["clock_ghz"]}}
+    if pairs_per_s_in_step:
+        tf = fpp * pairs_per_s_in_step / 1e12
+        out["in_step"] = {"pairs_per_s": pairs_per_s_in_step, "tflops": tf, "frac": tf / (PEAKS["fp32_vector"] / 1e12),
+                          "frac_of_unpacked_peak": tf / (PEAKS["fp32_vector"] / 2e12)}
+    return out
 
 
 def pmc_probe() -> int:
@@ -402,6 +429,8 @@ def adjoint_mode(steps: int, warmup: int, do_cpu: bool) -> int:
     ms64 = (time.perf_counter() - t0) * 1e3
     rel = float((gm - gd).abs().max() / gd.abs().max())
     pairs = N * (K + M)
+    seg_ms = prof["vjp_segments"][0] / steps if prof["vjp_segments"][1] else None
+    vjp_valu = valu_fraction("k_vjp_segments", N * K / (seg_ms * 1e-3) if seg_ms else None)
     out = {"metric": "sample x segment pairs/s (mixed adjoint, bem_vjp)", "value": pairs / (ms * 1e-3),
            "unit": "pairs/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -409,7 +438,7 @@ def adjoint_mode(steps: int, warmup: int, do_cpu: bool) -> int:
                       "params": wl.P, "outer_elements": M},
            "handle_pairs_per_s": N * K / (ms * 1e-3), "fp64_gpu_ms": ms64, "fp64_pairs_per_s": pairs / (ms64 * 1e-3),
            "speedup_vs_fp64_gpu": ms64 / ms,
-           "grad_rel_err_vs_fp64": {"max_abs_over_max": rel, "bar": 1e-3},
+           "grad_rel_err_vs_fp64": {"max_abs_over_max": rel, "bar": 1e-3}, "vjp_valu": vjp_valu,
            "kernel_ms_per_vjp": {k: v[0] / steps for k, v in prof.items() if v[1] > 0},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
@@ -562,36 +591,30 @@ def main() -> int:
         # context from the same counter run: the clock under the Gram launch alone (GRBM_GUI_ACTIVE
         # per XCD over its duration) and the MFMA work it issues (3 products per entry) against
         # the dense bf16 peak at that clock
-        g = pmc_record()["gram"]
-        if g.get("clock_ghz"):
-            issued = gram_tile_pairs(H, M, wl.spec.model) * 256 * 256 * 2.0 * GRAM_TILE * 3
-            roofline["alone"] = {"ms": g["duration_ms_in_counter_run"], "clock_ghz": g["clock_ghz"],
-                                 "mfma_issued_pflops": issued / (g["duration_ms_in_counter_run"] * 1e-3) / 1e15,
-                                 "frac_of_peak_at_clock": issued / (g["duration_ms_in_counter_run"] * 1e-3)
-                                 / (2.5e15 * g["clock_ghz"] / 2.4)}
+        g = counters("k_gram_bf16x3_lds")
+        issued = gram_tile_pairs(H, M, wl.spec.model) * 256 * 256 * 2.0 * GRAM_TILE * 3
+        roofline["alone"] = {"ms": g["duration_ms"], "clock_ghz": g["clock_ghz"],
+                             "mfma_issued_pflops": issued / (g["duration_ms"] * 1e-3) / 1e15,
+                             "frac_of_peak_at_clock": issued / (g["duration_ms"] * 1e-3) / (2.5e15 * g["clock_ghz"] / 2.4),
+                             "algorithmic_bytes": (gram_alg_bytes(H, M, wl.spec.model)
+                                                   if wl.spec.model == "cubic" else None)}
     fwd_ms = prof["sweep_mixed" if args.prec == "mixed" else "sweep_f64"]
     pairs_fwd = (N * (K + M)) / (fwd_ms[0] / fwd_ms[1] * 1e-3) if fwd_ms[1] else None
     vjp_ms = prof["vjp_segments"][0] + prof["vjp_elements"][0]
     pairs_vjp = steps * (N * (K + M)) / (vjp_ms * 1e-3) if vjp_ms > 0 else None
+    feat_ms = prof["features"][0]
+    pairs_feat = steps * N * K / (feat_ms * 1e-3) if feat_ms > 0 else None
 
-    # forward sweep against the float32 vector peak (packed FP32 counts twice; without it the
-    # vector ceiling is half of that)
-    fpp = sweep_flops_per_pair() if (args.prec == "mixed" and args.workload == "lm") else None
-    sweep_valu = None
-    if fpp and pairs_fwd:
-        tf = fpp * pairs_fwd / 1e12
-        sw = pmc_record()["sweep"]
+    # the VALU kernels against the float32 vector peak (packed FP32 counts twice; without it the
+    # vector ceiling is half of that), from the committed counters of the LM workload
+    lm_mixed = args.prec == "mixed" and args.workload == "lm"
+    sweep_valu = valu_fraction("k_sweep_far", pairs_fwd) if lm_mixed else None
+    if sweep_valu:
+        sw = counters("k_sweep_far")
         samples_per_s = pairs_fwd / (K + M)
-        bytes_per_sample = (sw["fetch_kib"] * pmc_record()["fetch_scale"] + sw["write_kib"] * pmc_record()["write_scale"]) \
-            * 1024.0 / sw["samples"]
-        trans = sw["trans_per_pair"] * pairs_fwd / 1e12
-        sweep_valu = {"kernel": "sweep_mixed", "pairs_per_s": pairs_fwd, "fp32_flops_per_pair": fpp, "achieved": tf,
-                      "unit": "TFLOP/s", "peak": PEAKS["fp32_vector"] / 1e12, "frac": tf / (PEAKS["fp32_vector"] / 1e12),
-                      "frac_of_unpacked_peak": tf / (PEAKS["fp32_vector"] / 2e12),
-                      # transcendental (quarter-rate) ops: 16 lanes per CU per clock = 157.3 / 16 T/s
-                      "transcendental_tops": trans, "transcendental_frac": trans / (PEAKS["fp32_vector"] / 16e12),
-                      "hbm_bytes_per_sample": bytes_per_sample,
-                      "hbm_gbps": bytes_per_sample * samples_per_s / 1e9, "hbm_frac": bytes_per_sample * samples_per_s / 8e12}
+        sweep_valu["transcendental_frac"] = sw["trans_per_pair"] * pairs_fwd / (PEAKS["fp32_vector"] / 16)
+        sweep_valu["hbm_gbps"] = sw["hbm_bytes"] / 65536 * samples_per_s / 1e9
+    features_valu = valu_fraction("k_features_far", pairs_feat) if lm_mixed else None
 
     # colour error of the mixed forward against the float64 path at the start parameters, over
     # every sample of the first batch (the metric's "at 1e-4 color err")
@@ -654,7 +677,7 @@ def main() -> int:
         "fp64_gpu": fp64, "speedup_vs_fp64_gpu": speedup,
         "step_direction_rel_err_vs_fp64": step_err,
         "kernel_ms_per_step": {k: v[0] / steps for k, v in timed.items()},
-        "sweep_valu": sweep_valu, "roofline": roofline, "cpu_baseline": cpu,
+        "sweep_valu": sweep_valu, "features_valu": features_valu, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
