@@ -179,27 +179,30 @@ __host__ __device__ inline int64_t jtr_row(int model, int v, int h, int64_t gp, 
     return 3 * gp + 4 * h + m;
 }
 
-// R[row][c] += sum over the tile's blocks of rpart[block][h][v] (float64, fixed order): thread per
-// (h, v) pair.  For straight handles the two products that share a row are added by the thread of
-// the first (m even) of them.
+// R[row][c] += sum over the tile's blocks of rpart[block][h][v] (float64, fixed order): a block per
+// handle h, lane v of each wavefront a product, the 4 wavefronts splitting the blocks (b = w mod 4)
+// and adding their partial sums in a fixed order through LDS.  For straight handles the two
+// products that share a row are added by the lane of the first (m even) of them.
 __global__ void __launch_bounds__(256) k_jtr_handles(const float* __restrict__ rpart, int nblocks, int H, int model,
                                                      int64_t gp, double* __restrict__ R)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= H * kJtrVals) return;
-    const int h = i / kJtrVals, v = i % kJtrVals;
+    __shared__ double part[4][kJtrVals];
+    const int h = blockIdx.x;
+    const int v = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc = 0.0;
+    if (v < kJtrVals)
+        for (int b = wave; b < nblocks; b += 4) acc += (double)rpart[((size_t)b * H + h) * kJtrVals + v];
+    if (v < kJtrVals) part[wave][v] = acc;
+    __syncthreads();
+    if (wave != 0 || v >= kJtrVals) return;
     int c;
     const int64_t row = jtr_row(model, v, h, gp, &c);
     if (row < 0) return;
     const bool pair = model == 1 && v >= 24 && (((v - 24) / 3) & 1) == 0;   // m even: also take m + 1
     if (model == 1 && v >= 24 && !pair) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        const float* pb = rpart + ((size_t)b * H + h) * kJtrVals;
-        acc += (double)pb[v];
-        if (pair) acc += (double)pb[v + 3];
-    }
-    R[row * 3 + c] += acc;
+    double tot = (part[0][v] + part[1][v]) + (part[2][v] + part[3][v]);
+    if (pair) tot += (part[0][v + 3] + part[1][v + 3]) + (part[2][v + 3] + part[3][v + 3]);
+    R[row * 3 + c] += tot;
 }
 
 // J^T r of one flagged sample's handle rows (the inline kernel): float64 atomics into R.
@@ -823,8 +826,8 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
                                H, S, model, gp, (float)eps2, near2, nl->list, nl->slots, (const int2*)runs, nl->flag, corr,
                                vtab, Xt, Xlo, ld, rr, rpart);
             if (rr)
-                hipLaunchKernelGGL(k_jtr_handles, dim3(blocks_for((int64_t)H * kJtrVals, 256)), dim3(256), 0, s,
-                                   (const float*)rpart, (int)grid.x, H, model, gp, R);
+                hipLaunchKernelGGL(k_jtr_handles, dim3(H), dim3(256), 0, s, (const float*)rpart, (int)grid.x, H, model,
+                                   gp, R);
             const int fb = blocks_for(npts, 256) < 16 ? blocks_for(npts, 256) : 16;
             if (nl->overflowed)
                 hipLaunchKernelGGL((k_features<true, OutT>), dim3(fb, H), dim3(256), 0, s, x, npts, (const double*)ctx->seg64.ptr,
