@@ -147,7 +147,7 @@ def valu_fraction(kernel: str, pairs_per_s_in_step):
         return None
     fpp = k["fp32_flops_per_pair"]
     out = {"kernel": kernel, "fp32_flops_per_pair": fpp, "valu_insts_per_pair": k["valu_insts_per_pair"],
-           "vgpr": k["vgpr"], "scratch_bytes_per_lane": k["scratch_bytes_per_lane"],
+           "compiler": k.get("compiler"),
            "alone": {"pairs_per_s": k["pairs_per_s_alone"], "tflops": k["tflops_alone"],
                      "frac": k["tflops_alone"] / (PEAKS["fp32_vector"] / 1e12),
                      "frac_of_unpacked_peak": k["tflops_alone"] / (PEAKS["fp32_vector"] / 2e12),

@@ -1,6 +1,6 @@
 // gemm.hip - float64 dense products used around the normal equations:
 //   C = alpha op(A) op(B) + beta C   (row-major, op = identity or transpose)
-// k_gemm_f64_mfma: 128 x 128 output tiles on float64 MFMA (v_mfma_f64_16x16x4f64), 16-deep
+// k_gemm_f64_mfma: 128 x 128 (or 64 x 64) output tiles on float64 MFMA (v_mfma_f64_16x16x4f64), 16-deep
 //   k slabs staged through LDS (double buffered, the next slab prefetched into registers while
 //   the current one is multiplied); also the float64 Gram restricted to a list of output tiles.
 // k_gemm_skinny: products with at most 4 columns (J^T r of the float64 Gram path): a wavefront
@@ -87,16 +87,16 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int k, double al
 // is row 4 q + l / 16, column l mod 16 of the 16 x 16 tile.  Both operand slabs are stored in LDS
 // k-major ([k][row] and [k][col]) so that each operand is one ds_read_b64 per lane.
 typedef double d4_t __attribute__((ext_vector_type(4)));
-constexpr int kMB = 128, kMK = 16, kMLd = kMB + 4;        // LDS row stride (doubles)
-constexpr int kMLoads = kMB * kMK / 256;                  // slab elements per thread and operand
+constexpr int kMB = 128, kMK = 16;
 
-// element e of a kMB x kMK slab of op(X) starting at (r0, k0): its slab coordinates and value
+// element e of a BM x kMK slab of op(X) starting at (r0, k0): its slab coordinates and value
 // (0 outside the m x k operand).  Non-transposed X is row-major [row][k] (16 consecutive
 // threads read one row's 16 k values); transposed X is stored [k][row].
+template <int BM>
 __device__ inline double slab_load(const double* __restrict__ X, int64_t ldx, int tx, int r0, int k0, int rows, int kd,
                                    int e, int& sr, int& sk)
 {
-    if (tx) { sk = e / kMB; sr = e % kMB; }
+    if (tx) { sk = e / BM; sr = e % BM; }
     else { sr = e / kMK; sk = e % kMK; }
     const int gr = r0 + sr, gk = k0 + sk;
     const bool in = gr < rows && gk < kd;
@@ -105,13 +105,20 @@ __device__ inline double slab_load(const double* __restrict__ X, int64_t ldx, in
     return in ? v : 0.0;
 }
 
-__global__ void __launch_bounds__(256, 2) k_gemm_f64_mfma(int m, int n, int k, double alpha, const double* __restrict__ A,
-                                                       int64_t lda, int ta, const double* __restrict__ B, int64_t ldb,
-                                                       int tb, double beta, double* __restrict__ C, int64_t ldc,
-                                                       const int* __restrict__ tiles)
+// BM x BM output tile per block (BM = 128: each wavefront 64 x 64 as 4 x 4 MFMA tiles; BM = 64:
+// 32 x 32 as 2 x 2, for products whose 128-tile grid would leave most CUs idle).
+template <int BM>
+__global__ void __launch_bounds__(256, BM == 128 ? 2 : 4) k_gemm_f64_mfma(int m, int n, int k, double alpha,
+                                                                        const double* __restrict__ A, int64_t lda, int ta,
+                                                                        const double* __restrict__ B, int64_t ldb, int tb,
+                                                                        double beta, double* __restrict__ C, int64_t ldc,
+                                                                        const int* __restrict__ tiles)
 {
-    __shared__ double As[2][kMK][kMLd];
-    __shared__ double Bs[2][kMK][kMLd];
+    constexpr int LD = BM + 4;                  // LDS row stride (doubles)
+    constexpr int NL = BM * kMK / 256;          // slab elements per thread and operand
+    constexpr int TI = BM / 32;                 // 16 x 16 MFMA tiles per wavefront and dimension
+    __shared__ double As[2][kMK][LD];
+    __shared__ double Bs[2][kMK][LD];
     int bm, bn;
     if (tiles) {
         bm = tiles[2 * blockIdx.x];
@@ -120,57 +127,57 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64_mfma(int m, int n, int k, d
         bm = blockIdx.y;
         bn = blockIdx.x;
     }
-    const int row0 = bm * kMB, col0 = bn * kMB;
+    const int row0 = bm * BM, col0 = bn * BM;
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
     // B as a (k x n) operand: op(B) row-major [k][col] unless transposed ([col][k]); slab_load takes
     // the "row" index as the column of op(B), so its transposition flag is the opposite one
     const int tbB = tb ? 0 : 1;
-    double pa[kMLoads], pb[kMLoads];
-    int ar[kMLoads], ak[kMLoads], br[kMLoads], bk[kMLoads];
+    double pa[NL], pb[NL];
+    int ar[NL], ak[NL], br[NL], bk[NL];
 #pragma unroll
-    for (int i = 0; i < kMLoads; ++i) {
-        pa[i] = slab_load(A, lda, ta, row0, 0, m, k, tid + 256 * i, ar[i], ak[i]);
-        pb[i] = slab_load(B, ldb, tbB, col0, 0, n, k, tid + 256 * i, br[i], bk[i]);
+    for (int i = 0; i < NL; ++i) {
+        pa[i] = slab_load<BM>(A, lda, ta, row0, 0, m, k, tid + 256 * i, ar[i], ak[i]);
+        pb[i] = slab_load<BM>(B, ldb, tbB, col0, 0, n, k, tid + 256 * i, br[i], bk[i]);
     }
 #pragma unroll
-    for (int i = 0; i < kMLoads; ++i) {
+    for (int i = 0; i < NL; ++i) {
         As[0][ak[i]][ar[i]] = pa[i];
         Bs[0][bk[i]][br[i]] = pb[i];
     }
     __syncthreads();
-    d4_t acc[4][4];
+    d4_t acc[TI][TI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TI; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
     const int nk = (k + kMK - 1) / kMK;
     for (int s = 0; s < nk; ++s) {
         const int cur = s & 1;
         const bool more = s + 1 < nk;
         if (more) {
 #pragma unroll
-            for (int i = 0; i < kMLoads; ++i) {
-                pa[i] = slab_load(A, lda, ta, row0, (s + 1) * kMK, m, k, tid + 256 * i, ar[i], ak[i]);
-                pb[i] = slab_load(B, ldb, tbB, col0, (s + 1) * kMK, n, k, tid + 256 * i, br[i], bk[i]);
+            for (int i = 0; i < NL; ++i) {
+                pa[i] = slab_load<BM>(A, lda, ta, row0, (s + 1) * kMK, m, k, tid + 256 * i, ar[i], ak[i]);
+                pb[i] = slab_load<BM>(B, ldb, tbB, col0, (s + 1) * kMK, n, k, tid + 256 * i, br[i], bk[i]);
             }
         }
 #pragma unroll
         for (int ks = 0; ks < kMK; ks += 4) {
             const int kk = ks + (l >> 4), rr = l & 15;
-            double a[4], b[4];
+            double a[TI], b[TI];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[cur][kk][64 * wr + 16 * i + rr];
+            for (int i = 0; i < TI; ++i) a[i] = As[cur][kk][(BM / 2) * wr + 16 * i + rr];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kk][64 * wc + 16 * j + rr];
+            for (int j = 0; j < TI; ++j) b[j] = Bs[cur][kk][(BM / 2) * wc + 16 * j + rr];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < TI; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more) {
 #pragma unroll
-            for (int i = 0; i < kMLoads; ++i) {
+            for (int i = 0; i < NL; ++i) {
                 As[cur ^ 1][ak[i]][ar[i]] = pa[i];
                 Bs[cur ^ 1][bk[i]][br[i]] = pb[i];
             }
@@ -178,13 +185,13 @@ __global__ void __launch_bounds__(256, 2) k_gemm_f64_mfma(int m, int n, int k, d
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < TI; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = row0 + 64 * wr + 16 * i + 4 * q + (l >> 4);
-                const int c = col0 + 64 * wc + 16 * j + (l & 15);
+                const int r = row0 + (BM / 2) * wr + 16 * i + 4 * q + (l >> 4);
+                const int c = col0 + (BM / 2) * wc + 16 * j + (l & 15);
                 if (r < m && c < n) {
                     double* o = C + (size_t)r * ldc + c;
                     *o = alpha * acc[i][j][q] + (beta == 0.0 ? 0.0 : beta * *o);
@@ -236,8 +243,8 @@ int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, i
             hipLaunchKernelGGL(k_gemm_f64, dim3(ntiles), dim3(256), 0, s, m, n, k, alpha, A, lda, ta ? 1 : 0, B, ldb,
                                tb ? 1 : 0, beta, C, ldc, tiles);
         else
-            hipLaunchKernelGGL(k_gemm_f64_mfma, dim3(ntiles), dim3(256), 0, s, m, n, k, alpha, A, lda, ta ? 1 : 0, B,
-                               ldb, tb ? 1 : 0, beta, C, ldc, tiles);
+            hipLaunchKernelGGL(k_gemm_f64_mfma<kMB>, dim3(ntiles), dim3(256), 0, s, m, n, k, alpha, A, lda, ta ? 1 : 0,
+                               B, ldb, tb ? 1 : 0, beta, C, ldc, tiles);
         return check_launch(ctx, "gemm_f64");
     }
     if (valu) {
@@ -246,8 +253,12 @@ int gemm_f64(bem_ctx* ctx, int m, int n, int k, double alpha, const double* A, i
     } else if (n <= kSkinnyMaxN && !ta) {
         hipLaunchKernelGGL(k_gemm_skinny, dim3(blocks_for(m, 4)), dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb,
                            tb ? 1 : 0, beta, C, ldc);
+    } else if ((int64_t)blocks_for(n, kMB) * blocks_for(m, kMB) >= 1024) {
+        hipLaunchKernelGGL(k_gemm_f64_mfma<kMB>, dim3(blocks_for(n, kMB), blocks_for(m, kMB)), dim3(256), 0, s, m, n, k,
+                           alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, C, ldc, (const int*)nullptr);
     } else {
-        hipLaunchKernelGGL(k_gemm_f64_mfma, dim3(blocks_for(n, kMB), blocks_for(m, kMB)), dim3(256), 0, s, m, n, k,
+        // fewer than two rounds of 128-tiles over the CUs: 64-tiles, 4x the blocks
+        hipLaunchKernelGGL(k_gemm_f64_mfma<64>, dim3(blocks_for(n, 64), blocks_for(m, 64)), dim3(256), 0, s, m, n, k,
                            alpha, A, lda, ta ? 1 : 0, B, ldb, tb ? 1 : 0, beta, C, ldc, (const int*)nullptr);
     }
     return check_launch(ctx, "gemm_f64");
