@@ -79,8 +79,10 @@ F_BOUNDARY_PAIR = 40.0     # forward / adjoint: one sample x one outer element
 F_GRAD_PAIR = 300.0        # adjoint or J-tile: one sample x one handle segment
 
 
-WORKLOADS = {"lm": 5, "paper": 6}
+WORKLOADS = {"lm": 5, "paper": 6, "medium": 2}
 WORKLOAD_TEXT = {
+    "medium": "medium: 32 crossing cubic handles x 16 segments (P = 640), 262,144 uniform samples per step, "
+              "sigma 0.2, eps 1e-2, 1,024 outer elements",
     "lm": "LM normal equations: 256 cubic handles x 32 segments (P = 5,120), 2,097,152 uniform samples per step, "
           "sigma 0.2, eps 1e-2, 1,024 outer elements",
     "paper": "paper-native: 500 straight handles x 1 segment (P = 5,000; Sobol placement, length 1/20), 100,000 "
@@ -494,7 +496,8 @@ def main() -> int:
                     help="enforce the compatibility condition in every LM step (constrained step + re-projection)")
     ap.add_argument("--workload", default="lm", choices=sorted(WORKLOADS) + ["near", "adjoint"],
                     help="lm: 256 cubic handles x 32 segments, 2,097,152 samples (LM steps/s); paper: 500 straight "
-                         "handles, 100,000 samples (LM steps/s); near: mixed forward with near-singular samples, "
+                         "handles, 100,000 samples (LM steps/s); medium: 32 crossing cubic handles x 16 segments, "
+                         "262,144 samples (LM steps/s; --prec fp64 --gram fp64 for the plain FP64 path); near: mixed forward with near-singular samples, "
                          "1,048,576 samples (pairs/s); adjoint: bem_vjp at 4,194,304 samples (pairs/s)")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
     ap.add_argument("--lm-curve-ref", action="store_true",

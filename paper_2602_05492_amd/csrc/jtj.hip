@@ -353,35 +353,37 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
             const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
             const SegGeom<float> gf = load_geom(s32);
             const float* B = vtab + 8 * j;
-            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near
-            if (gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2)) {
-                const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-                const Moments<float> m = pair_moments(gf, st);
-                for (int c = 0; c < 3; ++c) {
-                    const Grad4<float> gr = pair_backward(gf, st, eps2f, s32[kWdA + c], s32[kWdB + c],
-                                                          s32[kWcA + c], s32[kWcB + c]);
-                    const float gx = gr.ax + pv[c][0], gy = gr.ay + pv[c][1];
-                    for (int q = 0; q < 4; ++q) {
-                        geo[c][2 * q] += B[q] * gx;
-                        geo[c][2 * q + 1] += B[q] * gy;
-                    }
-                    pv[c][0] = gr.bx;
-                    pv[c][1] = gr.by;
+            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near.
+            // Every lane evaluates the pair (its values may be non-finite where the pair is near or
+            // the segment degenerate) and then keeps them only where it is far: every pair takes the
+            // same path, with no branch-local copies of the loop-carried sums
+            const bool far = gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2);
+            const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+            Moments<float> m = pair_moments(gf, st);
+            // the end-point gradient is linear in the channel's end densities: one matrix per pair
+            // serves the three channels
+            GradMatrix<float> G = pair_grad_matrix(gf, st, eps2f);
+            m.da = far ? m.da : 0.f;
+            m.db = far ? m.db : 0.f;
+            m.sa = far ? m.sa : 0.f;
+            m.sb = far ? m.sb : 0.f;
+            for (int r = 0; r < 4; ++r)
+                for (int k = 0; k < 4; ++k) G.g[r][k] = far ? G.g[r][k] : 0.f;
+            const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
+            const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
+            col[0] += m.da * sa_ + m.db * sb_;
+            col[1] += m.da * ta + m.db * tb;
+            col[2] += m.sa * sa_ + m.sb * sb_;
+            col[3] += m.sa * ta + m.sb * tb;
+            for (int c = 0; c < 3; ++c) {
+                const Grad4<float> gr = grad_apply(G, s32[kWdA + c], s32[kWdB + c], s32[kWcA + c], s32[kWcB + c]);
+                const float gx = gr.ax + pv[c][0], gy = gr.ay + pv[c][1];
+                for (int q = 0; q < 4; ++q) {
+                    geo[c][2 * q] += B[q] * gx;
+                    geo[c][2 * q + 1] += B[q] * gy;
                 }
-                const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
-                const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
-                col[0] += m.da * sa_ + m.db * sb_;
-                col[1] += m.da * ta + m.db * tb;
-                col[2] += m.sa * sa_ + m.sb * sb_;
-                col[3] += m.sa * ta + m.sb * tb;
-            } else {
-                for (int c = 0; c < 3; ++c) {
-                    for (int q = 0; q < 4; ++q) {
-                        geo[c][2 * q] += B[q] * pv[c][0];
-                        geo[c][2 * q + 1] += B[q] * pv[c][1];
-                    }
-                    pv[c][0] = pv[c][1] = 0.f;
-                }
+                pv[c][0] = gr.bx;
+                pv[c][1] = gr.by;
             }
         }
         {

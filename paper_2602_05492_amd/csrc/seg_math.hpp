@@ -223,6 +223,105 @@ BEM_HD inline Grad4<T> pair_backward(const SegGeom<T>& g, const PairState<T>& p,
     return r;
 }
 
+// The reverse pass above is linear in the cotangents.  Where one pair takes several
+// cotangent sets (the three colour channels of a Jacobian row share the pair but not the
+// end densities), the 4 x 4 matrix of that linear map is formed once and each set costs
+// 16 multiply-adds.  Its columns are taken in the basis (wa, wb - wa, sa, sa - sb), a
+// constant and a linearly varying density per layer, so that nearly equal end densities
+// cancel before the products rather than after them:
+//     grad = G (wa, wb - wa, sa, sa - sb),   rows ax, ay, bx, by.
+// Each column is pair_backward's chain evaluated for that unit cotangent with the terms that
+// vanish for it dropped (L2 iL2 = 1 used where it cancels a factor).
+template <class T>
+struct GradMatrix {
+    T g[4][4];
+};
+
+template <class T>
+BEM_HD inline void grad_column(const SegGeom<T>& g, const PairState<T>& p, T bC, T bL2, T ce, T cd, T cf,
+                               GradMatrix<T>& G, int k)
+{
+    const T tL = T(2) * bL2;
+    G.g[0][k] = bC * p.ey + ce * p.ex + cd * p.dx - tL * g.vx;
+    G.g[1][k] = -bC * p.ex + ce * p.ey + cd * p.dy - tL * g.vy;
+    G.g[2][k] = -bC * p.dy + ce * p.dx + cf * p.ex + tL * g.vx;
+    G.g[3][k] = bC * p.dx + ce * p.dy + cf * p.ey + tL * g.vy;
+}
+
+template <class T>
+BEM_HD inline GradMatrix<T> pair_grad_matrix(const SegGeom<T>& g, const PairState<T>& p, T eps2)
+{
+    GradMatrix<T> G;
+    const T iRR = p.iR0 * p.iR1;
+    const T PeR = p.Pe * iRR;
+    const T k1 = T(0.5) * p.iQ * p.iQ * (PeR - p.gq);    // bQ2 per unit bg
+    const T k2 = p.iQ * (p.Dl + p.Q * PeR);              // bQ2 per unit bS0
+    const T k3 = p.Q * p.iQ * iRR;                       // -bP per unit bg
+    const T k4 = T(2) * p.Q * p.Q * iRR;                 // -bP per unit bS0
+    const T C2 = T(2) * p.C;
+    const T kg = T(2) * p.kdC * p.gq;
+    {   // wa = wb = 1: Ad = 2 gq L2, bg = 2 kdC L2, bD1 = -bD0 = 2 kdC gq, bell = 0
+        const T bg = T(2) * p.kdC * g.L2;
+        const T bQ2 = k1 * bg;
+        const T bC = g.kd * (T(2) * p.gq * g.L2) + C2 * bQ2;
+        const T bL2 = -kg + eps2 * bQ2;
+        const T ce = -T(2) * kg - k3 * bg;
+        grad_column(g, p, bC, bL2, ce, T(2) * kg, T(2) * kg, G, 0);
+    }
+    {   // wb = 1: Ad = ell - 2 gq D0, bg = -2 kdC D0, bD0 = -2 kdC gq, bell = kdC
+        const T Ad = p.ell - T(2) * p.gq * p.D0;
+        const T bg = -T(2) * p.kdC * p.D0;
+        const T bQ2 = k1 * bg;
+        const T bC = g.kd * Ad + C2 * bQ2;
+        const T bL2 = -p.kdC * g.iL2 * Ad + eps2 * bQ2;
+        const T ce = -kg - k3 * bg;
+        const T cd = T(2) * (kg - p.kdC * p.iR0);
+        const T cf = T(2) * p.kdC * p.iR1;
+        grad_column(g, p, bC, bL2, ce, cd, cf, G, 1);
+    }
+    const T hS = T(2) * g.ks * p.S0;
+    {   // sa = sb = 1: bS0 = -2 ks L2, bS1 = 0, As = -2 S0 L2, bD1 = -2 ks S0 + bS0 ell, bD0 = 2 ks S0
+        const T b0 = -T(2) * g.ks * g.L2;
+        const T bQ2 = k2 * b0;
+        const T bC = C2 * bQ2;
+        const T bL2 = T(1.5) * hS + b0 * (p.l0 - T(2)) + eps2 * bQ2;
+        const T bD1 = -hS + b0 * p.ell;
+        const T ce = hS - bD1 - k4 * b0;
+        const T cd = T(2) * (-b0 * p.D0 * p.iR0 - hS);
+        const T cf = T(2) * (b0 * p.D1 * p.iR1 + bD1);
+        grad_column(g, p, bC, bL2, ce, cd, cf, G, 2);
+    }
+    {   // sb = -1: bS0 = -2 ks D0, bS1 = ks L2, As = L2 S1 - 2 S0 D0, bD1 = bS0 ell,
+        //          bD0 = -2 ks S0 + 2 bS1 (l0 - 1)
+        const T b0 = -T(2) * g.ks * p.D0;
+        const T b1 = g.ks * g.L2;
+        const T As = g.L2 * p.S1 - T(2) * p.S0 * p.D0;
+        const T bdR = b1 * (p.l0 - T(1));
+        const T bQ2 = k2 * b0;
+        const T bC = C2 * bQ2;
+        const T bL2 = g.ks * p.S1 - T(1.5) * g.ks * As * g.iL2 + b0 * (p.l0 - T(2)) + bdR + eps2 * bQ2;
+        const T bell = b0 * p.D1 + b1 * p.R1;
+        const T bD1 = b0 * p.ell;
+        const T bD0 = -hS + T(2) * bdR;
+        const T bl0 = b0 * g.L2 + b1 * p.dR;
+        const T bR1 = b1 * p.ell + bell * p.iR1;
+        const T bR0 = (bl0 - bell) * p.iR0;
+        const T ce = bD0 - bD1 - k4 * b0;
+        grad_column(g, p, bC, bL2, ce, T(2) * (bR0 - bD0), T(2) * (bR1 + bD1), G, 3);
+    }
+    return G;
+}
+
+// grad = G (wa, wb - wa, sa, sa - sb)
+template <class T>
+BEM_HD inline Grad4<T> grad_apply(const GradMatrix<T>& G, T wa, T wb, T sa, T sb)
+{
+    const T u[4] = {wa, wb - wa, sa, sa - sb};
+    T r[4];
+    for (int i = 0; i < 4; ++i) r[i] = G.g[i][0] * u[0] + G.g[i][1] * u[1] + G.g[i][2] * u[2] + G.g[i][3] * u[3];
+    return Grad4<T>{r[0], r[1], r[2], r[3]};
+}
+
 // Gradient of wa Md_a + wb Md_b + sa Ms_a + sb Ms_b w.r.t. (a, b), and the
 // moments themselves in *mom when mom != nullptr.
 template <class T, class M, bool Guard = true>

@@ -60,9 +60,33 @@ void adjoint(const double* x, int64_t n, const double* seg, int64_t K, double ep
             q[0] = m.da; q[1] = m.db; q[2] = m.sa; q[3] = m.sb;
         }
 }
+// The same gradients through the gradient-matrix form (one matrix per pair, applied to the
+// cotangents).
+template <class T>
+void adjoint_matrix(const double* x, int64_t n, const double* seg, int64_t K, double eps, const double* w,
+                    double* grad)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k < K; ++k) {
+            const auto g = geom<T>(seg + 4 * k);
+            const double* c = w + 4 * (i * K + k);
+            const T e2 = (T)(eps * eps);
+            const auto p = bem::pair_forward<T, HostM<T>>(g, (T)x[2 * i], (T)x[2 * i + 1], e2);
+            const auto G = bem::pair_grad_matrix(g, p, e2);
+            const auto r = bem::grad_apply(G, (T)c[0], (T)c[1], (T)c[2], (T)c[3]);
+            double* o = grad + 4 * (i * K + k);
+            o[0] = r.ax; o[1] = r.ay; o[2] = r.bx; o[3] = r.by;
+        }
+}
 }  // namespace
 
 extern "C" {
+void hm_adjoint_matrix_f64(const double* x, int64_t n, const double* seg, int64_t K, double eps, const double* w,
+                           double* grad)
+{ adjoint_matrix<double>(x, n, seg, K, eps, w, grad); }
+void hm_adjoint_matrix_f32(const double* x, int64_t n, const double* seg, int64_t K, double eps, const double* w,
+                           double* grad)
+{ adjoint_matrix<float>(x, n, seg, K, eps, w, grad); }
 void hm_moments_f64(const double* x, int64_t n, const double* seg, int64_t K, double eps, double* out)
 { moments<double>(x, n, seg, K, eps, out); }
 void hm_moments_f32(const double* x, int64_t n, const double* seg, int64_t K, double eps, double* out)

@@ -35,6 +35,9 @@ def hm():
     for name in ("hm_adjoint_f64", "hm_adjoint_f32"):
         getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    for name in ("hm_adjoint_matrix_f64", "hm_adjoint_matrix_f32"):
+        getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
     L.hm_beta_f64.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     return L
 
@@ -82,6 +85,40 @@ def test_device_adjoint_matches_oracle_duals(hm, eps):
     assert np.allclose(mom, np.stack([m.v for m in M], -1), rtol=1e-9, atol=1e-14)
     scale = np.abs(ref).max()
     assert np.abs(grad - ref).max() < 1e-9 * scale
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-2])
+def test_gradient_matrix_form_matches_oracle_duals(hm, eps):
+    """The per-pair gradient matrix applied to the cotangents (the J-tile kernel's form, one matrix
+    shared by the three colour channels) against the oracle's dual numbers; with nearly equal end
+    densities (a smooth colour along the curve) the float32 matrix form stays as accurate as the
+    float32 reverse pass."""
+    x, seg, a, b = _case(2)
+    n, K = len(x), len(seg)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal((n, K, 4))
+    M = O.segment_moments(x, du.seed(a[:, 0], 4, 0), du.seed(a[:, 1], 4, 1), du.seed(b[:, 0], 4, 2),
+                          du.seed(b[:, 1], 4, 3), eps)
+
+    def ref_of(w):
+        return sum(w[:, :, i, None] * M[i].d for i in range(4))
+
+    grad = np.zeros((n, K, 4))
+    hm.hm_adjoint_matrix_f64(_p(x), n, _p(seg), K, eps, _p(np.ascontiguousarray(w)), _p(grad))
+    ref = ref_of(w)
+    assert np.abs(grad - ref).max() < 1e-9 * np.abs(ref).max()
+    # float32: nearly equal end densities, each pair against its own scale
+    base = rng.standard_normal((n, K, 1, 2)) * np.ones((1, 1, 2, 1))
+    ws = np.ascontiguousarray((base + 1e-2 * rng.standard_normal((n, K, 2, 2))).reshape(n, K, 4)[:, :, [0, 2, 1, 3]])
+    ref = ref_of(ws)
+    g32, gm32, mom = np.zeros((n, K, 4)), np.zeros((n, K, 4)), np.zeros((n, K, 4))
+    hm.hm_adjoint_f32(_p(x), n, _p(seg), K, eps, _p(ws), _p(g32), _p(mom))
+    hm.hm_adjoint_matrix_f32(_p(x), n, _p(seg), K, eps, _p(ws), _p(gm32))
+    far = np.hypot(*(x[:, None, :] - 0.5 * (a + b)[None]).transpose(2, 0, 1)) > 0.1
+    scale = np.abs(ref).max(-1)[far] + 1e-30
+    e_rev = (np.abs(g32 - ref).max(-1)[far] / scale).max()
+    e_mat = (np.abs(gm32 - ref).max(-1)[far] / scale).max()
+    assert e_mat < max(4 * e_rev, 1e-5), (e_mat, e_rev)
 
 
 def test_device_beta_matches_oracle(hm):
