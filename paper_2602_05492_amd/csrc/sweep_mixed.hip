@@ -36,6 +36,25 @@ __device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearP
     used += __popcll(mask);
 }
 
+// The segment records are staged through LDS in chunks: the block copies a chunk with
+// coalesced 16-byte loads, then every wavefront reads each record by broadcast LDS reads.
+// Measured on one MI355X against the alternatives (LM workload, sweep time per step):
+// wave-uniform scalar loads of each record 81 ms, scalar loads issued one record ahead
+// 86 ms, LDS staging 72 ms.  The outer-element records (32 KB in all) stay on scalar
+// loads: staging them as well was no faster.
+constexpr int kStageSegs = 256;                                 // segment records per chunk
+constexpr int kSweepStage = kStageSegs * (kSegStride / 4);      // float4 slots (24 KB)
+static_assert(kSegStride % 4 == 0, "segment records are whole float4s");
+
+// Copies n float4s of records into the block's stage; every thread of the block calls it.
+__device__ inline void stage_records(float4* __restrict__ stage, const float* __restrict__ src, int n)
+{
+    __syncthreads();                              // the previous chunk has been read by all
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) stage[e] = s4[e];
+    __syncthreads();
+}
+
 // The float32 record of a degenerate segment evaluates to exactly zero and is
 // never near (its L2 is 0), so the segment loop needs no branch for it.
 __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x, int64_t N,
@@ -53,19 +72,24 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
     bool overflow = false;
     int used = 0;
-    for (int k = 0; k < K; ++k) {
-        const float* s = seg32 + (size_t)k * kSegStride;
-        const SegGeom<float> g = load_geom(s);
-        float w[12];
+    __shared__ float4 stage[kSweepStage];
+    for (int k0 = 0; k0 < K; k0 += kStageSegs) {
+        const int nk = K - k0 < kStageSegs ? K - k0 : kStageSegs;
+        stage_records(stage, seg32 + (size_t)k0 * kSegStride, nk * (kSegStride / 4));
+        for (int kk = 0; kk < nk; ++kk) {
+            const float* s = reinterpret_cast<const float*>(stage + kk * (kSegStride / 4));
+            const SegGeom<float> g = load_geom(s);
+            float w[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
-        const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
-        append_near(near, (int32_t)i, k, slice, slots, used, overflow);
-        const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
-        const float on = near ? 0.0f : 1.0f;
-        f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
-        f1 += on * (m.da * w[1] + m.db * w[4] + m.sa * w[7] + m.sb * w[10]);
-        f2 += on * (m.da * w[2] + m.db * w[5] + m.sa * w[8] + m.sb * w[11]);
+            for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
+            const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
+            append_near(near, (int32_t)i, k0 + kk, slice, slots, used, overflow);
+            const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
+            const float on = near ? 0.0f : 1.0f;
+            f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
+            f1 += on * (m.da * w[1] + m.db * w[4] + m.sa * w[7] + m.sb * w[10]);
+            f2 += on * (m.da * w[2] + m.db * w[5] + m.sa * w[8] + m.sb * w[11]);
+        }
     }
     float b0 = 0.f, b1 = 0.f, b2 = 0.f;
     for (int j = 0; j < M; ++j) {
