@@ -285,7 +285,8 @@ int bem_jtj(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
  * so that neighbouring samples share wavefronts; x and target themselves are
  * not modified, and the result depends on the order only through rounding.
  * If the near-pair list of the sweep at theta overflows, its capacity is raised
- * and the sweep repeated before the adjoint and the normal equations.
+ * (to 1.25 times the largest wavefront count, rounded up to 256) and the sweep
+ * repeated before the adjoint and the normal equations.
  * If the Cholesky fails, lambda is multiplied by 10 and the solve retried (at
  * most 10 times) before ENOTPD.  theta [H,Q] (device) is updated in place;
  * state (host) is read and written.  Synchronises the stream.

@@ -302,12 +302,14 @@ static int read_need(bem_ctx* ctx, const int* dneed, hipStream_t s, int* need)
     return BEM_OK;
 }
 
-// Raise the context's near-pair capacity to hold wavefronts of `need` pairs; true if that is
-// more than the slots per wavefront of the list that overflowed.
+// Raise the context's near-pair capacity to hold wavefronts of `need` pairs with a quarter of
+// headroom (a fresh batch of samples seldom packs more than that into one wavefront, and each
+// overflow costs a repeated sweep); true if that is more than the slots per wavefront of the
+// list that overflowed.
 static bool raise_near_slots(bem_ctx* ctx, int need, int64_t nwaves, int slots)
 {
     if (need <= slots) return false;
-    const int want = near_slots_for(need, nwaves);
+    const int want = near_slots_for(need + need / 4, nwaves);
     if (want > ctx->near_slots) ctx->near_slots = want;
     return want > slots;
 }
