@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstring>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include <cstring>
@@ -559,6 +560,70 @@ __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x,
     }
 }
 
+// beta rows into a split-bfloat16 tile in the blocked layout [t / 32][row][t % 32]: the block
+// computes its 256 samples x kBetaRunBlocked elements into LDS, then writes whole runs: the
+// kBetaRunBlocked rows of one 32-sample block are one contiguous 1 KiB run (hi, and another for
+// lo), written with 16-byte stores.  (Written lane by lane, each store instruction of a
+// wavefront covered two 64-byte halves of cache lines; beside the Gram that took 1.5-2.4 ms
+// per 32,768-sample tile against 0.05 ms alone.)  LDS rows hold their 8-sample chunks in
+// XOR-swizzled order (chunk q of row r at q ^ (r & 7)), so that the 16-byte reads of 16 rows
+// at one chunk fall in different banks; 16 KiB, so that a block fits beside a Gram block.
+// Samples past npts in a written block are zeros.
+constexpr int kBetaRunBlocked = 16;
+template <bool Mixed>
+__global__ void __launch_bounds__(256) k_beta_rows_blocked(const double* __restrict__ x, int64_t npts,
+                                                           const double* __restrict__ el64,
+                                                           const float* __restrict__ el32, int M, float near2,
+                                                           uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
+                                                           int64_t ld, int64_t row0)
+{
+    constexpr int R = kBetaRunBlocked;
+    __shared__ __attribute__((aligned(16))) uint16_t sh[2][R][256];
+    const int64_t t0 = (int64_t)blockIdx.x * 256;
+    const int64_t t = t0 + threadIdx.x;
+    const int j0 = blockIdx.y * R, nj = M - j0 < R ? M - j0 : R;
+    const bool live = t < npts;
+    const double X = live ? x[2 * t] : 0.0, Y = live ? x[2 * t + 1] : 0.0;
+    const float Xf = (float)X, Yf = (float)Y;
+    for (int jj = 0; jj < nj; ++jj) {
+        const int j = j0 + jj;
+        const double* e = el64 + (size_t)j * kElemStride;
+        double b = 0.0;
+        if (live) {
+            if (Mixed) {
+                const float* f = el32 + (size_t)j * kElemStride;
+                if (near_element(f[0], f[1], f[2], f[3], Xf, Yf, near2))
+                    b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+                else
+                    b = (double)element_beta<float, DevF32>(f[0], f[1], f[2], f[3], Xf, Yf);
+            } else {
+                b = element_beta<double, DevF64>(e[0], e[1], e[2], e[3], X, Y);
+            }
+        }
+        const float v = (float)b;
+        const uint16_t h = bf16_bits(v);
+        const int col = threadIdx.x ^ ((jj & 7) << 3);
+        sh[0][jj][col] = h;
+        sh[1][jj][col] = bf16_bits(v - bf16_value(h));
+    }
+    __syncthreads();
+    // hi and lo x 8 sample blocks x R rows x 4 chunks of 8 samples; a wavefront writes the R rows of
+    // one sample block (R x 64 bytes, contiguous)
+    constexpr int per = 8 * R * 4;
+    for (int e = threadIdx.x; e < 2 * per; e += 256) {
+        const int which = e / per, r = e % per;
+        const int sb = r / (R * 4), jj = (r >> 2) % R, c = r & 3;
+        // sample blocks wholly past npts are not written: the tile holds npts rounded up to 32
+        // (64) samples, which need not reach the block's 256
+        if (jj >= nj || t0 + sb * 32 >= npts) continue;
+        const int q = (sb * 4 + c) ^ (jj & 7);          // swizzled 8-sample chunk of this row
+        const uint4 v = *reinterpret_cast<const uint4*>(&sh[which][jj][q * 8]);
+        uint16_t* dst = (which ? Xl : Xh) + (size_t)((t0 >> 5) + sb) * (size_t)(ld << 5) +
+                        (size_t)((row0 + j0 + jj) << 5) + c * 8;
+        *reinterpret_cast<uint4*>(dst) = v;
+    }
+}
+
 __global__ void k_gauss_points(int M, const double* __restrict__ eg, double* __restrict__ gx)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -846,7 +911,16 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
         const int64_t nz = 3 * (gp - L.geo()) * npts;
         hipLaunchKernelGGL((k_zero_pad<OutT>), dim3(blocks_for(nz, 256)), dim3(256), 0, s, Xt, Xlo, ld, gp, L.geo(), npts);
     }
-    if (with_beta) {
+    if (with_beta && std::is_same<OutT, uint16_t>::value) {
+        const dim3 gb(blocks_for(npts, 256), blocks_for(ctx->M, kBetaRunBlocked));
+        ProfScope ps_(ctx, PT_BETA_ROWS, s);
+        if (mixed)
+            hipLaunchKernelGGL((k_beta_rows_blocked<true>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0);
+        else
+            hipLaunchKernelGGL((k_beta_rows_blocked<false>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
+                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0);
+    } else if (with_beta) {
         const dim3 gb(blocks_for(npts, 256), blocks_for(ctx->M, kBetaRun));
         if (mixed)
             {
