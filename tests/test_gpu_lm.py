@@ -64,6 +64,22 @@ def test_jtj_reduced_precision_modes(gram, prec):
     assert eh < 1e-4 and eg < 1e-3
 
 
+@pytest.mark.parametrize("per_side", [10, 256])
+def test_jtj_split_bf16_ragged_rows_and_tiles(per_side):
+    """Split-BF16 / mixed J^T J with sample tiles of 320 (the last 256-sample block of a tile holds
+    64 samples) and a ragged tail (N = 2085), and with 40 outer elements (the beta rows' last run of
+    16 holds 8) or 1,024, against the oracle."""
+    wl = W.make_config(1)
+    ctx = ctx_for(wl.S, per_side=per_side, tile_rows=320)
+    x = wl.samples(0)[:2085]
+    r = W.random_vector(53, (len(x), 3))
+    Ho, go = O.normal_equations(wl.theta_true, x, r, wl.S, wl.eps, per_side)
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(r, torch.float32), "bf16x3_mfma", "mixed")
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"jtj bf16x3 ragged (M = {4 * per_side}): rel err JtJ {eh:.3e} Jtr {eg:.3e}")
+    assert eh < 1e-4 and eg < 1e-3
+
+
 def test_jtj_default_tiles_absorb_short_tail():
     """33,000 samples with the default sample tile (32,768 for the split-BF16 Gram): the
     968-sample tail is spread over one tile of 33,024 samples instead of a second tile;
