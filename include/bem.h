@@ -221,6 +221,11 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
  * the segment adjoints at the boundary Gauss points with cotangent mu.
  * gbar [N,3] row-major (float64 for FP64, float32 for MIXED), grad [H,Q]
  * float64, overwritten.  The mean colour does not depend on theta.
+ * MIXED with N >= 65,536 samples: a copy of x and gbar reordered cell by cell
+ * (a 32 x 32 grid of Morton-ordered cells over the outer boundary's bounding
+ * box; 80 bytes per sample of context workspace) is processed, so that the
+ * near pairs of a wavefront form long runs; the result depends on the order
+ * only through rounding.
  * Errors: as bem_eval. */
 int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N,
             const void* gbar, double* grad, bem_prec prec, hipStream_t stream);

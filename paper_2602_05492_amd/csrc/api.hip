@@ -290,6 +290,8 @@ int bem_eval(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int6
     return launch_sweep_mixed(ctx, x, N, K, cbar, (float*)u, stream);
 }
 
+constexpr int64_t kVjpCellOrderMin = 65536;     // samples from which MIXED bem_vjp reorders them
+
 int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64_t N, const void* gbar, double* grad,
             bem_prec prec, hipStream_t stream)
 {
@@ -298,6 +300,14 @@ int bem_vjp(bem_ctx* ctx, const double* theta, int32_t H, const double* x, int64
     if (N > 0 && !gbar) return set_error(ctx, BEM_EINVAL, "gbar is null");
     if (H > 0 && !grad) return set_error(ctx, BEM_EINVAL, "grad is null");
     if (prec != BEM_PREC_FP64 && prec != BEM_PREC_MIXED) return set_error(ctx, BEM_EINVAL, "bad precision %d", (int)prec);
+    // MIXED with many samples: visit them cell by cell, so that the near pairs of a wavefront form
+    // long runs of one segment (one set of float64 sums per run instead of one per pair)
+    if (prec == BEM_PREC_MIXED && H > 0 && N >= kVjpCellOrderMin) {
+        const double* xo;
+        const float* go;
+        if ((rc = cell_order_f32(ctx, x, (const float*)gbar, N, &xo, &go, stream))) return rc;
+        return run_vjp(ctx, theta, H, xo, N, go, true, grad, stream);
+    }
     return run_vjp(ctx, theta, H, x, N, gbar, prec == BEM_PREC_MIXED, grad, stream);
 }
 

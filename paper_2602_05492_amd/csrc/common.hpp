@@ -152,9 +152,12 @@ struct NearList;
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s,
                        NearList* out = nullptr);
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
-// partition.hip
+// partition.hip (off_host may be null: no readback and no host synchronisation)
 int run_partition(bem_ctx* ctx, const int32_t* labels, int64_t N, int D, const double* x, const double* T, double* xo,
                   double* To, int64_t* off_host, hipStream_t s);
+// lm.hip: samples and float32 cotangents reordered cell by cell into the sort workspace
+int cell_order_f32(bem_ctx* ctx, const double* x, const float* g, int64_t N, const double** xo, const float** go,
+                   hipStream_t s);
 // reg.hip
 bool reg_active(const bem_ctx* ctx);
 int check_reg(const bem_reg& r, char* why, size_t n);

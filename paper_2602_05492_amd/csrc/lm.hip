@@ -291,6 +291,18 @@ __global__ void k_deal_chunks(const double* __restrict__ x, const double* __rest
     To[3 * j + 2] = T[3 * i + 2];
 }
 
+__global__ void k_widen3(const float* __restrict__ g, int64_t n, double* __restrict__ o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (double)g[i];
+}
+
+__global__ void k_narrow3(const double* __restrict__ g, int64_t n, float* __restrict__ o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (float)g[i];
+}
+
 // Largest overflowing near-pair count of a wavefront in a mixed sweep (0: no slice overflowed).
 static int read_need(bem_ctx* ctx, const int* dneed, hipStream_t s, int* need)
 {
@@ -312,6 +324,33 @@ static bool raise_near_slots(bem_ctx* ctx, int need, int64_t nwaves, int slots)
     const int want = near_slots_for(need + need / 4, nwaves);
     if (want > ctx->near_slots) ctx->near_slots = want;
     return want > slots;
+}
+
+// Samples and their float32 cotangents reordered cell by cell (the order of lm_step's sweeps) into
+// the context's sort workspace, without a host synchronisation; *xo and *go point into it.
+int cell_order_f32(bem_ctx* ctx, const double* x, const float* g, int64_t N, const double** xo, const float** go,
+                   hipStream_t s)
+{
+    int rc;
+    const size_t lb = ((size_t)N * sizeof(int32_t) + 255) / 256 * 256;
+    const size_t gb = ((size_t)N * 3 * sizeof(float) + 255) / 256 * 256;
+    if ((rc = ensure(ctx, ctx->sortw, lb + gb + (size_t)N * 8 * sizeof(double), s))) return rc;
+    int32_t* lab = (int32_t*)ctx->sortw.ptr;
+    float* g32 = (float*)((char*)ctx->sortw.ptr + lb);
+    double* xc = (double*)((char*)ctx->sortw.ptr + lb + gb);
+    double* gw = xc + 2 * N;                      // cotangents widened, input order
+    double* gc = gw + 3 * N;                      // cell order
+    const double bw = ctx->bbox[2] - ctx->bbox[0], bh = ctx->bbox[3] - ctx->bbox[1];
+    hipLaunchKernelGGL(k_cell_labels, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, ctx->bbox[0], ctx->bbox[1],
+                       bw > 0.0 ? kCellSide / bw : 0.0, bh > 0.0 ? kCellSide / bh : 0.0, lab);
+    hipLaunchKernelGGL(k_widen3, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, g, 3 * N, gw);
+    // every label is a cell index in [0, kCells), so every sample is kept
+    if ((rc = run_partition(ctx, lab, N, kCells, x, gw, xc, gc, nullptr, s))) return rc;
+    hipLaunchKernelGGL(k_narrow3, dim3(blocks_for(3 * N, 256)), dim3(256), 0, s, (const double*)gc, 3 * N, g32);
+    if ((rc = check_launch(ctx, "sample reordering"))) return rc;
+    *xo = xc;
+    *go = g32;
+    return BEM_OK;
 }
 
 int run_lm_step(bem_ctx* ctx, double* theta, int H, const double* x, int64_t N, const double* T, bem_lm_state* st,

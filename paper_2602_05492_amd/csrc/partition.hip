@@ -146,6 +146,7 @@ int run_partition(bem_ctx* ctx, const int32_t* labels, int64_t N, int D, const d
         hipLaunchKernelGGL(k_part_scatter, dim3(nb), dim3(256), 0, s, labels, N, D, nb, (const int64_t*)base,
                            (const int64_t*)off, x, T, xo, To);
     if ((rc = check_launch(ctx, "partition"))) return rc;
+    if (!off_host) return BEM_OK;                // no readback (and no host synchronisation)
     if (hipMemcpyAsync(off_host, off, (size_t)(D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_error(ctx, BEM_EHIP, "partition readback");

@@ -110,11 +110,72 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
     flag[i] = overflow ? 1 : 0;
 }
 
-// Near-pair classification only (for the adjoint and the J tiles): the same
-// wavefront slices and predicate as the float32 forward sweep.
+// Bounding boxes for the classification's culling: box g (g < H: handle g's S segments; g >= H:
+// group g - H of kElemGroup outer elements) = the end points' extent (xmin, ymin, xmax, ymax) and
+// the largest near radius sqrt(near2 L2) of its members.  Degenerate segments (L2 = 0) are never
+// near and are left out; a box with no member is empty (min > max) and culls everything.
+constexpr int kElemGroup = 32;
+__global__ void k_near_boxes(const float* __restrict__ seg32, int H, int S, const float* __restrict__ el32, int M,
+                             float near2, float4* __restrict__ box)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = H + (M + kElemGroup - 1) / kElemGroup;
+    if (g >= ng) return;
+    float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY, r = 0.0f;
+    if (g < H) {
+        for (int j = 0; j < S; ++j) {
+            const float* sg = seg32 + (size_t)(g * S + j) * kSegStride;
+            if (sg[6] == 0.0f) continue;
+            x0 = fminf(x0, fminf(sg[0], sg[2])); x1 = fmaxf(x1, fmaxf(sg[0], sg[2]));
+            y0 = fminf(y0, fminf(sg[1], sg[3])); y1 = fmaxf(y1, fmaxf(sg[1], sg[3]));
+            r = fmaxf(r, sqrtf(near2 * sg[6]));
+        }
+    } else {
+        const int j0 = (g - H) * kElemGroup, j1 = j0 + kElemGroup < M ? j0 + kElemGroup : M;
+        for (int j = j0; j < j1; ++j) {
+            const float* e = el32 + (size_t)j * kElemStride;
+            const float bx = e[0] + e[2], by = e[1] + e[3];
+            x0 = fminf(x0, fminf(e[0], bx)); x1 = fmaxf(x1, fmaxf(e[0], bx));
+            y0 = fminf(y0, fminf(e[1], by)); y1 = fmaxf(y1, fmaxf(e[1], by));
+            r = fmaxf(r, sqrtf(near2 * (e[2] * e[2] + e[3] * e[3])));
+        }
+    }
+    box[2 * g] = make_float4(x0, y0, x1, y1);
+    box[2 * g + 1] = make_float4(r, 0.0f, 0.0f, 0.0f);
+}
+
+// True when no sample of the wavefront's box [wx0, wx1] x [wy0, wy1] can be near a member of box g:
+// the boxes' distance exceeds the members' largest near radius by a margin far above the float32
+// rounding of the exact test (a pair is near only if both of its end points lie within the radius).
+__device__ inline bool box_culled(const float4* __restrict__ box, int g, float wx0, float wy0, float wx1, float wy1)
+{
+    const float4 b = box[2 * g];
+    const float r = box[2 * g + 1].x * 1.001f + 1e-6f;
+    const float dx = fmaxf(0.0f, fmaxf(b.x - wx1, wx0 - b.z));
+    const float dy = fmaxf(0.0f, fmaxf(b.y - wy1, wy0 - b.w));
+    return !(b.x <= b.z) || dx * dx + dy * dy > r * r;      // empty box, or too far
+}
+
+__device__ inline float wave_min(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Near-pair classification only (for the adjoint and the J tiles): the same wavefront slices and
+// predicate as the float32 forward sweep.  Each wavefront first bounds its samples and skips every
+// handle (and every group of kElemGroup elements) whose box is farther than its near radius; the
+// exact test runs for the others, in segment order.  With samples visited cell by cell a
+// wavefront's box is small and most handles are skipped.
 __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, int64_t N,
-                                                  const float* __restrict__ seg32, int K,
+                                                  const float* __restrict__ seg32, int H, int S,
                                                   const float* __restrict__ el32, int M, float near2,
+                                                  const float4* __restrict__ box,
                                                   NearPair* __restrict__ list, int slots, int* __restrict__ wave_count,
                                                   uint8_t* __restrict__ flag, int* __restrict__ need)
 {
@@ -123,17 +184,27 @@ __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, 
     NearPair* slice = list + wave * slots;
     const bool live = i < N;
     const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
+    const float wx0 = wave_min(live ? Xf : INFINITY), wx1 = wave_max(live ? Xf : -INFINITY);
+    const float wy0 = wave_min(live ? Yf : INFINITY), wy1 = wave_max(live ? Yf : -INFINITY);
     bool overflow = false;
     int used = 0;
-    for (int k = 0; k < K; ++k) {
-        const float* s = seg32 + (size_t)k * kSegStride;
-        const bool near = live & near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2);
-        append_near(near, (int32_t)i, k, slice, slots, used, overflow);
+    const int K = H * S;
+    for (int h = 0; h < H; ++h) {
+        if (box_culled(box, h, wx0, wy0, wx1, wy1)) continue;
+        for (int k = h * S; k < (h + 1) * S; ++k) {
+            const float* s = seg32 + (size_t)k * kSegStride;
+            const bool near = live & near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2);
+            append_near(near, (int32_t)i, k, slice, slots, used, overflow);
+        }
     }
-    for (int j = 0; j < M; ++j) {
-        const float* e = el32 + (size_t)j * kElemStride;
-        const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
-        append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
+    for (int g = 0; g * kElemGroup < M; ++g) {
+        if (box_culled(box, H + g, wx0, wy0, wx1, wy1)) continue;
+        const int j1 = (g + 1) * kElemGroup < M ? (g + 1) * kElemGroup : M;
+        for (int j = g * kElemGroup; j < j1; ++j) {
+            const float* e = el32 + (size_t)j * kElemStride;
+            const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
+            append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
+        }
     }
     if ((threadIdx.x & 63) == 0) {
         wave_count[wave] = used < slots ? used : slots;
@@ -254,11 +325,16 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     const double nf = near_radius(ctx->opts.near_factor);
     const int64_t nwaves = N > 0 ? (int64_t)blocks_for(N, 256) * 4 : 0;
     const int slots = near_slots_for(ctx->near_slots, nwaves);
-    // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N]
+    // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N] | culling boxes
+    const int S = ctx->opts.segs_per_handle, H = K / S;
+    const int nbox = H + (M + kElemGroup - 1) / kElemGroup;
     const size_t list_bytes = ((size_t)nwaves * slots * sizeof(NearPair) + 255) / 256 * 256;
     const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
-    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + 256 + (size_t)N + 256, s))) return rc;
+    const size_t flag_bytes = ((size_t)N + 255) / 256 * 256;
+    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + 256 + flag_bytes + (size_t)nbox * 2 * sizeof(float4) + 256, s)))
+        return rc;
     char* base = (char*)buf.ptr;
+    float4* box = (float4*)(base + list_bytes + cnt_bytes + 256 + flag_bytes);
     out->list = (NearPair*)base;
     out->count = (int*)(base + list_bytes);
     out->need = (int*)(base + list_bytes + cnt_bytes);
@@ -268,9 +344,12 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     if ((rc = fill_i32(ctx, out->need, 1, 0, s))) return rc;
     if (N == 0) return BEM_OK;
     ProfScope ps_(ctx, PT_NEAR, s);
-    hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, K,
-                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), out->list, slots, out->count, out->flag,
-                       out->need);
+    if (nbox > 0)
+        hipLaunchKernelGGL(k_near_boxes, dim3(blocks_for(nbox, 256)), dim3(256), 0, s, (const float*)ctx->seg32.ptr, H, S,
+                           (const float*)ctx->elem32.ptr, M, (float)(nf * nf), box);
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, H, S,
+                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), (const float4*)box, out->list, slots,
+                       out->count, out->flag, out->need);
     return check_launch(ctx, "classify");
 }
 
