@@ -484,7 +484,7 @@ void bem_destroy(bem_ctx* ctx)
     DevBuf* bufs[] = {&ctx->A, &ctx->Apinv, &ctx->LU, &ctx->piv, &ctx->un, &ctx->vn, &ctx->flag, &ctx->scal,
                       &ctx->seg64, &ctx->seg32, &ctx->F, &ctx->U, &ctx->elem64, &ctx->elem32, &ctx->red,
                       &ctx->tmp0, &ctx->tmp1, &ctx->tmp2, &ctx->tmp3, &ctx->tmp4, &ctx->tmp5, &ctx->lmw,
-                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw, &ctx->sortw,
+                      &ctx->nearw, &ctx->nearv, &ctx->nearf, &ctx->regw, &ctx->egeo, &ctx->cholw, &ctx->sortw, &ctx->boxw,
                       &ctx->tilew};
     for (DevBuf* b : bufs) release(*b);
     for (hipEvent_t e : ctx->ev)

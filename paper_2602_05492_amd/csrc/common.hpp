@@ -101,7 +101,8 @@ struct bem_ctx {
     // one-time boundary system
     bem::DevBuf A, Apinv, LU, piv, un, vn, flag, scal, egeo;   // egeo: outer elements [M][4] (a, b)
     // per-call workspaces
-    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw, sortw;
+    bem::DevBuf seg64, seg32, F, U, elem64, elem32, red, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, lmw, nearw, nearv, nearf, regw, cholw, sortw,
+        boxw;
     // Gram work list of the normal equations on the device, uploaded once per (W, H, handle
     // model, Gram arithmetic) and kept, so that later calls enqueue without a host synchronisation
     bem::DevBuf tilew;
@@ -152,6 +153,9 @@ struct NearList;
 int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const double* cbar_host, float* u, hipStream_t s,
                        NearList* out = nullptr);
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s);
+// culling boxes of the current segment table (groups of kBoxGroup segments, then of M outer
+// elements) into the context's box buffer
+int near_boxes(bem_ctx* ctx, int K, int M, const float4** box, hipStream_t s);
 // partition.hip (off_host may be null: no readback and no host synchronisation)
 int run_partition(bem_ctx* ctx, const int32_t* labels, int64_t N, int D, const double* x, const double* T, double* xo,
                   double* To, int64_t* off_host, hipStream_t s);

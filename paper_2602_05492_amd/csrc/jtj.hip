@@ -314,6 +314,49 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ x, 
     }
 }
 
+// One (sample, segment) pair of the mixed feature kernel: its moments and its end-point gradient
+// matrix, chained into col and geo (V: the vertex table at the segment's a end).  With Test the
+// values are masked to zero where the pair is near or the segment degenerate (every lane takes the
+// same path, with no branch-local copies of the loop-carried sums).  Without Test (a group of
+// segments whose box is out of the wavefront's reach: every pair far) a degenerate segment still
+// gives zeros: its float32 record is a far point with v = 0 and kd = ks = 0.
+__device__ __forceinline__ void feature_pair(const float* __restrict__ s32, const float* __restrict__ V, float Xf,
+                                             float Yf, float eps2f, float near2, bool Test, float (&geo)[3][8],
+                                             float (&col)[4], float (&pv)[3][2])
+{
+    const SegGeom<float> gf = load_geom(s32);
+    const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
+    Moments<float> m = pair_moments(gf, st);
+    // the end-point gradient is linear in the channel's end densities: one matrix per pair serves
+    // the three channels
+    GradMatrix<float> G = pair_grad_matrix(gf, st, eps2f);
+    if (Test) {
+        const bool far = gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2);
+        m.da = far ? m.da : 0.f;
+        m.db = far ? m.db : 0.f;
+        m.sa = far ? m.sa : 0.f;
+        m.sb = far ? m.sb : 0.f;
+        for (int r = 0; r < 4; ++r)
+            for (int k = 0; k < 4; ++k) G.g[r][k] = far ? G.g[r][k] : 0.f;
+    }
+    const float ta = V[4], sa_ = V[5];
+    const float tb = V[12], sb_ = V[13];
+    col[0] += m.da * sa_ + m.db * sb_;
+    col[1] += m.da * ta + m.db * tb;
+    col[2] += m.sa * sa_ + m.sb * sb_;
+    col[3] += m.sa * ta + m.sb * tb;
+    for (int c = 0; c < 3; ++c) {
+        const Grad4<float> gr = grad_apply(G, s32[kWdA + c], s32[kWdB + c], s32[kWcA + c], s32[kWcB + c]);
+        const float gx = gr.ax + pv[c][0], gy = gr.ay + pv[c][1];
+        for (int q = 0; q < 4; ++q) {
+            geo[c][2 * q] += V[q] * gx;
+            geo[c][2 * q + 1] += V[q] * gy;
+        }
+        pv[c][0] = gr.bx;
+        pv[c][1] = gr.by;
+    }
+}
+
 constexpr int kFeatVals = 28;   // chained contributions of one pair: geo[3][8] and col[4]
 
 // Mixed handle features: float32 pairs, near pairs skipped (same predicate as the
@@ -330,8 +373,8 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
                                                       float near2, const NearPair* __restrict__ list, int slots,
                                                       const int2* __restrict__ runs,
                                                       const uint8_t* __restrict__ flag, const float* __restrict__ corr,
-                                                      const float* __restrict__ vtab, OutT* __restrict__ Xt,
-                                                      uint16_t* __restrict__ Xlo, int64_t ld,
+                                                      const float* __restrict__ vtab, const float4* __restrict__ box,
+                                                      OutT* __restrict__ Xt, uint16_t* __restrict__ Xlo, int64_t ld,
                                                       const float* __restrict__ rr, float* __restrict__ rpart)
 {
     __shared__ float jtr_red[4][kJtrVals];
@@ -343,49 +386,34 @@ __global__ void __launch_bounds__(256, 6) k_features_far(const double* __restric
     for (int c = 0; c < 3; ++c)
         for (int q = 0; q < 8; ++q) geo[c][q] = 0.f;
     bool take = false;
+    // the wavefront's sample box (every lane takes part in the reductions, so before the branch on
+    // valid): groups of segments farther than their near radius take the loop without near tests
+    // (handles of few segments keep every near test: there a box lookup per pair and the box itself
+    // would cost more than they save; paper-native handles, S = 1: +0.25 ms per LM step)
+    const bool cull = S >= 8;
+    const float Xv = valid ? (float)x[2 * t] : 0.f, Yv = valid ? (float)x[2 * t + 1] : 0.f;
+    float wx0 = 0.f, wx1 = 0.f, wy0 = 0.f, wy1 = 0.f;
+    if (cull) {
+        wx0 = uniform_f32(wave_min(valid ? Xv : INFINITY));
+        wx1 = uniform_f32(wave_max(valid ? Xv : -INFINITY));
+        wy0 = uniform_f32(wave_min(valid ? Yv : INFINITY));
+        wy1 = uniform_f32(wave_max(valid ? Yv : -INFINITY));
+    }
     if (valid) {
-        const float Xf = (float)x[2 * t], Yf = (float)x[2 * t + 1];
+        const float Xf = Xv, Yf = Yv;
         // pv[c]: the b-end gradient of segment j - 1, carried to vertex j; each channel's a-end
         // gradient is chained into geo as soon as it is formed, so that only one channel's
         // end-point gradients are live at a time
         float pv[3][2];
         for (int c = 0; c < 3; ++c) pv[c][0] = pv[c][1] = 0.f;
+        // test: whether the pairs need the near test (false once the segment's group of kBoxGroup
+        // segments is out of the wavefront's reach; wave-uniform, looked up at each group's start)
+        bool test = true;
+#pragma unroll 1
         for (int j = 0; j < S; ++j) {
-            const float* s32 = seg32 + (size_t)(h * S + j) * kSegStride;
-            const SegGeom<float> gf = load_geom(s32);
-            const float* B = vtab + 8 * j;
-            // degenerate segments (L2 = 0 in the table) contribute nothing and are never near.
-            // Every lane evaluates the pair (its values may be non-finite where the pair is near or
-            // the segment degenerate) and then keeps them only where it is far: every pair takes the
-            // same path, with no branch-local copies of the loop-carried sums
-            const bool far = gf.L2 != 0.0f && !near_segment(gf.ax, gf.ay, gf.bx, gf.by, gf.L2, Xf, Yf, near2);
-            const PairState<float> st = pair_forward<float, DevF32, false>(gf, Xf, Yf, eps2f);
-            Moments<float> m = pair_moments(gf, st);
-            // the end-point gradient is linear in the channel's end densities: one matrix per pair
-            // serves the three channels
-            GradMatrix<float> G = pair_grad_matrix(gf, st, eps2f);
-            m.da = far ? m.da : 0.f;
-            m.db = far ? m.db : 0.f;
-            m.sa = far ? m.sa : 0.f;
-            m.sb = far ? m.sb : 0.f;
-            for (int r = 0; r < 4; ++r)
-                for (int k = 0; k < 4; ++k) G.g[r][k] = far ? G.g[r][k] : 0.f;
-            const float ta = vtab[8 * j + 4], sa_ = vtab[8 * j + 5];
-            const float tb = vtab[8 * j + 12], sb_ = vtab[8 * j + 13];
-            col[0] += m.da * sa_ + m.db * sb_;
-            col[1] += m.da * ta + m.db * tb;
-            col[2] += m.sa * sa_ + m.sb * sb_;
-            col[3] += m.sa * ta + m.sb * tb;
-            for (int c = 0; c < 3; ++c) {
-                const Grad4<float> gr = grad_apply(G, s32[kWdA + c], s32[kWdB + c], s32[kWcA + c], s32[kWcB + c]);
-                const float gx = gr.ax + pv[c][0], gy = gr.ay + pv[c][1];
-                for (int q = 0; q < 4; ++q) {
-                    geo[c][2 * q] += B[q] * gx;
-                    geo[c][2 * q + 1] += B[q] * gy;
-                }
-                pv[c][0] = gr.bx;
-                pv[c][1] = gr.by;
-            }
+            const int k = h * S + j;
+            if (cull && (j == 0 || k % kBoxGroup == 0)) test = !box_culled(box, k / kBoxGroup, wx0, wy0, wx1, wy1);
+            feature_pair(seg32 + (size_t)k * kSegStride, vtab + 8 * j, Xf, Yf, eps2f, near2, test, geo, col, pv);
         }
         {
             const float* B = vtab + 8 * S;                  // the last vertex takes the carried b end
@@ -864,7 +892,8 @@ template <class OutT>
 static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, bool mixed, bool with_beta, OutT* Xt,
                            uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
                            const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr,
-                           int2* runs = nullptr, const float* rr = nullptr, float* rpart = nullptr, double* R = nullptr)
+                           int2* runs = nullptr, const float* rr = nullptr, float* rpart = nullptr, double* R = nullptr,
+                           const float4* box = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -876,7 +905,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     const int64_t beta_row0 = L.handle_rows();
     const int64_t gp = L.Gp;
     const dim3 grid(blocks_for(npts, 256), H);
-    if (mixed && (!nl || !xg || !corr || !vtab || !runs || (t0 & 63)))
+    if (mixed && (!nl || !xg || !corr || !vtab || !runs || !box || (t0 & 63)))
         return set_error(ctx, BEM_EINVAL, "mixed features need the near-pair list (internal)");
     if (H > 0) {
         if (mixed) {
@@ -891,7 +920,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
             ProfScope ps_(ctx, PT_FEATURES, s);
             hipLaunchKernelGGL((k_features_far<OutT>), grid, dim3(256), 0, s, x, npts, t0, (const float*)ctx->seg32.ptr,
                                H, S, model, gp, (float)eps2, near2, nl->list, nl->slots, (const int2*)runs, nl->flag, corr,
-                               vtab, Xt, Xlo, ld, rr, rpart);
+                               vtab, box, Xt, Xlo, ld, rr, rpart);
             if (rr)
                 hipLaunchKernelGGL(k_jtr_handles, dim3(H), dim3(256), 0, s, (const float*)rpart, (int)grid.x, H, model,
                                    gp, R);
@@ -1163,6 +1192,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     const float* rr = fused_r ? (const float*)resid : nullptr;
     const int xr_row0 = fused_r ? (int)L.handle_rows() : 0;
     hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
+    const float4* box = nullptr;        // culling boxes of the segment groups (mixed feature kernel)
+    if (mixed && (rc = near_boxes(ctx, H * S, 0, &box, s))) return rc;
     hipEvent_t* evF = ctx->ev;          // features of the tile in buffer b done
     hipEvent_t* evG = ctx->ev + 2;      // Gram of the tile in buffer b done
     if (overlap) {                      // the Gram stream starts after everything queued so far
@@ -1179,7 +1210,9 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             return set_error(ctx, BEM_EHIP, "stream wait");
         if (f64) {
             double* Xt = (double*)tile;
-            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs))) return rc;
+            if ((rc = launch_features<double>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs,
+                                              nullptr, nullptr, nullptr, box)))
+                return rc;
             {
                 ProfScope ps_(ctx, PT_GRAM_F64, s);
                 rc = gemm_f64(ctx, (int)W, (int)W, (int)n, 1.0, Xt, T, false, Xt, T, true, it > 0 ? 1.0 : 0.0, G, W, s,
@@ -1192,7 +1225,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
         } else if (gram == BEM_GRAM_FP32_MFMA) {
             float* Xt = (float*)tile;
             if ((rc = launch_features<float>(ctx, xt, n, H, mixed, true, Xt, nullptr, T, s, &nl, t0, x, corr, vtab, runs,
-                                             rr ? rr + 3 * t0 : nullptr, rpart, R)))
+                                             rr ? rr + 3 * t0 : nullptr, rpart, R, box)))
                 return rc;
             if (overlap && (hipEventRecord(evF[buf], s) != hipSuccess || hipStreamWaitEvent(sg, evF[buf], 0) != hipSuccess))
                 return set_error(ctx, BEM_EHIP, "stream wait");
@@ -1205,7 +1238,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
             if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab, runs,
-                                                rr ? rr + 3 * t0 : nullptr, rpart, R)))
+                                                rr ? rr + 3 * t0 : nullptr, rpart, R, box)))
                 return rc;
             if (n & 31)
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);

@@ -62,6 +62,39 @@ __device__ inline bool near_element(float ax, float ay, float vx, float vy, floa
     return (dd < lim) & (ee < lim);
 }
 
+// Culling of near-pair tests: a box per group of kBoxGroup consecutive segments (and of outer
+// elements), k_near_boxes.  A wavefront whose samples all lie farther from a group's box than the
+// group's largest near radius can skip the group's near tests: no pair in it is near.
+constexpr int kBoxGroup = 32;
+
+// True when no sample of the wavefront's box [wx0, wx1] x [wy0, wy1] can be near a member of box g:
+// the boxes' distance exceeds the members' largest near radius by a margin far above the float32
+// rounding of the exact test (a pair is near only if both of its end points lie within the radius).
+__device__ inline bool box_culled(const float4* __restrict__ box, int g, float wx0, float wy0, float wx1, float wy1)
+{
+    const float4 b = box[2 * g];
+    const float r = box[2 * g + 1].x * 1.001f + 1e-6f;
+    const float dx = fmaxf(0.0f, fmaxf(b.x - wx1, wx0 - b.z));
+    const float dy = fmaxf(0.0f, fmaxf(b.y - wy1, wy0 - b.w));
+    return !(b.x <= b.z) || dx * dx + dy * dy > r * r;      // empty box, or too far
+}
+
+__device__ inline float wave_min(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// a value equal in every lane of the wavefront, held in a scalar register
+__device__ inline float uniform_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 struct NearPair {
     int32_t sample;   // index within the launch's sample range
     int32_t seg;      // < K: handle segment, else outer element seg - K

@@ -45,6 +45,7 @@ __device__ inline void append_near(bool near, int32_t sample, int32_t seg, NearP
 constexpr int kStageSegs = 256;                                 // segment records per chunk
 constexpr int kSweepStage = kStageSegs * (kSegStride / 4);      // float4 slots (24 KB)
 static_assert(kSegStride % 4 == 0, "segment records are whole float4s");
+static_assert(kStageSegs % kBoxGroup == 0, "box groups lie within a chunk");
 
 // Copies n float4s of records into the block's stage; every thread of the block calls it.
 __device__ inline void stage_records(float4* __restrict__ stage, const float* __restrict__ src, int n)
@@ -60,6 +61,7 @@ __device__ inline void stage_records(float4* __restrict__ stage, const float* __
 __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x, int64_t N,
                                                    const float* __restrict__ seg32, int K,
                                                    const float* __restrict__ el32, int M, float eps2f, float near2,
+                                                   const float4* __restrict__ box,
                                                    float* __restrict__ u, NearPair* __restrict__ list, int slots,
                                                    int* __restrict__ wave_count, uint8_t* __restrict__ flag,
                                                    int* __restrict__ need)
@@ -72,23 +74,41 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
     float f0 = 0.f, f1 = 0.f, f2 = 0.f;
     bool overflow = false;
     int used = 0;
+    // the wavefront's sample box: groups of segments farther than their near radius take the
+    // loop without near tests (every pair in them is far; the result is the same)
+    const float wx0 = uniform_f32(wave_min(live ? Xf : INFINITY)), wx1 = uniform_f32(wave_max(live ? Xf : -INFINITY));
+    const float wy0 = uniform_f32(wave_min(live ? Yf : INFINITY)), wy1 = uniform_f32(wave_max(live ? Yf : -INFINITY));
     __shared__ float4 stage[kSweepStage];
     for (int k0 = 0; k0 < K; k0 += kStageSegs) {
         const int nk = K - k0 < kStageSegs ? K - k0 : kStageSegs;
         stage_records(stage, seg32 + (size_t)k0 * kSegStride, nk * (kSegStride / 4));
-        for (int kk = 0; kk < nk; ++kk) {
-            const float* s = reinterpret_cast<const float*>(stage + kk * (kSegStride / 4));
-            const SegGeom<float> g = load_geom(s);
-            float w[12];
+        for (int q0 = 0; q0 < nk; q0 += kBoxGroup) {
+            const int q1 = q0 + kBoxGroup < nk ? q0 + kBoxGroup : nk;
+            if (box_culled(box, (k0 + q0) / kBoxGroup, wx0, wy0, wx1, wy1)) {
+                for (int kk = q0; kk < q1; ++kk) {
+                    const float* s = reinterpret_cast<const float*>(stage + kk * (kSegStride / 4));
+                    const SegGeom<float> g = load_geom(s);
+                    const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
+                    f0 += m.da * s[kWdA] + m.db * s[kWdB] + m.sa * s[kWcA] + m.sb * s[kWcB];
+                    f1 += m.da * s[kWdA + 1] + m.db * s[kWdB + 1] + m.sa * s[kWcA + 1] + m.sb * s[kWcB + 1];
+                    f2 += m.da * s[kWdA + 2] + m.db * s[kWdB + 2] + m.sa * s[kWcA + 2] + m.sb * s[kWcB + 2];
+                }
+                continue;
+            }
+            for (int kk = q0; kk < q1; ++kk) {
+                const float* s = reinterpret_cast<const float*>(stage + kk * (kSegStride / 4));
+                const SegGeom<float> g = load_geom(s);
+                float w[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
-            const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
-            append_near(near, (int32_t)i, k0 + kk, slice, slots, used, overflow);
-            const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
-            const float on = near ? 0.0f : 1.0f;
-            f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
-            f1 += on * (m.da * w[1] + m.db * w[4] + m.sa * w[7] + m.sb * w[10]);
-            f2 += on * (m.da * w[2] + m.db * w[5] + m.sa * w[8] + m.sb * w[11]);
+                for (int c = 0; c < 12; ++c) w[c] = s[kWdA + c];
+                const bool near = live & near_segment(g.ax, g.ay, g.bx, g.by, g.L2, Xf, Yf, near2);
+                append_near(near, (int32_t)i, k0 + kk, slice, slots, used, overflow);
+                const Moments<float> m = seg_moments<float, DevF32, false>(g, Xf, Yf, eps2f);
+                const float on = near ? 0.0f : 1.0f;
+                f0 += on * (m.da * w[0] + m.db * w[3] + m.sa * w[6] + m.sb * w[9]);
+                f1 += on * (m.da * w[1] + m.db * w[4] + m.sa * w[7] + m.sb * w[10]);
+                f2 += on * (m.da * w[2] + m.db * w[5] + m.sa * w[8] + m.sb * w[11]);
+            }
         }
     }
     float b0 = 0.f, b1 = 0.f, b2 = 0.f;
@@ -110,28 +130,29 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
     flag[i] = overflow ? 1 : 0;
 }
 
-// Bounding boxes for the classification's culling: box g (g < H: handle g's S segments; g >= H:
-// group g - H of kElemGroup outer elements) = the end points' extent (xmin, ymin, xmax, ymax) and
-// the largest near radius sqrt(near2 L2) of its members.  Degenerate segments (L2 = 0) are never
-// near and are left out; a box with no member is empty (min > max) and culls everything.
-constexpr int kElemGroup = 32;
-__global__ void k_near_boxes(const float* __restrict__ seg32, int H, int S, const float* __restrict__ el32, int M,
+// Bounding boxes for culling near-pair tests per wavefront: box g (g < ceil(K / kBoxGroup): segments
+// [kBoxGroup g, kBoxGroup (g + 1)); after those, group g - nsg of kBoxGroup outer elements) = the end
+// points' extent (xmin, ymin, xmax, ymax) and the largest near radius sqrt(near2 L2) of its members.
+// Degenerate segments (L2 = 0) are never near and are left out; a box with no member is empty
+// (min > max) and culls everything.
+__global__ void k_near_boxes(const float* __restrict__ seg32, int K, const float* __restrict__ el32, int M,
                              float near2, float4* __restrict__ box)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ng = H + (M + kElemGroup - 1) / kElemGroup;
-    if (g >= ng) return;
+    const int nsg = (K + kBoxGroup - 1) / kBoxGroup;
+    if (g >= nsg + (M + kBoxGroup - 1) / kBoxGroup) return;
     float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY, r = 0.0f;
-    if (g < H) {
-        for (int j = 0; j < S; ++j) {
-            const float* sg = seg32 + (size_t)(g * S + j) * kSegStride;
+    if (g < nsg) {
+        const int k1 = (g + 1) * kBoxGroup < K ? (g + 1) * kBoxGroup : K;
+        for (int k = g * kBoxGroup; k < k1; ++k) {
+            const float* sg = seg32 + (size_t)k * kSegStride;
             if (sg[6] == 0.0f) continue;
             x0 = fminf(x0, fminf(sg[0], sg[2])); x1 = fmaxf(x1, fmaxf(sg[0], sg[2]));
             y0 = fminf(y0, fminf(sg[1], sg[3])); y1 = fmaxf(y1, fmaxf(sg[1], sg[3]));
             r = fmaxf(r, sqrtf(near2 * sg[6]));
         }
     } else {
-        const int j0 = (g - H) * kElemGroup, j1 = j0 + kElemGroup < M ? j0 + kElemGroup : M;
+        const int j0 = (g - nsg) * kBoxGroup, j1 = j0 + kBoxGroup < M ? j0 + kBoxGroup : M;
         for (int j = j0; j < j1; ++j) {
             const float* e = el32 + (size_t)j * kElemStride;
             const float bx = e[0] + e[2], by = e[1] + e[3];
@@ -144,36 +165,13 @@ __global__ void k_near_boxes(const float* __restrict__ seg32, int H, int S, cons
     box[2 * g + 1] = make_float4(r, 0.0f, 0.0f, 0.0f);
 }
 
-// True when no sample of the wavefront's box [wx0, wx1] x [wy0, wy1] can be near a member of box g:
-// the boxes' distance exceeds the members' largest near radius by a margin far above the float32
-// rounding of the exact test (a pair is near only if both of its end points lie within the radius).
-__device__ inline bool box_culled(const float4* __restrict__ box, int g, float wx0, float wy0, float wx1, float wy1)
-{
-    const float4 b = box[2 * g];
-    const float r = box[2 * g + 1].x * 1.001f + 1e-6f;
-    const float dx = fmaxf(0.0f, fmaxf(b.x - wx1, wx0 - b.z));
-    const float dy = fmaxf(0.0f, fmaxf(b.y - wy1, wy0 - b.w));
-    return !(b.x <= b.z) || dx * dx + dy * dy > r * r;      // empty box, or too far
-}
-
-__device__ inline float wave_min(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline float wave_max(float v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // Near-pair classification only (for the adjoint and the J tiles): the same wavefront slices and
 // predicate as the float32 forward sweep.  Each wavefront first bounds its samples and skips every
-// handle (and every group of kElemGroup elements) whose box is farther than its near radius; the
-// exact test runs for the others, in segment order.  With samples visited cell by cell a
-// wavefront's box is small and most handles are skipped.
+// group of kBoxGroup segments (and of outer elements) whose box is farther than its near radius;
+// the exact test runs for the others, in segment order.  With samples visited cell by cell a
+// wavefront's box is small and most groups are skipped.
 __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, int64_t N,
-                                                  const float* __restrict__ seg32, int H, int S,
+                                                  const float* __restrict__ seg32, int K,
                                                   const float* __restrict__ el32, int M, float near2,
                                                   const float4* __restrict__ box,
                                                   NearPair* __restrict__ list, int slots, int* __restrict__ wave_count,
@@ -184,23 +182,24 @@ __global__ void __launch_bounds__(256) k_classify(const double* __restrict__ x, 
     NearPair* slice = list + wave * slots;
     const bool live = i < N;
     const float Xf = live ? (float)x[2 * i] : 0.0f, Yf = live ? (float)x[2 * i + 1] : 0.0f;
-    const float wx0 = wave_min(live ? Xf : INFINITY), wx1 = wave_max(live ? Xf : -INFINITY);
-    const float wy0 = wave_min(live ? Yf : INFINITY), wy1 = wave_max(live ? Yf : -INFINITY);
+    const float wx0 = uniform_f32(wave_min(live ? Xf : INFINITY)), wx1 = uniform_f32(wave_max(live ? Xf : -INFINITY));
+    const float wy0 = uniform_f32(wave_min(live ? Yf : INFINITY)), wy1 = uniform_f32(wave_max(live ? Yf : -INFINITY));
     bool overflow = false;
     int used = 0;
-    const int K = H * S;
-    for (int h = 0; h < H; ++h) {
-        if (box_culled(box, h, wx0, wy0, wx1, wy1)) continue;
-        for (int k = h * S; k < (h + 1) * S; ++k) {
+    const int nsg = (K + kBoxGroup - 1) / kBoxGroup;
+    for (int g = 0; g < nsg; ++g) {
+        if (box_culled(box, g, wx0, wy0, wx1, wy1)) continue;
+        const int k1 = (g + 1) * kBoxGroup < K ? (g + 1) * kBoxGroup : K;
+        for (int k = g * kBoxGroup; k < k1; ++k) {
             const float* s = seg32 + (size_t)k * kSegStride;
             const bool near = live & near_segment(s[0], s[1], s[2], s[3], s[6], Xf, Yf, near2);
             append_near(near, (int32_t)i, k, slice, slots, used, overflow);
         }
     }
-    for (int g = 0; g * kElemGroup < M; ++g) {
-        if (box_culled(box, H + g, wx0, wy0, wx1, wy1)) continue;
-        const int j1 = (g + 1) * kElemGroup < M ? (g + 1) * kElemGroup : M;
-        for (int j = g * kElemGroup; j < j1; ++j) {
+    for (int g = 0; g * kBoxGroup < M; ++g) {
+        if (box_culled(box, nsg + g, wx0, wy0, wx1, wy1)) continue;
+        const int j1 = (g + 1) * kBoxGroup < M ? (g + 1) * kBoxGroup : M;
+        for (int j = g * kBoxGroup; j < j1; ++j) {
             const float* e = el32 + (size_t)j * kElemStride;
             const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
             append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
@@ -318,6 +317,19 @@ __global__ void __launch_bounds__(256) k_sweep_inline(const double* __restrict__
 
 }  // namespace
 
+int near_boxes(bem_ctx* ctx, int K, int M, const float4** box, hipStream_t s)
+{
+    int rc;
+    const int nbox = (K + kBoxGroup - 1) / kBoxGroup + (M + kBoxGroup - 1) / kBoxGroup;
+    if ((rc = ensure(ctx, ctx->boxw, (size_t)(nbox > 0 ? nbox : 1) * 2 * sizeof(float4), s))) return rc;
+    const double nf = near_radius(ctx->opts.near_factor);
+    if (nbox > 0)
+        hipLaunchKernelGGL(k_near_boxes, dim3(blocks_for(nbox, 256)), dim3(256), 0, s, (const float*)ctx->seg32.ptr, K,
+                           (const float*)ctx->elem32.ptr, M, (float)(nf * nf), (float4*)ctx->boxw.ptr);
+    *box = (const float4*)ctx->boxw.ptr;
+    return check_launch(ctx, "near boxes");
+}
+
 // Classify the near pairs of samples x[0..N) (segments, and outer elements when M > 0) into buf.
 int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, int M, NearList* out, hipStream_t s)
 {
@@ -325,16 +337,11 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     const double nf = near_radius(ctx->opts.near_factor);
     const int64_t nwaves = N > 0 ? (int64_t)blocks_for(N, 256) * 4 : 0;
     const int slots = near_slots_for(ctx->near_slots, nwaves);
-    // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N] | culling boxes
-    const int S = ctx->opts.segs_per_handle, H = K / S;
-    const int nbox = H + (M + kElemGroup - 1) / kElemGroup;
+    // list [nwaves][slots] | counts [nwaves] | overflow count (256 bytes) | flags [N]
     const size_t list_bytes = ((size_t)nwaves * slots * sizeof(NearPair) + 255) / 256 * 256;
     const size_t cnt_bytes = ((size_t)nwaves * sizeof(int) + 255) / 256 * 256;
-    const size_t flag_bytes = ((size_t)N + 255) / 256 * 256;
-    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + 256 + flag_bytes + (size_t)nbox * 2 * sizeof(float4) + 256, s)))
-        return rc;
+    if ((rc = ensure(ctx, buf, list_bytes + cnt_bytes + 256 + (size_t)N + 256, s))) return rc;
     char* base = (char*)buf.ptr;
-    float4* box = (float4*)(base + list_bytes + cnt_bytes + 256 + flag_bytes);
     out->list = (NearPair*)base;
     out->count = (int*)(base + list_bytes);
     out->need = (int*)(base + list_bytes + cnt_bytes);
@@ -344,11 +351,10 @@ int near_classify(bem_ctx* ctx, DevBuf& buf, const double* x, int64_t N, int K, 
     if ((rc = fill_i32(ctx, out->need, 1, 0, s))) return rc;
     if (N == 0) return BEM_OK;
     ProfScope ps_(ctx, PT_NEAR, s);
-    if (nbox > 0)
-        hipLaunchKernelGGL(k_near_boxes, dim3(blocks_for(nbox, 256)), dim3(256), 0, s, (const float*)ctx->seg32.ptr, H, S,
-                           (const float*)ctx->elem32.ptr, M, (float)(nf * nf), box);
-    hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, H, S,
-                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), (const float4*)box, out->list, slots,
+    const float4* box;
+    if ((rc = near_boxes(ctx, K, M, &box, s))) return rc;
+    hipLaunchKernelGGL(k_classify, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr, K,
+                       (const float*)ctx->elem32.ptr, M, (float)(nf * nf), box, out->list, slots,
                        out->count, out->flag, out->need);
     return check_launch(ctx, "classify");
 }
@@ -381,11 +387,13 @@ int launch_sweep_mixed(bem_ctx* ctx, const double* x, int64_t N, int K, const do
     ctx->sweep_need = need;
     if ((rc = fill_i32(ctx, need, 1, 0, s))) return rc;
     if (out) *out = NearList{list, wave_count, flag, need, nwaves, slots, true};
+    const float4* box;
+    if ((rc = near_boxes(ctx, K, ctx->M, &box, s))) return rc;
     {
         ProfScope ps_(ctx, PT_SWEEP_MIXED, s);
         hipLaunchKernelGGL(k_sweep_far, dim3(blocks_for(N, 256)), dim3(256), 0, s, x, N, (const float*)ctx->seg32.ptr,
-                           K, (const float*)ctx->elem32.ptr, ctx->M, (float)eps2, near2, u, list, slots, wave_count,
-                           flag, need);
+                           K, (const float*)ctx->elem32.ptr, ctx->M, (float)eps2, near2, box, u, list, slots,
+                           wave_count, flag, need);
     }
     {
         ProfScope ps_(ctx, PT_NEAR, s);
