@@ -162,22 +162,24 @@ def valu_fraction(kernel: str, pairs_per_s_in_step):
 
 
 def pmc_probe() -> int:
-    """Small run for counters: the mixed forward sweep on one batch (2,097,152 samples), J^T J on
-    two 32,768-sample tiles (the bench's tile) and the mixed adjoint on those 65,536 samples of the
-    LM workload, then a plain 256 MiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    """Small run for counters: one mixed split-BF16 LM step of the LM workload on batch 0 (its forward
+    sweeps on the cell-ordered samples, its 64 J tiles of 32,768 samples and their Gram launches,
+    exactly as in the timed step), the mixed adjoint on 65,536 samples, then a plain 256 MiB device
+    copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
     wl = W.make_config(5)
-    ctx = B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side)
-    n = 2 * GRAM_TILE
-    xs = wl.samples(0)
-    x = torch.from_numpy(xs[:n]).cuda()
-    r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
+    ctx = make_context(wl)
+    tht = torch.from_numpy(wl.theta_true).cuda()
+    xs = torch.from_numpy(wl.samples(0)).cuda()
+    T = make_target(ctx, wl, tht, xs, 0)
     th = torch.from_numpy(wl.theta0).cuda()
-    ctx.eval(th, torch.from_numpy(xs).cuda(), wl.cbar_true, "mixed")      # the forward on the whole batch
-    ctx.jtj(th, x, r, "bf16x3_mfma", "mixed")
-    ctx.vjp(th, x, r, "mixed")
+    st = B.new_lm_state(wl.lam0, 0)
+    ctx.lm_step(th, xs, T, st, "bf16x3_mfma", "mixed")
+    n = 2 * GRAM_TILE
+    r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
+    ctx.vjp(torch.from_numpy(wl.theta0).cuda(), xs[:n].contiguous(), r, "mixed")
     a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
