@@ -112,12 +112,24 @@ __global__ void __launch_bounds__(256) k_sweep_far(const double* __restrict__ x,
         }
     }
     float b0 = 0.f, b1 = 0.f, b2 = 0.f;
-    for (int j = 0; j < M; ++j) {
-        const float* e = el32 + (size_t)j * kElemStride;
-        const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
-        append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
-        const float beta = near ? 0.0f : element_beta<float, DevF32>(e[0], e[1], e[2], e[3], Xf, Yf);
-        b0 += beta * e[4]; b1 += beta * e[5]; b2 += beta * e[6];
+    const int nsg = (K + kBoxGroup - 1) / kBoxGroup;     // element groups' boxes follow the segments'
+    for (int j0 = 0; j0 < M; j0 += kBoxGroup) {
+        const int j1 = j0 + kBoxGroup < M ? j0 + kBoxGroup : M;
+        if (box_culled(box, nsg + j0 / kBoxGroup, wx0, wy0, wx1, wy1)) {
+            for (int j = j0; j < j1; ++j) {
+                const float* e = el32 + (size_t)j * kElemStride;
+                const float beta = element_beta<float, DevF32>(e[0], e[1], e[2], e[3], Xf, Yf);
+                b0 += beta * e[4]; b1 += beta * e[5]; b2 += beta * e[6];
+            }
+            continue;
+        }
+        for (int j = j0; j < j1; ++j) {
+            const float* e = el32 + (size_t)j * kElemStride;
+            const bool near = live & near_element(e[0], e[1], e[2], e[3], Xf, Yf, near2);
+            append_near(near, (int32_t)i, K + j, slice, slots, used, overflow);
+            const float beta = near ? 0.0f : element_beta<float, DevF32>(e[0], e[1], e[2], e[3], Xf, Yf);
+            b0 += beta * e[4]; b1 += beta * e[5]; b2 += beta * e[6];
+        }
     }
     if ((threadIdx.x & 63) == 0) {
         wave_count[wave] = used < slots ? used : slots;
