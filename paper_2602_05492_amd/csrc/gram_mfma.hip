@@ -217,22 +217,34 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
     __builtin_amdgcn_sched_group_barrier(0x100, nreads, 0);                                   \
     __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);                                        \
     __builtin_amdgcn_sched_barrier(0);
-#define G2_MULTIPLY(SM)                                                                       \
-    {                                                                                         \
-        bf16x8 a0h[2], a0l[2], a1h[2], a1l[2], b0h, b0l, b1h, b1l;                            \
-        G2_A(SM, 0, a0h, a0l)                                                                 \
-        G2_B(SM, 0, 0, b0h, b0l)                                                              \
-        __builtin_amdgcn_sched_barrier(0);                                                    \
-        G2_B(SM, 0, 1, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 0)  G2_ORDER(2)                 \
-        G2_B(SM, 0, 2, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 1)  G2_ORDER(2)                 \
-        G2_B(SM, 0, 3, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 2)  G2_ORDER(2)                 \
-        G2_A(SM, 1, a1h, a1l)                                                                 \
-        G2_B(SM, 1, 0, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 3)  G2_ORDER(6)                 \
-        G2_B(SM, 1, 1, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 0)  G2_ORDER(2)                 \
-        G2_B(SM, 1, 2, b0h, b0l)  G2_STEP(a1h, a1l, b1h, b1l, 1)  G2_ORDER(2)                 \
-        G2_B(SM, 1, 3, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 2)  G2_ORDER(2)                 \
-                                  G2_STEP(a1h, a1l, b1h, b1l, 3)                              \
-    }
+// operands of a stage's first step (A of the first half, B of column tile 0)
+#define G2_HEAD(SM)                                                                           \
+    G2_A(SM, 0, a0h, a0l)                                                                     \
+    G2_B(SM, 0, 0, b0h, b0l)
+// steps 0..6 of the stage in SM (its first operands already requested); the operands of step 7
+// are in registers at the end, and no LDS read of SM is left in flight once lgkmcnt is 0
+#define G2_BODY(SM)                                                                           \
+    G2_B(SM, 0, 1, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 0)  G2_ORDER(2)                     \
+    G2_B(SM, 0, 2, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 1)  G2_ORDER(2)                     \
+    G2_B(SM, 0, 3, b1h, b1l)  G2_STEP(a0h, a0l, b0h, b0l, 2)  G2_ORDER(2)                     \
+    G2_A(SM, 1, a1h, a1l)                                                                     \
+    G2_B(SM, 1, 0, b0h, b0l)  G2_STEP(a0h, a0l, b1h, b1l, 3)  G2_ORDER(6)                     \
+    G2_B(SM, 1, 1, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 0)  G2_ORDER(2)                     \
+    G2_B(SM, 1, 2, b0h, b0l)  G2_STEP(a1h, a1l, b1h, b1l, 1)  G2_ORDER(2)                     \
+    G2_B(SM, 1, 3, b1h, b1l)  G2_STEP(a1h, a1l, b0h, b0l, 2)  G2_ORDER(2)
+// end of the stage in CUR at sample k0, the other buffer NXT holding stage k0 + 32 (if any):
+// every wavefront has read CUR and written its share of NXT -> barrier; CUR is refilled with stage
+// k0 + 64; the first operands of NXT are requested (unused past the last stage; the reads stay
+// inside the buffer) and the step-7 MFMAs of CUR, whose operands are in registers, cover their
+// latency and the barrier's LDS burst
+#define G2_TURN(CUR, NXT, k0)                                                                 \
+    __builtin_amdgcn_s_waitcnt(0x3f70);               /* vmcnt(0): this wavefront's loads of NXT */ \
+    __syncthreads();                                                                          \
+    if ((k0) + 2 * G2_BK < n) G2_LOAD_STAGE(CUR, (k0) + 2 * G2_BK)                            \
+    G2_HEAD(NXT)                                                                              \
+    __builtin_amdgcn_sched_barrier(0);                                                        \
+    G2_STEP(a1h, a1l, b1h, b1l, 3)                                                            \
+    __builtin_amdgcn_sched_barrier(0);
     floatx16 acc[2][4];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -240,25 +252,29 @@ __global__ void __launch_bounds__(512) k_gram_bf16x3_lds(const uint16_t* __restr
         for (int nj = 0; nj < 4; ++nj)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][nj][r] = 0.0f;
+    bf16x8 a0h[2], a0l[2], a1h[2], a1l[2], b0h, b0l, b1h, b1l;
     G2_LOAD_STAGE(sm0, kb)
-    for (int k0 = kb; k0 < n; k0 += 2 * G2_BK) {
-        // stage k0 is in sm0, stage k0 + 32 goes to sm1 (read two stages ago, free after the barrier)
-        __builtin_amdgcn_s_waitcnt(0x3f70);               // vmcnt(0): this wavefront's loads of stage k0
-        __syncthreads();
-        if (k0 + G2_BK < n) G2_LOAD_STAGE(sm1, k0 + G2_BK)
-        G2_MULTIPLY(sm0)
+    __builtin_amdgcn_s_waitcnt(0x3f70);
+    __syncthreads();
+    if (kb + G2_BK < n) G2_LOAD_STAGE(sm1, kb + G2_BK)
+    G2_HEAD(sm0)
+    for (int k0 = kb;; k0 += 2 * G2_BK) {
+        // stage k0 in sm0, stage k0 + 32 (if any) arriving in sm1
+        G2_BODY(sm0)
+        G2_TURN(sm0, sm1, k0)
         if (k0 + G2_BK >= n) break;
-        __builtin_amdgcn_s_waitcnt(0x3f70);
-        __syncthreads();
-        if (k0 + 2 * G2_BK < n) G2_LOAD_STAGE(sm0, k0 + 2 * G2_BK)
-        G2_MULTIPLY(sm1)
+        G2_BODY(sm1)
+        G2_TURN(sm1, sm0, k0 + G2_BK)
+        if (k0 + 2 * G2_BK >= n) break;
     }
 #undef G2_LOAD_STAGE
 #undef G2_A
 #undef G2_B
 #undef G2_STEP
 #undef G2_ORDER
-#undef G2_MULTIPLY
+#undef G2_HEAD
+#undef G2_BODY
+#undef G2_TURN
     // epilogue: G += acc (G = acc for the first sample tile).  A tile inside the matrix reads its 16
     // values of an MFMA tile in one batch (one wait instead of 16); tiles at the matrix edge go
     // element by element.
