@@ -92,9 +92,10 @@ WORKLOAD_TEXT = {
 FEATURE_ROWS = {"cubic": (8, 4), "straight": (4, 2)}
 
 
-def make_context(wl):
+def make_context(wl, tile_rows: int = 0):
     from paper_2602_05492_amd import bem as B
-    return B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side, handle_model=wl.spec.model)
+    return B.Context(segs_per_handle=wl.S, eps=wl.eps, elems_per_side=wl.elems_per_side, handle_model=wl.spec.model,
+                     tile_rows=tile_rows)
 
 
 def make_target(ctx, wl, tht, x, step):
@@ -494,6 +495,8 @@ def main() -> int:
     ap.add_argument("--fp64-ref", type=int, default=1,
                     help="also time the plain FP64 GPU step (one warm-up, median of 3) for the speedup")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="samples per J tile of the normal equations (0: the library's choice)")
     ap.add_argument("--compat", type=int, default=0,
                     help="enforce the compatibility condition in every LM step (constrained step + re-projection)")
     ap.add_argument("--workload", default="lm", choices=sorted(WORKLOADS) + ["near", "adjoint"],
@@ -534,7 +537,7 @@ def main() -> int:
     from paper_2602_05492_amd import workload as W
 
     wl = W.make_config(WORKLOADS[args.workload])
-    ctx = make_context(wl)
+    ctx = make_context(wl, args.tile_rows)
     H, S, N, M = wl.H, wl.S, wl.N, ctx.M
     K = H * S
     nb = args.warmup + args.steps
@@ -588,8 +591,8 @@ def main() -> int:
     achieved = work[dom] / (tot_ms * 1e-3) / 1e12
     bound, peak = peak_of[dom]
     # the committed byte counters were taken on the LM workload's Gram
-    traffic = (gram_traffic(GRAM_TILE) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma" and args.workload == "lm")
-               else None)
+    traffic = (gram_traffic(GRAM_TILE) if (dom == "gram_mfma" and args.gram == "bf16x3_mfma" and args.workload == "lm"
+                                           and args.tile_rows in (0, GRAM_TILE)) else None)
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (peak / 1e12), "traffic": traffic, "launches": launches,
                 "avg_launch_ms": tot_ms / launches}
