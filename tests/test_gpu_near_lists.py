@@ -135,3 +135,53 @@ def test_eval_mixed_small_near_factor():
     err = float(np.abs(got - ref).max())
     log(f"near_factor 0.5: mixed eval max abs err {err:.3e}")
     assert err < 1e-4
+
+
+def _boundary_band(n, seed, per_side=256):
+    """n samples between 1e-7 and 1e-4 inside the unit square's edges, each within 1e-6 to 1e-2
+    element lengths of a junction of two outer elements, ordered along the perimeter so that each
+    64-sample wavefront covers a short stretch of one or two edges: its bounding box is small, and
+    the wavefront skips the near tests of every other group of outer elements.  There a float32
+    value of a single element's double layer is off by up to 3e-2 (the angle it subtends turns
+    fast), so a near pair missed by the culling shows in the colour's beta rows of J^T J."""
+    rng = np.random.default_rng(seed)
+    off = np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0) * 10.0 ** rng.uniform(-6.0, -2.0, n)
+    s = np.sort(np.mod((rng.integers(0, 4 * per_side, n) + off) / per_side, 4.0))
+    d = 10.0 ** rng.uniform(-7.0, -4.0, n)
+    side, t = np.floor(s).astype(int), s - np.floor(s)
+    x = np.empty((n, 2))
+    for k, (px, py) in enumerate([(t, d), (1.0 - d, t), (1.0 - t, 1.0 - d), (d, 1.0 - t)]):
+        m = side == k
+        x[m, 0], x[m, 1] = px[m], py[m]
+    return x
+
+
+def test_eval_mixed_boundary_band():
+    """Samples in the boundary band, wavefronts compact along it: the forward sweep's culled
+    element groups; colour within the mixed-precision bar of the oracle."""
+    wl = W.make_config(2)
+    x = _boundary_band(4096, 71)
+    ctx = ctx_for(wl.S)
+    got = host(ctx.eval(dev(wl.theta_true), dev(x), wl.cbar_true, "mixed"))
+    ref = O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps)
+    err = float(np.abs(got - ref).max())
+    log(f"boundary band: mixed eval max abs err {err:.3e}")
+    assert err < 1e-4
+
+
+def test_vjp_and_jtj_mixed_boundary_band():
+    """The same band through the classification of the adjoint and of the J tiles (element groups
+    culled per wavefront there too): every pair of a sample with an outer element within the near
+    radius must reach the float64 list for the beta rows of J^T J to meet their bar."""
+    wl = W.make_config(2)
+    x = _boundary_band(2048, 72)
+    ctx = ctx_for(wl.S, tile_rows=1024)
+    g = W.random_vector(73, (len(x), 3))
+    got = host(ctx.vjp(dev(wl.theta_true), dev(x), dev(g, torch.float32), "mixed"))
+    ref = O.vjp(wl.theta_true, x, g, wl.S, wl.eps)
+    ev = _rel(got, ref)
+    Ho, go = O.normal_equations(wl.theta_true, x, g, wl.S, wl.eps)
+    JtJ, Jtr = ctx.jtj(dev(wl.theta_true), dev(x), dev(g, torch.float32), "bf16x3_mfma", "mixed")
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"boundary band: mixed vjp rel err {ev:.3e}, JtJ {eh:.3e}, Jtr {eg:.3e}")
+    assert ev < 1e-3 and eh < 1e-4 and eg < 1e-3
