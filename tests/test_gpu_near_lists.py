@@ -185,3 +185,35 @@ def test_vjp_and_jtj_mixed_boundary_band():
     eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
     log(f"boundary band: mixed vjp rel err {ev:.3e}, JtJ {eh:.3e}, Jtr {eg:.3e}")
     assert ev < 1e-3 and eh < 1e-4 and eg < 1e-3
+
+
+def _morton_sorted(x, bits=10):
+    """x reordered along a Z curve over a 2^bits grid of the unit square (wavefronts of nearby
+    samples)."""
+    q = np.clip((x * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    key = np.zeros(len(x), dtype=np.int64)
+    for b in range(bits):
+        key |= ((q[:, 0] >> b) & 1) << (2 * b) | ((q[:, 1] >> b) & 1) << (2 * b + 1)
+    return x[np.argsort(key, kind="stable")]
+
+
+def test_near_singular_compact_wavefronts():
+    """Samples within 1e-3 of the handle segments, ordered along a Z curve so that each wavefront's
+    box is small and most groups of 32 segments are skipped per wavefront in the forward sweep, the
+    classification and the J-tile feature kernel (16 segments per handle).  Every pair nearer than
+    the near radius must reach the float64 evaluation, where the float32 forms fail; colour,
+    gradient, J^T J and J^T r within the mixed-precision bars of the oracle."""
+    wl = W.make_config(2)
+    rng = np.random.default_rng(74)
+    x = _morton_sorted(W.near_samples(rng, wl.theta_true[:, :8].reshape(-1, 4, 2), wl.S, 4096))
+    ctx = ctx_for(wl.S, tile_rows=1024)
+    th = dev(wl.theta_true)
+    u = host(ctx.eval(th, dev(x), wl.cbar_true, "mixed"))
+    eu = float(np.abs(u - O.evaluate(wl.theta_true, x, wl.cbar_true, wl.S, wl.eps)).max())
+    g = W.random_vector(75, (len(x), 3))
+    ev = _rel(host(ctx.vjp(th, dev(x), dev(g, torch.float32), "mixed")), O.vjp(wl.theta_true, x, g, wl.S, wl.eps))
+    Ho, go = O.normal_equations(wl.theta_true, x, g, wl.S, wl.eps)
+    JtJ, Jtr = ctx.jtj(th, dev(x), dev(g, torch.float32), "bf16x3_mfma", "mixed")
+    eh, eg = _rel(host(JtJ), Ho), _rel(host(Jtr), go)
+    log(f"near-singular, compact wavefronts: colour {eu:.3e}, vjp {ev:.3e}, JtJ {eh:.3e}, Jtr {eg:.3e}")
+    assert eu < 1e-4 and ev < 1e-3 and eh < 1e-4 and eg < 1e-3
