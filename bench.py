@@ -165,8 +165,9 @@ def valu_fraction(kernel: str, pairs_per_s_in_step):
 def pmc_probe() -> int:
     """Small run for counters: one mixed split-BF16 LM step of the LM workload on batch 0 (its forward
     sweeps on the cell-ordered samples, its 64 J tiles of 32,768 samples and their Gram launches,
-    exactly as in the timed step), the mixed adjoint on 65,536 samples, then a plain 256 MiB device
-    copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    exactly as in the timed step), one mixed adjoint of the adjoint workload (4,194,304 samples, as
+    `--workload adjoint` times it; the cotangent's values do not change the work), then a plain
+    256 MiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2602_05492_amd import bem as B
     from paper_2602_05492_amd import workload as W
@@ -178,9 +179,10 @@ def pmc_probe() -> int:
     th = torch.from_numpy(wl.theta0).cuda()
     st = B.new_lm_state(wl.lam0, 0)
     ctx.lm_step(th, xs, T, st, "bf16x3_mfma", "mixed")
-    n = 2 * GRAM_TILE
-    r = (wl.spec.sigma * torch.from_numpy(wl.noise(0)[:n])).float().cuda()
-    ctx.vjp(torch.from_numpy(wl.theta0).cuda(), xs[:n].contiguous(), r, "mixed")
+    wa = W.make_config(4)
+    xa = torch.from_numpy(wa.samples(0)).cuda()
+    ra = (1e-6 * torch.from_numpy(wa.noise(0))).float().cuda()
+    make_context(wa).vjp(torch.from_numpy(wa.theta0).cuda(), xa, ra, "mixed")
     a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
