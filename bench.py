@@ -191,6 +191,83 @@ def pmc_probe() -> int:
     return 0
 
 
+def power_probe(seconds: float = 6.0) -> int:
+    """Board power and shader clock (read-only sysfs: hwmon power1_input, pp_dpm_sclk), sampled every
+    20 ms while the LM workload's mixed forward sweep runs back to back, then while its normal
+    equations (J tiles and split-BF16 Gram on two streams, bem_jtj) run back to back; one JSON line
+    with the median, 10th and 90th percentiles per phase."""
+    import glob
+    import re
+    import threading
+    import torch
+    from paper_2602_05492_amd import bem as B
+    from paper_2602_05492_amd import workload as W
+    dev = sorted(glob.glob("/sys/class/drm/card*/device"))
+    pw = [p for d in dev for p in glob.glob(d + "/hwmon/hwmon*/power1_input")]
+    sc = [d + "/pp_dpm_sclk" for d in dev if os.path.exists(d + "/pp_dpm_sclk")]
+
+    def power_w():
+        try:
+            with open(pw[0]) as f:
+                return int(f.read()) / 1e6
+        except (OSError, ValueError, IndexError):
+            return None
+
+    def sclk_mhz():
+        try:
+            with open(sc[0]) as f:
+                m = re.search(r"(\d+)Mhz \*", f.read())
+            return int(m.group(1)) if m else None
+        except (OSError, IndexError):
+            return None
+
+    wl = W.make_config(5)
+    ctx = make_context(wl)
+    th = torch.from_numpy(wl.theta0).cuda()
+    x = torch.from_numpy(wl.samples(0)).cuda()
+    r = (wl.spec.sigma * torch.from_numpy(wl.noise(0))).float().cuda()
+    phases = {"forward_sweep": lambda: ctx.eval(th, x, wl.cbar_true, "mixed"),
+              "normal_equations": lambda: ctx.jtj(th, x, r, "bf16x3_mfma", "mixed")}
+    for f in phases.values():
+        f()
+    torch.cuda.synchronize()
+    label, stop, samples = ["idle"], [False], []
+
+    def sampler():
+        while not stop[0]:
+            samples.append((label[0], power_w(), sclk_mhz()))
+            time.sleep(0.02)
+
+    t = threading.Thread(target=sampler, daemon=True)
+    t.start()
+    calls = {}
+    for name, f in phases.items():
+        time.sleep(0.5)
+        label[0] = name
+        t0, n = time.perf_counter(), 0
+        while time.perf_counter() - t0 < seconds:
+            f()
+            n += 1
+            if n % 4 == 0:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        calls[name] = {"calls": n, "ms_per_call": (time.perf_counter() - t0) * 1e3 / n}
+        label[0] = "idle"
+    stop[0] = True
+    t.join()
+
+    def stats(v):
+        v = sorted(x for x in v if x is not None)
+        return {"n": len(v), "median": v[len(v) // 2], "p10": v[len(v) // 10], "p90": v[9 * len(v) // 10]} if v else None
+
+    out = {"what": "board power (W) and shader clock (MHz) per phase, LM workload", "sources": pw[:1] + sc[:1]}
+    for name in phases:
+        out[name] = {"power_w": stats([p for l, p, c in samples if l == name]),
+                     "sclk_mhz": stats([c for l, p, c in samples if l == name]), **calls[name]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def lm_curve(steps: int, gram: str, prec: str, workload: str, compat: int, ref: bool = False) -> int:
     """LM iterations of a workload with fresh samples per step; one JSON line per step.  With ref,
     each step's direction is also compared with the plain float64 step (float64 sweeps and Gram)
@@ -507,6 +584,8 @@ def main() -> int:
                          "262,144 samples (LM steps/s; --prec fp64 --gram fp64 for the plain FP64 path); near: mixed forward with near-singular samples, "
                          "1,048,576 samples (pairs/s); adjoint: bem_vjp at 4,194,304 samples (pairs/s)")
     ap.add_argument("--pmc-probe", action="store_true", help="only the small run profiled for byte counters")
+    ap.add_argument("--power-probe", action="store_true",
+                    help="only sample board power and shader clock during the forward sweep and the normal equations")
     ap.add_argument("--lm-curve-ref", action="store_true",
                     help="with --lm-curve: also take the float64 step from the same state each step and report the "
                          "step direction's relative error")
@@ -516,6 +595,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.pmc_probe:
         return pmc_probe()
+    if args.power_probe:
+        return power_probe()
     if args.lm_curve:
         return lm_curve(args.lm_curve, args.gram, args.prec, args.workload, args.compat, args.lm_curve_ref)
     world = int(os.environ.get("WORLD_SIZE", "1"))
