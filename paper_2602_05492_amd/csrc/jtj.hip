@@ -598,22 +598,94 @@ __global__ void __launch_bounds__(256) k_beta_rows(const double* __restrict__ x,
 // at one chunk fall in different banks; 16 KiB, so that a block fits beside a Gram block.
 // Samples past npts in a written block are zeros.
 constexpr int kBetaRunBlocked = 16;
+constexpr int kBetaJtrVals = 3 * kBetaRunBlocked;   // 16 beta rows x 3 residual channels
+
+// J^T r of a block's beta rows: value 3 jj + c = sum over the block's 256 samples of
+// beta[jj] r_c, in float32.  Values 0..31 by recursive halving over the wavefront (lane l ends
+// with value (l >> 1) & 31 summed over its lane pair, the offset-1 step completes it), values
+// 32..47 likewise with four halving steps (lane l: value 32 + ((l >> 2) & 15)) and two
+// butterflies; the 4 wavefronts are added through LDS and values 0 .. nv-1 written to out.
+__device__ inline void beta_jtr_block(const float (&bv)[kBetaRunBlocked], float r0, float r1, float r2,
+                                      float (*red)[kBetaJtrVals], float* __restrict__ out, int nv)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float r[3] = {r0, r1, r2};
+    float v[32], e[16];
+#pragma unroll
+    for (int i = 0; i < kBetaJtrVals; ++i) {
+        const float p = bv[i / 3] * r[i % 3];
+        if (i < 32) v[i] = p;
+        else e[i - 32] = p;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int half = 16 >> k, o = 32 >> k;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < half) {
+                const float keep = up ? v[i + half] : v[i];
+                const float send = up ? v[i] : v[i + half];
+                v[i] = keep + __shfl_xor(send, o, 64);
+            }
+        }
+    }
+    v[0] += __shfl_xor(v[0], 1, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int half = 8 >> k, o = 32 >> k;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i < half) {
+                const float keep = up ? e[i + half] : e[i];
+                const float send = up ? e[i] : e[i + half];
+                e[i] = keep + __shfl_xor(send, o, 64);
+            }
+        }
+    }
+    e[0] += __shfl_xor(e[0], 2, 64);
+    e[0] += __shfl_xor(e[0], 1, 64);
+    if ((lane & 1) == 0) red[wave][(lane >> 1) & 31] = v[0];
+    if ((lane & 3) == 0) red[wave][32 + ((lane >> 2) & 15)] = e[0];
+    __syncthreads();
+    if (threadIdx.x < nv)
+        out[threadIdx.x] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// R[row0 + j][c] += sum over the tile's sample blocks b of bpart[b][j][c] (float64, fixed order):
+// a thread per (j, c).
+__global__ void __launch_bounds__(256) k_jtr_beta(const float* __restrict__ bpart, int nblocks, int M, int64_t row0,
+                                                  double* __restrict__ R)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * M) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) acc += (double)bpart[(size_t)b * 3 * M + i];
+    R[row0 * 3 + i] += acc;
+}
 template <bool Mixed>
 __global__ void __launch_bounds__(256) k_beta_rows_blocked(const double* __restrict__ x, int64_t npts,
                                                            const double* __restrict__ el64,
                                                            const float* __restrict__ el32, int M, float near2,
                                                            uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
-                                                           int64_t ld, int64_t row0)
+                                                           int64_t ld, int64_t row0, const float* __restrict__ rr,
+                                                           float* __restrict__ bpart)
 {
     constexpr int R = kBetaRunBlocked;
     __shared__ __attribute__((aligned(16))) uint16_t sh[2][R][256];
+    __shared__ float jtr_red[4][kBetaJtrVals];
     const int64_t t0 = (int64_t)blockIdx.x * 256;
     const int64_t t = t0 + threadIdx.x;
     const int j0 = blockIdx.y * R, nj = M - j0 < R ? M - j0 : R;
     const bool live = t < npts;
     const double X = live ? x[2 * t] : 0.0, Y = live ? x[2 * t + 1] : 0.0;
     const float Xf = (float)X, Yf = (float)Y;
-    for (int jj = 0; jj < nj; ++jj) {
+    float bv[R];                                      // this sample's beta values (the J^T r products)
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+        bv[jj] = 0.0f;
+        if (jj >= nj) continue;
         const int j = j0 + jj;
         const double* e = el64 + (size_t)j * kElemStride;
         double b = 0.0;
@@ -629,6 +701,7 @@ __global__ void __launch_bounds__(256) k_beta_rows_blocked(const double* __restr
             }
         }
         const float v = (float)b;
+        bv[jj] = v;
         const uint16_t h = bf16_bits(v);
         const int col = threadIdx.x ^ ((jj & 7) << 3);
         sh[0][jj][col] = h;
@@ -649,6 +722,11 @@ __global__ void __launch_bounds__(256) k_beta_rows_blocked(const double* __restr
         uint16_t* dst = (which ? Xl : Xh) + (size_t)((t0 >> 5) + sb) * (size_t)(ld << 5) +
                         (size_t)((row0 + j0 + jj) << 5) + c * 8;
         *reinterpret_cast<uint4*>(dst) = v;
+    }
+    // with residuals (mixed J^T r): the block's sums of beta r over its samples, rows j0 .. j0+nj-1
+    if (rr) {
+        const float r0 = live ? rr[3 * t] : 0.0f, r1 = live ? rr[3 * t + 1] : 0.0f, r2 = live ? rr[3 * t + 2] : 0.0f;
+        beta_jtr_block(bv, r0, r1, r2, jtr_red, bpart + ((size_t)blockIdx.x * M + j0) * 3, 3 * nj);
     }
 }
 
@@ -893,7 +971,7 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
                            uint16_t* Xlo, int64_t ld, hipStream_t s, const NearList* nl = nullptr, int64_t t0 = 0,
                            const double* xg = nullptr, float* corr = nullptr, const float* vtab = nullptr,
                            int2* runs = nullptr, const float* rr = nullptr, float* rpart = nullptr, double* R = nullptr,
-                           const float4* box = nullptr)
+                           const float4* box = nullptr, float* bpart = nullptr)
 {
     if (npts == 0) return BEM_OK;
     const int S = ctx->opts.segs_per_handle;
@@ -943,12 +1021,19 @@ static int launch_features(bem_ctx* ctx, const double* x, int64_t npts, int H, b
     if (with_beta && std::is_same<OutT, uint16_t>::value) {
         const dim3 gb(blocks_for(npts, 256), blocks_for(ctx->M, kBetaRunBlocked));
         ProfScope ps_(ctx, PT_BETA_ROWS, s);
+        // with residuals and a partials buffer (mixed J^T r) the beta rows' J^T r is summed here as well
+        const float* brr = mixed && rr && bpart && R ? rr : nullptr;
         if (mixed)
             hipLaunchKernelGGL((k_beta_rows_blocked<true>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0);
+                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0, brr,
+                               bpart);
         else
             hipLaunchKernelGGL((k_beta_rows_blocked<false>), gb, dim3(256), 0, s, x, npts, (const double*)ctx->elem64.ptr,
-                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0);
+                               (const float*)ctx->elem32.ptr, ctx->M, near2, (uint16_t*)Xt, Xlo, ld, beta_row0,
+                               (const float*)nullptr, (float*)nullptr);
+        if (brr)
+            hipLaunchKernelGGL(k_jtr_beta, dim3(blocks_for(3 * (int64_t)ctx->M, 256)), dim3(256), 0, s, (const float*)bpart,
+                               (int)gb.x, ctx->M, beta_row0, R);
     } else if (with_beta) {
         const dim3 gb(blocks_for(npts, 256), blocks_for(ctx->M, kBetaRun));
         if (mixed)
@@ -1184,11 +1269,17 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
     // (float32 per 256-sample block, float64 across blocks); only the beta rows are read back
     const bool fused_r = want_r && mixed && !f64;
     const size_t rpart_bytes = fused_r ? (size_t)blocks_for(T, 256) * H * kJtrVals * sizeof(float) : 0;
-    if ((rc = ensure(ctx, ctx->tmp5, vtab_bytes + corr_bytes + runs_bytes + rpart_bytes + 256, s))) return rc;
+    // the split-BF16 tile's beta rows sum their J^T r in the beta-row kernel too (no read-back pass)
+    const bool fused_beta = fused_r && gram == BEM_GRAM_BF16X3_MFMA;
+    const size_t bpart_bytes = fused_beta ? ((size_t)blocks_for(T, 256) * M * 3 * sizeof(float) + 255) / 256 * 256 : 0;
+    if ((rc = ensure(ctx, ctx->tmp5, vtab_bytes + corr_bytes + runs_bytes + rpart_bytes + bpart_bytes + 256, s)))
+        return rc;
     float* vtab = (float*)ctx->tmp5.ptr;
     float* corr = mixed ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes) : nullptr;
     int2* runs = mixed ? (int2*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes) : nullptr;
     float* rpart = fused_r ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes + runs_bytes) : nullptr;
+    float* bpart = fused_beta ? (float*)((char*)ctx->tmp5.ptr + vtab_bytes + corr_bytes + runs_bytes + rpart_bytes)
+                              : nullptr;
     const float* rr = fused_r ? (const float*)resid : nullptr;
     const int xr_row0 = fused_r ? (int)L.handle_rows() : 0;
     hipLaunchKernelGGL(k_vertex_table, dim3(blocks_for(S + 1, 64)), dim3(64), 0, s, S, ctx->model, vtab);
@@ -1238,7 +1329,7 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
             uint16_t* Xl = Xh + (size_t)W * T;
             // blocked layout: ld is the row count
             if ((rc = launch_features<uint16_t>(ctx, xt, n, H, mixed, true, Xh, Xl, W, s, &nl, t0, x, corr, vtab, runs,
-                                                rr ? rr + 3 * t0 : nullptr, rpart, R, box)))
+                                                rr ? rr + 3 * t0 : nullptr, rpart, R, box, bpart)))
                 return rc;
             if (n & 31)
                 hipLaunchKernelGGL(k_zero_tail, dim3(blocks_for(W * (32 - (n & 31)), 256)), dim3(256), 0, s, Xh, Xl, W, n);
@@ -1246,7 +1337,8 @@ int run_jtj(bem_ctx* ctx, const double* theta, int H, const double* x, int64_t N
                 return set_error(ctx, BEM_EHIP, "stream wait");
             if ((rc = launch_gram_mfma(ctx, gram, Xh, Xl, T, (int)W, n, dtiles, ntiles, kchunk, G, W * W, it > 0, sg)))
                 return rc;
-            if (want_r && (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg, xr_row0)))
+            if (want_r && !fused_beta &&
+                (rc = launch_xr(ctx, gram, Xh, Xl, T, (int)W, n, r64 + 3 * t0, R, Rp, sg, xr_row0)))
                 return rc;
         }
         if (overlap && hipEventRecord(evG[buf], sg) != hipSuccess) return set_error(ctx, BEM_EHIP, "stream event");
